@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled D3Q27 RR-LBM + IBM time step on one MI355X.
+
+Workload: the falling-frame scale case -- a 256 x 256 x 768 box (50.3 M
+cells), tau from Re = 100, periodic x/y, free-slip top and bottom, sponge of
+61 rows, one tilted oblate ellipsoid (semi-axes 32/32/16) carried by 12,252
+surface markers, density ratio 2.7.  A step is the whole Table 1 sequence
+(body advance, fused stream + collide, IBM coupling with 4 multi-direct
+forcing cycles and force/torque, window test).  Populations start at rest
+and live in HBM before timing starts.
+
+Output: one JSON line with MLUPS (cells x steps / s / 1e6) and the HBM
+roofline of the dominant kernel (the fused stream + collide): algorithmic
+bytes per launch (27 reads + 27 writes per cell) over its average launch
+time, measured with events on the library's stream during the timed steps.
+FP16 and BF16 storage are reported beside FP32 with their drag difference.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM peak, D3Q27 RR+IBM; FP16-store vs FP32 at equal drag error"
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_ellipsoid256x256x768.txt")
+KERNEL_SOURCES = ["paper_2408_15115_amd/csrc/kernels.hip", "paper_2408_15115_amd/csrc/lattice.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(storage):
+    """HBM bytes per launch of the lattice kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != kernel_source_hash():
+        return None
+    v = kv.get(f"traffic_bytes_{storage}")
+    return float(v) if v else None
+
+
+def timed_steps(S, torch, steps, warmup):
+    """Eager step sequence; events on the library stream bracket every
+    lattice-kernel launch and the whole timed region."""
+    st = S.stream
+    for _ in range(warmup):
+        S.run(1)
+    torch.cuda.synchronize()
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(st)
+    for k in range(steps):
+        S.body_advance()
+        pairs[k][0].record(st)
+        S.lbm_step()
+        pairs[k][1].record(st)
+        S.ibm_couple()
+        S.window_shift()
+    t1.record(st)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    k1 = [a.elapsed_time(b) for a, b in pairs]
+    return total_ms, sum(k1) / len(k1)
+
+
+def graph_steps(S, torch, steps):
+    S.graph_capture(2)
+    S.graph_launch()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(S.stream)
+    for _ in range(steps // 2):
+        S.graph_launch()
+    t1.record(S.stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / (2 * (steps // 2))
+
+
+def copy_bandwidth(T, torch, nbytes=4 << 30, reps=10):
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    T.stream_copy(b, a, nbytes)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        T.stream_copy(b, a, nbytes)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(case, body, steps):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: the
+    same body, relaxation time and walls in a 128^3 window."""
+    from oracle import oracle as O
+    c = dict(case)
+    c.update(nx=128, ny=128, nz=128, sponge=10, h_ini=0.0, h_end=0.0)
+    b = dict(body)
+    b["r0"] = [63.5, 63.5, 63.5]
+    sim = O.OracleSim(c, b)
+    sim.step(1)
+    t = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t
+    cells = 128 ** 3
+    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"128^3 window of the workload (same ellipsoid, 12252 markers, tau, walls), "
+                      f"{steps} coupled steps after 1 untimed, FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--variant-steps", type=int, default=400)
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each case runs on a single MI355X); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2408_15115_amd import turret as T
+    from paper_2408_15115_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    case, body = W.case_ellipsoid_tall()
+    cells = case["nx"] * case["ny"] * case["nz"]
+    M = body["x_body"].shape[0]
+    log(f"workload {case['nx']}x{case['ny']}x{case['nz']} ({cells / 1e6:.1f} M cells), {M} markers, "
+        f"tau {case['tau']:.5f}, gravity {case['gravity']:.3e}")
+
+    copy_gbps = None if args.no_copy else copy_bandwidth(T, torch)
+    if copy_gbps:
+        log(f"streaming copy: {copy_gbps:.0f} GB/s")
+
+    def run_storage(storage, steps, warmup, graph):
+        S = T.Solver([case], [body], storage=storage, stream=torch.cuda.Stream())
+        total_ms, k1_ms = timed_steps(S, torch, steps, warmup)
+        st = S.body_state()
+        gms = None if not graph else graph_steps(S, torch, min(steps, 200))
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        eb = T.ELEM_BYTES[T.STORAGE[storage]]
+        kbytes = 2 * 27 * eb * cells
+        return {"ms_per_step": total_ms / steps, "mlups": cells * steps / (total_ms * 1e-3) / 1e6,
+                "k1_ms": k1_ms, "k1_gbps": kbytes / (k1_ms * 1e-3) / 1e9, "k1_bytes": kbytes,
+                "graph_ms_per_step": gms, "F": st["F"].tolist(), "v": st["v"].tolist(), "steps": st["steps"]}
+
+    log(f"timed: {args.steps} steps ({args.storage}) after {args.warmup} warm-up")
+    main_run = run_storage(args.storage, args.steps, args.warmup, not args.no_graph)
+    log(f"  {main_run['ms_per_step']:.3f} ms/step, {main_run['mlups']:.0f} MLUPS; lattice kernel "
+        f"{main_run['k1_ms']:.3f} ms = {main_run['k1_gbps']:.0f} GB/s")
+
+    variants = {}
+    if not args.no_variants:
+        ref = run_storage("f32", args.variant_steps, 5, False)
+        for sto in ("f16", "bf16"):
+            r = run_storage(sto, args.variant_steps, 5, False)
+            fz, fz_ref = r["F"][2], ref["F"][2]
+            variants[sto] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                             "k1_gbps": round(r["k1_gbps"], 1), "k1_frac": round(r["k1_gbps"] / HBM_PEAK_GBPS, 4),
+                             "drag_rel_diff_vs_f32": abs(fz - fz_ref) / abs(fz_ref),
+                             "vz_rel_diff_vs_f32": abs(r["v"][2] - ref["v"][2]) / abs(ref["v"][2]),
+                             "after_steps": args.variant_steps}
+            log(f"  {sto}: {r['mlups']:.0f} MLUPS, kernel {r['k1_gbps']:.0f} GB/s, drag diff vs f32 "
+                f"{variants[sto]['drag_rel_diff_vs_f32']:.2e}")
+        variants["f32_same_steps"] = {"mlups": round(ref["mlups"], 1), "k1_gbps": round(ref["k1_gbps"], 1)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: FP64 oracle on a 128^3 sample")
+        cpu = cpu_baseline(case, body, args.cpu_steps)
+        log(f"  {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+
+    achieved = main_run["k1_gbps"]
+    out = {
+        "metric": METRIC,
+        "value": round(main_run["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": "falling-frame box 256x256x768, tilted oblate ellipsoid 32/32/16 with 12252 "
+                               "markers, kappa 2.7, Re 100, sponge 61, free-slip z, 4 IBM cycles",
+                   "cells": cells, "markers": M, "storage": args.storage, "launch": "eager, one stream",
+                   "graph_ms_per_step": (round(main_run["graph_ms_per_step"], 5)
+                                         if main_run["graph_ms_per_step"] else None)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(args.storage),
+                     "kernel": f"k_stream_collide<{args.storage}>",
+                     "algorithmic_bytes_per_launch": main_run["k1_bytes"],
+                     "avg_launch_ms": round(main_run["k1_ms"], 5),
+                     "copy_GBps": round(copy_gbps, 1) if copy_gbps else None},
+        "cpu_baseline": cpu,
+        "variants": variants or None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * turret.h -- C ABI of the MI355X (gfx950) settling-particle time step:
+ * D3Q27 recursive-regularized lattice Boltzmann with fused pull streaming,
+ * immersed-boundary multi-direct forcing, stress-integral force and torque,
+ * the leapfrog / predictor-corrector rigid-body update and the falling-frame
+ * window, after arXiv 2408.15115 ("Palabos Turret"), Sec. 2.
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = rho_0 = rho_f = 1.  z is vertical; gravity
+ *     points along -z.  x and y are periodic (Sec. 2.5).
+ *   - Direction i = 9*(xi_z+1) + 3*(xi_y+1) + (xi_x+1); opposite(i) = 26 - i.
+ *   - Device populations are stored as deviations g_i = f_i - w_i from the
+ *     lattice weights, structure of arrays: for case c the block
+ *     [27][nz][ny][nx] starts at element offset pop_offset(c) of each of the
+ *     two population buffers.  The z index is a ring: physical row z lives at
+ *     slot (z + z0) mod nz, z0 being moved by window_shift.  FP16/BF16 storage
+ *     keeps s_i * g_i with s_i = 4096 / w_i.
+ *   - Every call returns LBM_OK (0) or a negative LBM_E* code; no C++
+ *     exception crosses the boundary.  lbm_last_error() gives the message.
+ *   - Ownership: the caller allocates all device memory (sizes from
+ *     lbm_required_bytes) and keeps it alive until lbm_destroy; the library
+ *     never allocates or frees device memory.  Host arrays passed to lbm_init
+ *     are copied.  The stream is the caller's; every call is asynchronous on
+ *     it except lbm_get_populations, lbm_set_populations, body_get_state,
+ *     lbm_save and lbm_load, which synchronize it.  A context must not be
+ *     used from two threads at once.
+ */
+#ifndef TURRET_H
+#define TURRET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument (checked before any launch) */
+    LBM_ENOMEM = -2,     /* a caller buffer is smaller than required */
+    LBM_EHIP = -3,       /* HIP runtime or launch error */
+    LBM_EUNSTABLE = -4,  /* a marker stencil left the box, or NaN/overflow seen */
+    LBM_ESTATE = -5      /* call out of order (see the step sequence below) */
+};
+
+enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 };                   /* population storage */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_FREESLIP = 1, LBM_BC_NOSLIP = 2 }; /* z walls */
+
+/* One settling case (Sec. 2.5 and Table 2).
+ *   nx, ny, nz      lattice cells, each >= 8; x, y periodic
+ *   bc_zlo, bc_zhi  LBM_BC_*: walls halfway below z = 0 and above z = nz-1;
+ *                   free-slip = specular reflection, no-slip = bounce-back
+ *   sponge_cells    0, or >= 2: tau rises linearly from tau to 1 over the top
+ *                   sponge_cells rows (Sec. 2.5)
+ *   tau             relaxation time > 0.5 (nu = (tau - 1/2)/3, Sec. 2.1)
+ *   gravity         magnitude of g along -z
+ *   h_ini, h_end    falling-frame window (Sec. 2.5): when the body centre
+ *                   drops below h_end, the whole content moves up by
+ *                   round(h_ini - h_end) rows; h_end <= 0 disables it */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t bc_zlo, bc_zhi;
+    int32_t sponge_cells;
+    double tau;
+    double gravity;
+    double h_ini, h_end;
+} lbm_case;
+
+/* The rigid particle of a case (Sec. 2.2 markers, Sec. 2.3 body).
+ *   n_markers       surface markers (0 = no particle)
+ *   x_body, n_body  host, n_markers x 3 row-major: marker positions about the
+ *                   centre of mass and outward normals, body frame
+ *   dS              host, n_markers: marker areas
+ *   kappa, volume   density ratio rho_p / rho_f and particle volume
+ *   J_over_m        body-frame inertia per unit mass, 3 x 3 row-major
+ *   r0, d0, v0, w0  centre, orientation rows d_0..d_2 (3 x 3 row-major),
+ *                   velocity v(-1/2) and angular velocity w(-1/2) */
+typedef struct {
+    int32_t n_markers;
+    const double *x_body;
+    const double *n_body;
+    const double *dS;
+    double kappa, volume;
+    double J_over_m[9];
+    double r0[3], d0[9], v0[3], w0[3];
+} lbm_body;
+
+/* Options.
+ *   storage     LBM_F32, LBM_F16 or LBM_BF16
+ *   ibm_cycles  multi-direct forcing cycles n (the paper uses 4), 1..16
+ *   block       threads per block of the lattice kernel: 64, 128 or 256
+ *               (0 = default 256)
+ *   schedule    lattice kernel tile schedule: 0 = one tile per workgroup,
+ *               1 = XCD-grouped tiles, 2 = persistent workgroups (grid =
+ *               persist_wgs) striding over the tile table */
+typedef struct {
+    int32_t storage;
+    int32_t ibm_cycles;
+    int32_t block;
+    int32_t schedule;
+    int32_t persist_wgs;
+    int32_t reserved[3];
+} lbm_options;
+
+/* Caller-owned device buffers (byte sizes from lbm_required_bytes):
+ *   pop_a, pop_b  the two population buffers (ping-pong)
+ *   aux           descriptors, body states, markers, IBM region fields */
+typedef struct {
+    void *pop_a;
+    void *pop_b;
+    void *aux;
+} lbm_buffers;
+
+/* Byte sizes of the three device buffers for n_cases cases.
+ * out_bytes[0] = pop_a, out_bytes[1] = pop_b, out_bytes[2] = aux.
+ * cases and bodies are arrays of n_cases entries (bodies may be NULL: no
+ * particles).  Errors: LBM_EINVAL for invalid cases or options. */
+int32_t lbm_required_bytes(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
+                           const lbm_options *opt, int64_t out_bytes[3]);
+
+/* Set up a context over caller buffers (Table 1 event (0)): fluid at rest
+ * (g = 0, i.e. f = w), immersed force 0, F = T = 0, body state from bodies.
+ * buf_bytes are the caller's sizes of the three buffers (checked against
+ * lbm_required_bytes: LBM_ENOMEM if smaller).  hip_stream is a hipStream_t
+ * (NULL = default stream).  Errors: LBM_EINVAL (tau <= 0.5, a dimension < 8,
+ * sponge_cells == 1, a region wider than the box, markers closer than two
+ * cells to a z wall, NULL buffers), LBM_ENOMEM, LBM_EHIP. */
+int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
+                 const lbm_options *opt, const lbm_buffers *buf, const int64_t buf_bytes[3],
+                 void *hip_stream, lbm_ctx **out);
+
+/* Step sequence of one time iteration (Table 1, Sec. 2.4), each call
+ * asynchronous on the context stream:
+ *     body_advance -> lbm_step -> ibm_couple -> window_shift
+ * Without particles only lbm_step is needed.  ibm_couple without a preceding
+ * lbm_step, or lbm_step twice without ibm_couple while particles exist,
+ * return LBM_ESTATE. */
+
+/* Table 1 event (2), Sec. 2.3: advance every body with F(t), T(t):
+ * a = g + F/(kappa V); v += a; r += v; w += M^-1 (J/m)^-1 M T/(kappa V);
+ * d_pred = d + w x d; d += w x (d + d_pred)/2, in FP64. */
+int32_t body_advance(lbm_ctx *ctx);
+
+/* Table 1 event (1), Sec. 2.1 evolution rule: pull streaming from the
+ * current buffer, recursive-regularized collision (App. A) without immersed
+ * force, written to the other buffer, which becomes current. */
+int32_t lbm_step(lbm_ctx *ctx);
+
+/* Table 1 events (3)-(4), Sec. 2.2: markers at the new body state, stress
+ * and u* from the streamed populations, F(t+1), T(t+1) from the stress
+ * integral (FP64 reductions), n-cycle multi-direct forcing, and the forced
+ * collision of Sec. 2.2 (f^(0) at u + tau h) applied to the current buffer. */
+int32_t ibm_couple(lbm_ctx *ctx);
+
+/* Sec. 2.5 re-injection, decided on the device: if the body centre is below
+ * h_end, move the content up by round(h_ini - h_end) rows (ring origin
+ * shift; the rows entering at the bottom restart at rest) and the body with
+ * it.  A no-op otherwise. */
+int32_t window_shift(lbm_ctx *ctx);
+
+/* The four calls above, nsteps times. */
+int32_t lbm_run(lbm_ctx *ctx, int32_t nsteps);
+
+/* Capture steps_per_graph (even, >= 2) full steps into a HIP graph, and
+ * replay it.  The graph reads all changing state from device memory, so one
+ * capture serves any number of replays. */
+int32_t lbm_graph_capture(lbm_ctx *ctx, int32_t steps_per_graph);
+int32_t lbm_graph_launch(lbm_ctx *ctx);
+
+/* Host copies (synchronizing).  Populations are f = w + g in FP64, layout
+ * [27][nz][ny][nx] in physical z order, of the current post-collision state
+ * of case case_id. */
+int32_t lbm_get_populations(lbm_ctx *ctx, int32_t case_id, double *host_out);
+int32_t lbm_set_populations(lbm_ctx *ctx, int32_t case_id, const double *host_in);
+
+/* Body state of a case (synchronizing), out[32]:
+ *   r(3) d(9) v(3) w(3) F(3) T(3) F_pressure(3) ibm_residual steps shifts
+ *   z0 err.  F, T are the latest stress-integral force and torque
+ *   (Sec. 2.2); F_pressure is the -pI part of F. */
+int32_t body_get_state(lbm_ctx *ctx, int32_t case_id, double out[32]);
+
+/* Checkpoint: populations (storage format), body states, ring origins and
+ * step counters; lbm_load needs a context created with the same cases. */
+int32_t lbm_save(lbm_ctx *ctx, const char *path);
+int32_t lbm_load(lbm_ctx *ctx, const char *path);
+
+/* Element offset of a case's population block inside pop_a / pop_b, and the
+ * device pointer of the current buffer (for tests that read raw storage). */
+int64_t lbm_pop_offset(const lbm_ctx *ctx, int32_t case_id);
+void *lbm_current_buffer(const lbm_ctx *ctx);
+
+/* Measurement helper: copy `bytes` (a multiple of 16) from src to dst, both
+ * device pointers, with a plain streaming kernel on hip_stream (NULL =
+ * default).  It gives the achievable HBM copy bandwidth and calibrates the
+ * hardware byte counters; it is not part of the time step.  Errors:
+ * LBM_EINVAL for NULL pointers or a bad size, LBM_EHIP. */
+int32_t lbm_stream_copy(void *dst, const void *src, int64_t bytes, void *hip_stream);
+
+int32_t lbm_destroy(lbm_ctx *ctx);
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TURRET_H */

@@ -1,0 +1,650 @@
+// api.hip -- the C ABI of libturret (declared in include/turret.h): argument
+// checks, the device memory plan over caller buffers, the Table 1 call
+// sequence with its state checks, HIP graph capture, host copies and
+// checkpoints.  All arithmetic of the time step runs in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/turret.h"
+#include "internal.hpp"
+#include "lattice.hpp"
+
+using namespace turret;
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int elem_bytes(int storage) { return storage == LBM_F32 ? 4 : 2; }
+
+struct Plan {
+    std::vector<CaseDev> cd;
+    std::vector<Tile> tiles;
+    int Mtot = 0, maxL3 = 0, max_slab = 0;
+    long long pop_elems = 0, reg_cells = 0;
+    size_t off_cases, off_body, off_tiles, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
+        off_dh, off_part, off_res, off_reg, off_H, aux_bytes;
+    int block = 256;
+};
+
+std::string check_case(const lbm_case &c, const lbm_body *b)
+{
+    char msg[256];
+    if (c.nx < 8 || c.ny < 8 || c.nz < 8) return "every dimension must be >= 8";
+    if ((long long)c.nx * c.ny * c.nz >= (1LL << 31)) return "a case must have fewer than 2^31 cells";
+    if (!(c.tau > 0.5)) return "tau must be > 0.5";
+    if (c.sponge_cells < 0 || c.sponge_cells == 1 || c.sponge_cells > c.nz) return "sponge_cells must be 0 or 2..nz";
+    for (int bc : {c.bc_zlo, c.bc_zhi})
+        if (bc < LBM_BC_PERIODIC || bc > LBM_BC_NOSLIP) return "unknown z boundary code";
+    if ((c.bc_zlo == LBM_BC_PERIODIC) != (c.bc_zhi == LBM_BC_PERIODIC)) return "periodic z needs both walls periodic";
+    if (c.h_end > 0.0 && std::lround(c.h_ini - c.h_end) >= c.nz) return "window shift exceeds the box height";
+    if (b && b->n_markers > 0) {
+        if (!b->x_body || !b->n_body || !b->dS) return "marker arrays must not be NULL";
+        if (!(b->kappa > 0) || !(b->volume > 0)) return "kappa and volume must be > 0";
+        double rb = 0;
+        for (int k = 0; k < b->n_markers; k++) {
+            double s = 0;
+            for (int a = 0; a < 3; a++) s += b->x_body[3 * k + a] * b->x_body[3 * k + a];
+            rb = std::max(rb, std::sqrt(s));
+        }
+        const double lo = b->r0[2] - rb, hi = b->r0[2] + rb;
+        if (std::floor(lo) - 1 < 0 || std::floor(hi) + 2 > c.nz - 1) {
+            std::snprintf(msg, sizeof msg, "markers closer than two cells to a z wall (z in [%g, %g], nz %d)", lo, hi, c.nz);
+            return msg;
+        }
+        const int L = (int)std::ceil(2.0 * (1.001 * rb + 0.01)) + 6;
+        if (L > c.nx || L > c.ny) return "particle region wider than the box";
+        double det = b->J_over_m[0] * (b->J_over_m[4] * b->J_over_m[8] - b->J_over_m[5] * b->J_over_m[7]) -
+                     b->J_over_m[1] * (b->J_over_m[3] * b->J_over_m[8] - b->J_over_m[5] * b->J_over_m[6]) +
+                     b->J_over_m[2] * (b->J_over_m[3] * b->J_over_m[7] - b->J_over_m[4] * b->J_over_m[6]);
+        if (!(std::fabs(det) > 0)) return "J_over_m is singular";
+    }
+    return "";
+}
+
+std::string check_options(const lbm_options *o)
+{
+    if (!o) return "";
+    if (o->storage < LBM_F32 || o->storage > LBM_BF16) return "unknown storage";
+    if (o->ibm_cycles < 0 || o->ibm_cycles > 16) return "ibm_cycles must be 1..16 (0 = default 4)";
+    if (o->block && o->block != 64 && o->block != 128 && o->block != 256) return "block must be 64, 128 or 256";
+    if (o->schedule < 0 || o->schedule > 2) return "schedule must be 0, 1 or 2";
+    if (o->persist_wgs < 0) return "persist_wgs must be >= 0";
+    return "";
+}
+
+std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, const lbm_options *opt, Plan &P)
+{
+    if (n < 1 || !cases) return "need at least one case";
+    std::string e = check_options(opt);
+    if (!e.empty()) return e;
+    P.block = (opt && opt->block) ? opt->block : 256;
+    const int eb = elem_bytes(opt ? opt->storage : LBM_F32);
+    P.cd.assign(n, CaseDev{});
+    long long pop = 0, reg = 0;
+    int moff = 0;
+    for (int c = 0; c < n; c++) {
+        const lbm_case &k = cases[c];
+        const lbm_body *b = bodies ? &bodies[c] : nullptr;
+        e = check_case(k, b);
+        if (!e.empty()) return "case " + std::to_string(c) + ": " + e;
+        CaseDev &d = P.cd[c];
+        d.nx = k.nx;
+        d.ny = k.ny;
+        d.nz = k.nz;
+        d.bc_lo = k.bc_zlo;
+        d.bc_hi = k.bc_zhi;
+        d.sponge = k.sponge_cells;
+        d.tau0 = (float)k.tau;
+        d.h_ini = k.h_ini;
+        d.h_end = k.h_end;
+        d.dz = k.h_end > 0.0 ? (int)std::lround(k.h_ini - k.h_end) : 0;
+        if (d.dz < 0) d.dz = 0;
+        d.cells = (long long)k.nx * k.ny * k.nz;
+        d.plane = (d.cells + 127) / 128 * 128;   // 256-byte aligned direction planes
+        d.pop_off = pop;
+        pop += Q * d.plane;
+        d.M = b ? std::max(0, b->n_markers) : 0;
+        d.marker_off = moff;
+        moff += d.M;
+        if (d.M > 0) {
+            double rb = 0;
+            for (int q = 0; q < d.M; q++) {
+                double s = 0;
+                for (int a = 0; a < 3; a++) s += b->x_body[3 * q + a] * b->x_body[3 * q + a];
+                rb = std::max(rb, std::sqrt(s));
+            }
+            d.L = (int)std::ceil(2.0 * (1.001 * rb + 0.01)) + 6;
+        } else {
+            d.L = 0;
+        }
+        d.reg_off = reg;
+        reg += (long long)d.L * d.L * d.L;
+        P.maxL3 = std::max(P.maxL3, d.L * d.L * d.L);
+        if (d.M > 0) P.max_slab = std::max(P.max_slab, d.dz * k.nx * k.ny);
+        const int nt = (int)((d.cells + P.block - 1) / P.block);
+        for (int t = 0; t < nt; t++) P.tiles.push_back(Tile{c, t * P.block});
+    }
+    P.pop_elems = pop;
+    P.reg_cells = reg;
+    P.Mtot = moff;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    const size_t M = (size_t)std::max(P.Mtot, 1);
+    P.off_cases = take(sizeof(CaseDev) * n);
+    P.off_body = take(sizeof(BodyDev) * n);
+    P.off_tiles = take(sizeof(Tile) * P.tiles.size());
+    P.off_mcase = take(sizeof(int) * M);
+    P.off_xb = take(sizeof(double) * 3 * M);
+    P.off_nb = take(sizeof(double) * 3 * M);
+    P.off_dS = take(sizeof(double) * M);
+    P.off_X = take(sizeof(double) * 3 * M);
+    P.off_N = take(sizeof(double) * 3 * M);
+    P.off_U = take(sizeof(double) * 3 * M);
+    P.off_hk = take(sizeof(double) * 3 * M);
+    P.off_dh = take(sizeof(double) * 3 * M);
+    P.off_part = take(sizeof(double) * kPart * M);
+    P.off_res = take(sizeof(double) * M);
+    P.off_reg = take(sizeof(float) * kRegFields * std::max<long long>(reg, 1));
+    P.off_H = take(sizeof(long long) * 3 * std::max<long long>(reg, 1));
+    P.aux_bytes = o;
+    (void)eb;
+    return "";
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    int n = 0;
+    lbm_options opt{};
+    hipStream_t stream = nullptr;
+    Plan plan;
+    std::vector<lbm_case> cases;
+    void *pop[2] = {nullptr, nullptr};
+    int cur = 0;                  // index of the buffer holding the latest post-collision state
+    char *aux = nullptr;
+    DevPtrs p{};
+    bool has_body = false;
+    bool needs_ibm = false;       // lbm_step ran, ibm_couple not yet
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0;
+    std::string err;
+};
+
+static int32_t fail(lbm_ctx *ctx, int32_t code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+static int32_t hip_fail(lbm_ctx *ctx, hipError_t e, const char *where)
+{
+    return fail(ctx, LBM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr, where)                       \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+    } while (0)
+
+static thread_local std::string g_init_error;
+
+extern "C" {
+
+int32_t lbm_required_bytes(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases, const lbm_options *opt,
+                           int64_t out_bytes[3])
+{
+    Plan P;
+    std::string e = make_plan(cases, bodies, n_cases, opt, P);
+    if (!e.empty()) {
+        g_init_error = e;
+        return LBM_EINVAL;
+    }
+    const int eb = elem_bytes(opt ? opt->storage : LBM_F32);
+    out_bytes[0] = out_bytes[1] = P.pop_elems * eb;
+    out_bytes[2] = (int64_t)P.aux_bytes;
+    return LBM_OK;
+}
+
+int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases, const lbm_options *opt,
+                 const lbm_buffers *buf, const int64_t buf_bytes[3], void *hip_stream, lbm_ctx **out)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    lbm_ctx *ctx = new lbm_ctx();
+    auto bail = [&](int32_t code, const std::string &m) {
+        g_init_error = m;
+        delete ctx;
+        return code;
+    };
+    std::string e = make_plan(cases, bodies, n_cases, opt, ctx->plan);
+    if (!e.empty()) return bail(LBM_EINVAL, e);
+    if (!buf || !buf->pop_a || !buf->pop_b || !buf->aux || !buf_bytes) return bail(LBM_EINVAL, "NULL buffer");
+    ctx->opt = opt ? *opt : lbm_options{};
+    if (ctx->opt.ibm_cycles == 0) ctx->opt.ibm_cycles = 4;
+    if (ctx->opt.block == 0) ctx->opt.block = 256;
+    const int eb = elem_bytes(ctx->opt.storage);
+    const Plan &P = ctx->plan;
+    if (buf_bytes[0] < P.pop_elems * eb || buf_bytes[1] < P.pop_elems * eb || buf_bytes[2] < (int64_t)P.aux_bytes)
+        return bail(LBM_ENOMEM, "a buffer is smaller than lbm_required_bytes");
+    ctx->n = n_cases;
+    ctx->cases.assign(cases, cases + n_cases);
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->pop[0] = buf->pop_a;
+    ctx->pop[1] = buf->pop_b;
+    ctx->aux = (char *)buf->aux;
+    char *a = ctx->aux;
+    DevPtrs &p = ctx->p;
+    p.cases = (CaseDev *)(a + P.off_cases);
+    p.body = (BodyDev *)(a + P.off_body);
+    p.tiles = (Tile *)(a + P.off_tiles);
+    p.mcase = (int *)(a + P.off_mcase);
+    p.xb = (double *)(a + P.off_xb);
+    p.nb = (double *)(a + P.off_nb);
+    p.dS = (double *)(a + P.off_dS);
+    p.X = (double *)(a + P.off_X);
+    p.N = (double *)(a + P.off_N);
+    p.U = (double *)(a + P.off_U);
+    p.hk = (double *)(a + P.off_hk);
+    p.dh = (double *)(a + P.off_dh);
+    p.part = (double *)(a + P.off_part);
+    p.res = (double *)(a + P.off_res);
+    p.reg = (float *)(a + P.off_reg);
+    p.H = (long long *)(a + P.off_H);
+
+    // host images of the descriptors, body states and markers
+    std::vector<BodyDev> bd(n_cases);
+    std::vector<int> mcase(std::max(P.Mtot, 1));
+    std::vector<double> xb(3 * std::max(P.Mtot, 1)), nb(3 * std::max(P.Mtot, 1)), dS(std::max(P.Mtot, 1));
+    for (int c = 0; c < n_cases; c++) {
+        BodyDev &B = bd[c];
+        std::memset(&B, 0, sizeof B);
+        const CaseDev &d = P.cd[c];
+        B.gravity = cases[c].gravity;
+        B.kappa = 1.0;
+        B.vol = 1.0;
+        B.d[0] = B.d[4] = B.d[8] = 1.0;
+        B.Jm_inv[0] = B.Jm_inv[4] = B.Jm_inv[8] = 1.0;
+        if (d.M > 0) {
+            const lbm_body &b = bodies[c];
+            ctx->has_body = true;
+            B.kappa = b.kappa;
+            B.vol = b.volume;
+            std::memcpy(B.r, b.r0, sizeof B.r);
+            std::memcpy(B.d, b.d0, sizeof B.d);
+            std::memcpy(B.v, b.v0, sizeof B.v);
+            std::memcpy(B.w, b.w0, sizeof B.w);
+            const double *J = b.J_over_m;
+            const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+            const double inv = 1.0 / (J[0] * c00 + J[1] * c01 + J[2] * c02);
+            const double Ji[9] = {c00 * inv, (J[2] * J[7] - J[1] * J[8]) * inv, (J[1] * J[5] - J[2] * J[4]) * inv,
+                                  c01 * inv, (J[0] * J[8] - J[2] * J[6]) * inv, (J[2] * J[3] - J[0] * J[5]) * inv,
+                                  c02 * inv, (J[1] * J[6] - J[0] * J[7]) * inv, (J[0] * J[4] - J[1] * J[3]) * inv};
+            std::memcpy(B.Jm_inv, Ji, sizeof Ji);
+            double rb = 0;
+            for (int q = 0; q < d.M; q++) {
+                double s = 0;
+                for (int k = 0; k < 3; k++) {
+                    xb[3 * (d.marker_off + q) + k] = b.x_body[3 * q + k];
+                    nb[3 * (d.marker_off + q) + k] = b.n_body[3 * q + k];
+                    s += b.x_body[3 * q + k] * b.x_body[3 * q + k];
+                }
+                dS[d.marker_off + q] = b.dS[q];
+                mcase[d.marker_off + q] = c;
+                rb = std::max(rb, std::sqrt(s));
+            }
+            B.Rb = 1.001 * rb + 0.01;
+            for (int k = 0; k < 3; k++) B.org[k] = (int)std::floor(B.r[k] - B.Rb) - 2;
+        }
+    }
+    hipStream_t s = ctx->stream;
+    const size_t popb = (size_t)P.pop_elems * eb;
+    hipError_t he;
+    if ((he = hipMemsetAsync(ctx->pop[0], 0, popb, s)) != hipSuccess ||
+        (he = hipMemsetAsync(ctx->pop[1], 0, popb, s)) != hipSuccess ||
+        (he = hipMemsetAsync(ctx->aux, 0, P.aux_bytes, s)) != hipSuccess ||
+        (he = hipMemcpyAsync(p.cases, P.cd.data(), sizeof(CaseDev) * n_cases, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (he = hipMemcpyAsync(p.body, bd.data(), sizeof(BodyDev) * n_cases, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (he = hipMemcpyAsync(p.tiles, P.tiles.data(), sizeof(Tile) * P.tiles.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (he = hipMemcpyAsync(p.mcase, mcase.data(), sizeof(int) * mcase.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (he = hipMemcpyAsync(p.xb, xb.data(), sizeof(double) * xb.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (he = hipMemcpyAsync(p.nb, nb.data(), sizeof(double) * nb.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (he = hipMemcpyAsync(p.dS, dS.data(), sizeof(double) * dS.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (he = hipStreamSynchronize(s)) != hipSuccess)
+        return bail(LBM_EHIP, std::string("init: ") + hipGetErrorString(he));
+    *out = ctx;
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------- step calls
+static int32_t do_body_advance(lbm_ctx *ctx)
+{
+    if (!ctx->has_body) return LBM_OK;
+    HIPCHK(ctx, launch_body_advance(ctx->p, ctx->n, ctx->stream), "body_advance");
+    return LBM_OK;
+}
+
+static int32_t do_lbm_step(lbm_ctx *ctx)
+{
+    const int src = ctx->cur, dst = 1 - ctx->cur;
+    HIPCHK(ctx,
+           launch_stream_collide(ctx->opt.storage, ctx->pop[src], ctx->pop[dst], ctx->p, (int)ctx->plan.tiles.size(),
+                                 ctx->opt.block, ctx->opt.schedule, ctx->opt.persist_wgs, ctx->stream),
+           "lbm_step");
+    ctx->cur = dst;
+    ctx->needs_ibm = ctx->has_body;
+    return LBM_OK;
+}
+
+static int32_t do_ibm(lbm_ctx *ctx)
+{
+    if (!ctx->has_body) return LBM_OK;
+    HIPCHK(ctx,
+           launch_ibm(ctx->opt.storage, ctx->pop[1 - ctx->cur], ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.Mtot,
+                      ctx->plan.maxL3, ctx->opt.ibm_cycles, ctx->stream),
+           "ibm_couple");
+    ctx->needs_ibm = false;
+    return LBM_OK;
+}
+
+static int32_t do_window(lbm_ctx *ctx)
+{
+    if (!ctx->has_body) return LBM_OK;
+    HIPCHK(ctx, launch_window(ctx->opt.storage, ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.max_slab, ctx->stream),
+           "window_shift");
+    return LBM_OK;
+}
+
+int32_t body_advance(lbm_ctx *ctx)
+{
+    if (!ctx) return LBM_EINVAL;
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "body_advance between lbm_step and ibm_couple");
+    return do_body_advance(ctx);
+}
+
+int32_t lbm_step(lbm_ctx *ctx)
+{
+    if (!ctx) return LBM_EINVAL;
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "lbm_step twice without ibm_couple");
+    return do_lbm_step(ctx);
+}
+
+int32_t ibm_couple(lbm_ctx *ctx)
+{
+    if (!ctx) return LBM_EINVAL;
+    if (ctx->has_body && !ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "ibm_couple without a preceding lbm_step");
+    return do_ibm(ctx);
+}
+
+int32_t window_shift(lbm_ctx *ctx)
+{
+    if (!ctx) return LBM_EINVAL;
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "window_shift between lbm_step and ibm_couple");
+    return do_window(ctx);
+}
+
+static int32_t full_step(lbm_ctx *ctx)
+{
+    int32_t r;
+    if ((r = do_body_advance(ctx)) || (r = do_lbm_step(ctx)) || (r = do_ibm(ctx)) || (r = do_window(ctx))) return r;
+    return LBM_OK;
+}
+
+int32_t lbm_run(lbm_ctx *ctx, int32_t nsteps)
+{
+    if (!ctx || nsteps < 0) return LBM_EINVAL;
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "lbm_run between lbm_step and ibm_couple");
+    for (int s = 0; s < nsteps; s++) {
+        int32_t r = full_step(ctx);
+        if (r) return r;
+    }
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------- graphs
+static void drop_graph(lbm_ctx *ctx)
+{
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->gexec = nullptr;
+    ctx->graph = nullptr;
+    ctx->gsteps = 0;
+}
+
+int32_t lbm_graph_capture(lbm_ctx *ctx, int32_t steps)
+{
+    if (!ctx) return LBM_EINVAL;
+    if (steps < 2 || steps % 2) return fail(ctx, LBM_EINVAL, "steps_per_graph must be even and >= 2");
+    if (!ctx->stream) return fail(ctx, LBM_EINVAL, "graph capture needs a non-default stream");
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "capture between lbm_step and ibm_couple");
+    drop_graph(ctx);
+    const int cur0 = ctx->cur;
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    int32_t r = LBM_OK;
+    for (int s = 0; s < steps && r == LBM_OK; s++) r = full_step(ctx);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    ctx->cur = cur0;
+    ctx->needs_ibm = false;
+    if (r) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+    ctx->graph = g;
+    e = hipGraphInstantiateWithFlags(&ctx->gexec, g, 0);
+    if (e != hipSuccess) {
+        drop_graph(ctx);
+        return hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    ctx->gsteps = steps;
+    return LBM_OK;
+}
+
+int32_t lbm_graph_launch(lbm_ctx *ctx)
+{
+    if (!ctx) return LBM_EINVAL;
+    if (!ctx->gexec) return fail(ctx, LBM_ESTATE, "no captured graph");
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "graph launch between lbm_step and ibm_couple");
+    HIPCHK(ctx, hipGraphLaunch(ctx->gexec, ctx->stream), "hipGraphLaunch");
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------ host copies
+static float host_dec(int storage, const void *raw, size_t idx, int i)
+{
+    const double inv = wq(i) / kScaleBase;
+    if (storage == LBM_F32) return ((const float *)raw)[idx];
+    if (storage == LBM_F16) return (float)((const _Float16 *)raw)[idx] * (float)inv;
+    uint32_t u = (uint32_t)((const uint16_t *)raw)[idx] << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f * (float)inv;
+}
+
+static void host_enc(int storage, void *raw, size_t idx, int i, float g)
+{
+    const float sc = (float)store_scale(i);
+    if (storage == LBM_F32) {
+        ((float *)raw)[idx] = g;
+    } else if (storage == LBM_F16) {
+        ((_Float16 *)raw)[idx] = (_Float16)(g * sc);
+    } else {
+        float f = g * sc;
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        if ((u & 0x7fffffffu) > 0x7f800000u) u = (u >> 16) | 0x40u;
+        else u = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+        ((uint16_t *)raw)[idx] = (uint16_t)u;
+    }
+}
+
+static int32_t read_body(lbm_ctx *ctx, int c, BodyDev &B)
+{
+    HIPCHK(ctx, hipMemcpyAsync(&B, ctx->p.body + c, sizeof B, hipMemcpyDeviceToHost, ctx->stream), "read body");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    return LBM_OK;
+}
+
+int32_t lbm_get_populations(lbm_ctx *ctx, int32_t c, double *out)
+{
+    if (!ctx || !out || c < 0 || c >= ctx->n) return fail(ctx, LBM_EINVAL, "bad case or NULL output");
+    BodyDev B;
+    int32_t r = read_body(ctx, c, B);
+    if (r) return r;
+    const CaseDev &d = ctx->plan.cd[c];
+    const int eb = elem_bytes(ctx->opt.storage);
+    std::vector<char> raw((size_t)Q * d.plane * eb);
+    const char *src = (const char *)ctx->pop[ctx->cur] + (size_t)d.pop_off * eb;
+    HIPCHK(ctx, hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, ctx->stream), "copy populations");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    const size_t slab = (size_t)d.nx * d.ny;
+    for (int i = 0; i < Q; i++)
+        for (int z = 0; z < d.nz; z++) {
+            const int zc = (z + B.z0) % d.nz;
+            for (size_t q = 0; q < slab; q++)
+                out[((size_t)i * d.nz + z) * slab + q] =
+                    wq(i) + (double)host_dec(ctx->opt.storage, raw.data(), (size_t)i * d.plane + zc * slab + q, i);
+        }
+    return B.err ? fail(ctx, LBM_EUNSTABLE, "unstable: marker stencil left the box or non-finite IBM value") : LBM_OK;
+}
+
+int32_t lbm_set_populations(lbm_ctx *ctx, int32_t c, const double *in)
+{
+    if (!ctx || !in || c < 0 || c >= ctx->n) return fail(ctx, LBM_EINVAL, "bad case or NULL input");
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "set_populations between lbm_step and ibm_couple");
+    BodyDev B;
+    int32_t r = read_body(ctx, c, B);
+    if (r) return r;
+    const CaseDev &d = ctx->plan.cd[c];
+    const int eb = elem_bytes(ctx->opt.storage);
+    std::vector<char> raw((size_t)Q * d.plane * eb);
+    const size_t slab = (size_t)d.nx * d.ny;
+    for (int i = 0; i < Q; i++)
+        for (int z = 0; z < d.nz; z++) {
+            const int zc = (z + B.z0) % d.nz;
+            for (size_t q = 0; q < slab; q++)
+                host_enc(ctx->opt.storage, raw.data(), (size_t)i * d.plane + zc * slab + q, i,
+                         (float)(in[((size_t)i * d.nz + z) * slab + q] - wq(i)));
+        }
+    char *dst = (char *)ctx->pop[ctx->cur] + (size_t)d.pop_off * eb;
+    HIPCHK(ctx, hipMemcpyAsync(dst, raw.data(), raw.size(), hipMemcpyHostToDevice, ctx->stream), "copy populations");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    return LBM_OK;
+}
+
+int32_t body_get_state(lbm_ctx *ctx, int32_t c, double out[32])
+{
+    if (!ctx || !out || c < 0 || c >= ctx->n) return fail(ctx, LBM_EINVAL, "bad case or NULL output");
+    BodyDev B;
+    int32_t r = read_body(ctx, c, B);
+    if (r) return r;
+    std::memcpy(out, B.r, 3 * sizeof(double));
+    std::memcpy(out + 3, B.d, 9 * sizeof(double));
+    std::memcpy(out + 12, B.v, 3 * sizeof(double));
+    std::memcpy(out + 15, B.w, 3 * sizeof(double));
+    std::memcpy(out + 18, B.F, 3 * sizeof(double));
+    std::memcpy(out + 21, B.T, 3 * sizeof(double));
+    std::memcpy(out + 24, B.Fp, 3 * sizeof(double));
+    out[27] = B.resid;
+    out[28] = B.steps;
+    out[29] = B.shifts;
+    out[30] = B.z0;
+    out[31] = B.err;
+    return B.err ? fail(ctx, LBM_EUNSTABLE, "unstable: marker stencil left the box or non-finite IBM value") : LBM_OK;
+}
+
+// ------------------------------------------------------------ checkpoints
+static const char kMagic[8] = {'T', 'U', 'R', 'R', 'E', 'T', '0', '1'};
+
+int32_t lbm_save(lbm_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return LBM_EINVAL;
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "save between lbm_step and ibm_couple");
+    const int eb = elem_bytes(ctx->opt.storage);
+    const size_t popb = (size_t)ctx->plan.pop_elems * eb;
+    std::vector<char> pop(popb);
+    std::vector<BodyDev> bd(ctx->n);
+    HIPCHK(ctx, hipMemcpyAsync(pop.data(), ctx->pop[ctx->cur], popb, hipMemcpyDeviceToHost, ctx->stream), "save");
+    HIPCHK(ctx, hipMemcpyAsync(bd.data(), ctx->p.body, sizeof(BodyDev) * ctx->n, hipMemcpyDeviceToHost, ctx->stream), "save");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(ctx, LBM_EINVAL, std::string("cannot open ") + path);
+    const int64_t hdr[4] = {ctx->n, ctx->opt.storage, (int64_t)popb, (int64_t)sizeof(BodyDev)};
+    bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+              std::fwrite(bd.data(), sizeof(BodyDev), ctx->n, f) == (size_t)ctx->n &&
+              std::fwrite(pop.data(), 1, popb, f) == popb;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? LBM_OK : fail(ctx, LBM_EINVAL, "write failed");
+}
+
+int32_t lbm_load(lbm_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return LBM_EINVAL;
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "load between lbm_step and ibm_couple");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(ctx, LBM_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    int64_t hdr[4];
+    const int eb = elem_bytes(ctx->opt.storage);
+    const size_t popb = (size_t)ctx->plan.pop_elems * eb;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+              std::fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == ctx->n && hdr[1] == ctx->opt.storage &&
+              hdr[2] == (int64_t)popb && hdr[3] == (int64_t)sizeof(BodyDev);
+    std::vector<BodyDev> bd(ctx->n);
+    std::vector<char> pop(ok ? popb : 0);
+    ok = ok && std::fread(bd.data(), sizeof(BodyDev), ctx->n, f) == (size_t)ctx->n &&
+         std::fread(pop.data(), 1, popb, f) == popb;
+    std::fclose(f);
+    if (!ok) return fail(ctx, LBM_EINVAL, "checkpoint does not match this context");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->pop[ctx->cur], pop.data(), popb, hipMemcpyHostToDevice, ctx->stream), "load");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->p.body, bd.data(), sizeof(BodyDev) * ctx->n, hipMemcpyHostToDevice, ctx->stream), "load");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    return LBM_OK;
+}
+
+int64_t lbm_pop_offset(const lbm_ctx *ctx, int32_t c)
+{
+    if (!ctx || c < 0 || c >= ctx->n) return -1;
+    return ctx->plan.cd[c].pop_off;
+}
+
+void *lbm_current_buffer(const lbm_ctx *ctx) { return ctx ? ctx->pop[ctx->cur] : nullptr; }
+
+int32_t lbm_stream_copy(void *dst, const void *src, int64_t bytes, void *hip_stream)
+{
+    if (!dst || !src || bytes <= 0 || bytes % 16) {
+        g_init_error = "lbm_stream_copy: NULL pointer or size not a positive multiple of 16";
+        return LBM_EINVAL;
+    }
+    hipError_t e = launch_copy(dst, src, bytes, (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+        g_init_error = std::string("lbm_stream_copy: ") + hipGetErrorString(e);
+        return LBM_EHIP;
+    }
+    return LBM_OK;
+}
+
+int32_t lbm_destroy(lbm_ctx *ctx)
+{
+    if (!ctx) return LBM_OK;
+    drop_graph(ctx);
+    delete ctx;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// internal.hpp -- device-side descriptors shared by the kernels and the C-ABI
+// layer of libturret (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace turret {
+
+// Static description of one case, in device memory.
+struct CaseDev {
+    int nx, ny, nz;
+    int bc_lo, bc_hi, sponge;
+    int M, marker_off;      // markers of this case: [marker_off, marker_off + M)
+    int L, dz;              // IBM region edge (cells) and window shift rows
+    long long cells;        // nx * ny * nz
+    long long plane;        // elements per direction plane (cells rounded up to 128)
+    long long pop_off;      // element offset of the case block in the population buffers
+    long long reg_off;      // cell offset of the case region in the region pool
+    float tau0;
+    int pad;
+    double h_ini, h_end;
+};
+
+// Dynamic FP64 rigid-body state of one case plus the ring origin and region
+// origin, in device memory (Sec. 2.3; window of Sec. 2.5).
+struct BodyDev {
+    double r[3], d[9], v[3], w[3];
+    double F[3], T[3], Fp[3];
+    double kappa, vol, Jm_inv[9], gravity, Rb, resid;
+    int z0;          // ring origin: physical row z is stored in slot (z + z0) mod nz
+    int shift_now;   // 1 if the window moved during the last window_shift
+    int shifts, steps;
+    int org[3];      // IBM region origin (physical cell coordinates, x/y unwrapped)
+    int err;         // bit 0: a marker stencil left the box in z; bit 1: non-finite IBM value
+};
+
+struct Tile {
+    int c;           // case
+    int first;       // first cell (flat index inside the case) of the tile
+};
+
+// Fixed-point scale of the deterministic immersed-force accumulator.
+constexpr double kFixScale = 1099511627776.0;   // 2^40
+constexpr double kFixInv = 1.0 / 1099511627776.0;
+
+// Per-marker partial sums written by the force kernel: F(3) T(3) Fp(3).
+constexpr int kPart = 9;
+// Region fields: rho - 1, u (3), sigma xx yy zz xy xz yz (6).
+constexpr int kRegFields = 10;
+
+struct DevPtrs {
+    CaseDev *cases;
+    BodyDev *body;
+    Tile *tiles;
+    int *mcase;
+    double *xb, *nb, *dS;
+    double *X, *N, *U, *hk, *dh, *part, *res;
+    float *reg;
+    long long *H;
+};
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_stream_collide(int storage, const void *src, void *dst, const DevPtrs &p, int ntiles,
+                                 int block, int schedule, int persist_wgs, hipStream_t s);
+hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
+hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
+                      int maxL3, int cycles, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s);
+hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s);
+
+}  // namespace turret

@@ -1,0 +1,650 @@
+// kernels.hip -- gfx950 kernels of the settling-particle time step
+// (arXiv 2408.15115, Sec. 2) and their stream launchers.
+//
+//   k_stream_collide  Sec. 2.1: fused pull streaming + recursive-regularized
+//                     collision (App. A), one thread per cell, SoA storage
+//   k_body_advance    Sec. 2.3: leapfrog / predictor-corrector, FP64
+//   k_markers         Sec. 2.3: marker position, normal and rigid velocity
+//   k_region_gather   Sec. 2.1 stress and Sec. 2.2 u* on the particle region
+//   k_interp_force    Sec. 2.2: l = 0 interpolation and the stress integral
+//   k_reduce_ft       FP64 force / torque sums (deterministic tree)
+//   k_spread          Sec. 2.2 l = 1 (deterministic fixed-point atomics)
+//   k_interp_update   Sec. 2.2 l = 2..4
+//   k_correct         Sec. 2.2 forced rule: add f0(u + tau h) - f0(u)
+//   k_window_*        Sec. 2.5 re-injection as a ring-origin shift
+//
+// IBM kernels give one 64-lane wavefront to each marker: lane l is the
+// stencil node (l & 3, (l >> 2) & 3, l >> 4) of the 4 x 4 x 4 weight support.
+#include "internal.hpp"
+#include "lattice.hpp"
+
+namespace turret {
+
+__device__ inline int wrapi(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// ------------------------------------------------------------------ pull
+// The 27 populations arriving at cell (x, y, z): g_i = C_i(x - xi_i) from the
+// previous post-collision buffer.  x, y periodic; at the z walls the missing
+// population comes from specular reflection (free-slip: C_{mirror_z(i)} of the
+// lateral neighbour in the same row) or bounce-back (no-slip: C_{opposite(i)}
+// of the cell itself); periodic z wraps.  Physical row z sits in ring slot
+// (z + z0) mod nz.
+template <class CD>
+__device__ inline void pull(const typename CD::T *__restrict__ src, long long plane, int nx, int ny, int nz,
+                            int z0, int bc_lo, int bc_hi, int x, int y, int z, float g[Q])
+{
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    int zc = z + z0;
+    if (zc >= nz) zc -= nz;
+    const int zlo = zc == 0 ? nz - 1 : zc - 1;
+    const int zhi = zc == nz - 1 ? 0 : zc + 1;
+    const bool wlo = (z == 0) && bc_lo != BC_PERIODIC;
+    const bool whi = (z == nz - 1) && bc_hi != BC_PERIODIC;
+    const int rowc = zc * ny, rowlo = zlo * ny, rowhi = zhi * ny;
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        int sx = cx(i) == 1 ? xm : (cx(i) == -1 ? xp : x);
+        int sy = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
+        int srow = cz(i) == 1 ? rowlo : (cz(i) == -1 ? rowhi : rowc);
+        int dir = i;
+        if constexpr (cz(i) != 0) {
+            const bool wall = cz(i) == 1 ? wlo : whi;
+            const int bc = cz(i) == 1 ? bc_lo : bc_hi;
+            if (wall) {
+                srow = rowc;
+                if (bc == BC_FREESLIP) {
+                    dir = mirror_z(i);
+                } else {
+                    dir = opposite(i);
+                    sx = x;
+                    sy = y;
+                }
+            }
+        }
+        g[i] = CD::template dec<i>(src[(long long)dir * plane + (long long)((srow + sy) * nx + sx)]);
+    });
+}
+
+template <class CD>
+__device__ inline void store_all(typename CD::T *__restrict__ dst, long long plane, int off, const float out[Q])
+{
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        dst[(long long)i * plane + off] = CD::template enc<i>(out[i]);
+    });
+}
+
+// ------------------------------------------------------------ stream-collide
+// schedule 0: tile = block; 1: tiles grouped per XCD (consecutive tiles on
+// one XCD, so neighbouring rows share its L2); 2: persistent blocks striding
+// over the tile table.
+template <class CD>
+__global__ void __launch_bounds__(256) k_stream_collide(const typename CD::T *__restrict__ src,
+                                                        typename CD::T *__restrict__ dst,
+                                                        const CaseDev *__restrict__ cases,
+                                                        const BodyDev *__restrict__ body,
+                                                        const Tile *__restrict__ tiles, int ntiles, int schedule)
+{
+    int t = blockIdx.x, tstep = 0x40000000;
+    if (schedule == 1) {
+        const int per = gridDim.x >> 3;
+        t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    } else if (schedule == 2) {
+        tstep = gridDim.x;
+    }
+    for (; t < ntiles; t += tstep) {
+        const Tile tl = tiles[t];
+        const CaseDev &cd = cases[tl.c];
+        const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
+        const int cell = tl.first + (int)threadIdx.x;
+        if (cell >= (int)cd.cells) continue;
+        const int z0 = body[tl.c].z0;
+        const int x = cell % nx;
+        const int t2 = cell / nx;
+        const int y = t2 % ny;
+        const int z = t2 / ny;
+        const typename CD::T *s = src + cd.pop_off;
+        float g[Q];
+        pull<CD>(s, cd.plane, nx, ny, nz, z0, cd.bc_lo, cd.bc_hi, x, y, z, g);
+        const Macro M = macro(raw_moments(g));
+        const float tau = tau_at(cd.tau0, nz, cd.sponge, z);
+        const float om = 1.0f - 1.0f / tau;
+        float A[Q], out[Q];
+        post_collision_coeffs(M, M.u, om, A);
+        hermite_to_populations(A, out);
+        int zc = z + z0;
+        if (zc >= nz) zc -= nz;
+        store_all<CD>(dst + cd.pop_off, cd.plane, (zc * ny + y) * nx + x, out);
+    }
+}
+
+// ---------------------------------------------------------------- body
+__device__ inline void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ inline void inverse3(const double A[9], double B[9])
+{
+    const double c00 = A[4] * A[8] - A[5] * A[7];
+    const double c01 = A[5] * A[6] - A[3] * A[8];
+    const double c02 = A[3] * A[7] - A[4] * A[6];
+    const double inv = 1.0 / (A[0] * c00 + A[1] * c01 + A[2] * c02);
+    B[0] = c00 * inv;
+    B[1] = (A[2] * A[7] - A[1] * A[8]) * inv;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) * inv;
+    B[3] = c01 * inv;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) * inv;
+    B[5] = (A[2] * A[3] - A[0] * A[5]) * inv;
+    B[6] = c02 * inv;
+    B[7] = (A[1] * A[6] - A[0] * A[7]) * inv;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) * inv;
+}
+
+__device__ inline void mv3(const double A[9], const double x[3], double y[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) y[a] = A[3 * a] * x[0] + A[3 * a + 1] * x[1] + A[3 * a + 2] * x[2];
+}
+
+// Sec. 2.3 leapfrog with F(t), T(t): a = g + F/(kappa V), v(t+1/2), r(t+1);
+// w(t+1/2) through M^-1 (J/m)^-1 M; orientation predictor-corrector.  Then
+// the IBM region origin for the new position.
+__global__ void k_body_advance(DevPtrs p, int n_cases)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cases) return;
+    const CaseDev &cd = p.cases[c];
+    if (cd.M == 0) return;
+    BodyDev &B = p.body[c];
+    const double kv = B.kappa * B.vol;
+    const double a[3] = {B.F[0] / kv, B.F[1] / kv, B.F[2] / kv - B.gravity};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        B.v[d] += a[d];
+        B.r[d] += B.v[d];
+    }
+    double Minv[9], t1[3], t2[3], t3[3];
+    inverse3(B.d, Minv);
+    mv3(B.d, B.T, t1);
+    mv3(B.Jm_inv, t1, t2);
+    mv3(Minv, t2, t3);
+#pragma unroll
+    for (int d = 0; d < 3; d++) B.w[d] += t3[d] / kv;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        double di[3] = {B.d[3 * i], B.d[3 * i + 1], B.d[3 * i + 2]}, wd[3], mid[3], wm[3];
+        cross3(B.w, di, wd);
+#pragma unroll
+        for (int d = 0; d < 3; d++) mid[d] = 0.5 * (di[d] + (di[d] + wd[d]));
+        cross3(B.w, mid, wm);
+#pragma unroll
+        for (int d = 0; d < 3; d++) B.d[3 * i + d] = di[d] + wm[d];
+    }
+    B.steps += 1;
+#pragma unroll
+    for (int d = 0; d < 3; d++) B.org[d] = (int)floor(B.r[d] - B.Rb) - 2;
+}
+
+// X_k = r + sum_j xb_kj d_j, n_k = sum_j nb_kj d_j, U_k = v + w x (X_k - r).
+__global__ void k_markers(DevPtrs p, int Mtot)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Mtot) return;
+    const int c = p.mcase[k];
+    const BodyDev &B = p.body[c];
+    const double xb[3] = {p.xb[3 * k], p.xb[3 * k + 1], p.xb[3 * k + 2]};
+    const double nb[3] = {p.nb[3 * k], p.nb[3 * k + 1], p.nb[3 * k + 2]};
+    double X[3], N[3], rel[3], wr[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        X[a] = B.r[a] + xb[0] * B.d[a] + xb[1] * B.d[3 + a] + xb[2] * B.d[6 + a];
+        N[a] = nb[0] * B.d[a] + nb[1] * B.d[3 + a] + nb[2] * B.d[6 + a];
+        rel[a] = X[a] - B.r[a];
+    }
+    cross3(B.w, rel, wr);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        p.X[3 * k + a] = X[a];
+        p.N[3 * k + a] = N[a];
+        p.U[3 * k + a] = B.v[a] + wr[a];
+    }
+    const int fz = (int)floor(X[2]);
+    if (fz - 1 < 0 || fz + 2 > p.cases[c].nz - 1) atomicOr(&p.body[c].err, 1);
+}
+
+// ------------------------------------------------------------ region fields
+// For every cell of the particle region: pull f(t+1) from the buffer the
+// lattice kernel read, then rho - 1, u* = sum xi f / sum f and the stress
+// sigma = -p I + (1/(2 tau) - 1) P1 with p = cs^2 (rho - 1) (Sec. 2.1).
+// Also clears the fixed-point immersed-force accumulator.
+template <class CD>
+__global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs p)
+{
+    const int c = blockIdx.y;
+    const CaseDev &cd = p.cases[c];
+    if (cd.M == 0) return;
+    const int L = cd.L, L3 = L * L * L;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= L3) return;
+    const BodyDev &B = p.body[c];
+    float *R = p.reg + cd.reg_off * kRegFields;
+    long long *H = p.H + cd.reg_off * 3;
+    H[q] = 0;
+    H[L3 + q] = 0;
+    H[2 * L3 + q] = 0;
+    const int a = q % L, b = (q / L) % L, cc = q / (L * L);
+    const int gz = B.org[2] + cc;
+    if (gz < 0 || gz >= cd.nz) {
+#pragma unroll
+        for (int f = 0; f < kRegFields; f++) R[f * L3 + q] = 0.0f;
+        return;
+    }
+    const int gx = wrapi(B.org[0] + a, cd.nx), gy = wrapi(B.org[1] + b, cd.ny);
+    float g[Q];
+    pull<CD>(src + cd.pop_off, cd.plane, cd.nx, cd.ny, cd.nz, B.z0, cd.bc_lo, cd.bc_hi, gx, gy, gz, g);
+    const Macro M = macro(raw_moments(g));
+    const float tau = tau_at(cd.tau0, cd.nz, cd.sponge, gz);
+    const float fac = 0.5f / tau - 1.0f;
+    const float pr = CS2 * M.r1;
+    R[0 * L3 + q] = M.r1;
+    R[1 * L3 + q] = M.u[0];
+    R[2 * L3 + q] = M.u[1];
+    R[3 * L3 + q] = M.u[2];
+    R[4 * L3 + q] = -pr + fac * M.P[0][0];
+    R[5 * L3 + q] = -pr + fac * M.P[1][1];
+    R[6 * L3 + q] = -pr + fac * M.P[2][2];
+    R[7 * L3 + q] = fac * M.P[0][1];
+    R[8 * L3 + q] = fac * M.P[0][2];
+    R[9 * L3 + q] = fac * M.P[1][2];
+}
+
+// --------------------------------------------------------- marker stencils
+// One-dimensional four-point weight function of Sec. 2.2 (two branches).
+__device__ inline double phi4(double r)
+{
+    const double a = fabs(r);
+    if (a <= 1.0) return 0.125 * (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a));
+    if (a <= 2.0) return 0.125 * (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
+    return 0.0;
+}
+
+struct Node {
+    int q;        // region cell index, -1 if outside the region
+    double W;     // tensor-product weight
+};
+
+__device__ inline Node stencil_node(const double X[3], int lane, const CaseDev &cd, const BodyDev &B)
+{
+    const int off[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+    const int n[3] = {cd.nx, cd.ny, cd.nz};
+    const int L = cd.L;
+    Node nd;
+    nd.W = 1.0;
+    int r[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int node = (int)floor(X[d]) - 1 + off[d];
+        nd.W *= phi4((double)node - X[d]);
+        int rel = node - B.org[d];
+        if (d < 2) rel = wrapi(rel, n[d]);
+        ok = ok && rel >= 0 && rel < L;
+        r[d] = rel;
+    }
+    nd.q = ok ? r[0] + L * (r[1] + L * r[2]) : -1;
+    return nd;
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// l = 0 and the stress integral: u*(X_k), h_k = U_k - u*(X_k); the traction
+// s = sigma(X_k) n_k gives F_k = dS s, T_k = dS (X_k - r) x s and the
+// pressure part dS (-p) n_k (FP64 per marker, summed by k_reduce_ft).
+__global__ void __launch_bounds__(256) k_interp_force(DevPtrs p, int Mtot)
+{
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= Mtot) return;
+    const int c = p.mcase[k];
+    const CaseDev &cd = p.cases[c];
+    const BodyDev &B = p.body[c];
+    const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
+    const Node nd = stencil_node(X, lane, cd, B);
+    const int L3 = cd.L * cd.L * cd.L;
+    const float *R = p.reg + cd.reg_off * kRegFields;
+    double v[kRegFields];
+#pragma unroll
+    for (int f = 0; f < kRegFields; f++) v[f] = nd.q >= 0 ? nd.W * (double)R[f * L3 + nd.q] : 0.0;
+#pragma unroll
+    for (int f = 0; f < kRegFields; f++) v[f] = wave_sum(v[f]);
+    if (nd.q < 0) atomicOr(&p.body[c].err, 1);
+    if (lane != 0) return;
+    const double pr = (double)CS2 * v[0];
+    const double sg[3][3] = {{v[4], v[7], v[8]}, {v[7], v[5], v[9]}, {v[8], v[9], v[6]}};
+    const double nk[3] = {p.N[3 * k], p.N[3 * k + 1], p.N[3 * k + 2]};
+    const double dS = p.dS[k];
+    double s[3], rel[3], ts[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        s[a] = sg[a][0] * nk[0] + sg[a][1] * nk[1] + sg[a][2] * nk[2];
+        rel[a] = X[a] - B.r[a];
+        const double h0 = p.U[3 * k + a] - v[1 + a];
+        p.hk[3 * k + a] = h0;
+        p.dh[3 * k + a] = h0;
+    }
+    cross3(rel, s, ts);
+    double *o = p.part + (long long)kPart * k;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        o[a] = dS * s[a];
+        o[3 + a] = dS * ts[a];
+        o[6 + a] = dS * (-pr) * nk[a];
+    }
+}
+
+// Deterministic FP64 sums of the per-marker parts of one case.
+__global__ void __launch_bounds__(256) k_reduce_ft(DevPtrs p)
+{
+    __shared__ double sh[kPart][256];
+    const int c = blockIdx.x;
+    const CaseDev &cd = p.cases[c];
+    if (cd.M == 0) return;
+    double acc[kPart];
+#pragma unroll
+    for (int j = 0; j < kPart; j++) acc[j] = 0.0;
+    for (int k = threadIdx.x; k < cd.M; k += blockDim.x) {
+        const double *o = p.part + (long long)kPart * (cd.marker_off + k);
+#pragma unroll
+        for (int j = 0; j < kPart; j++) acc[j] += o[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kPart; j++) sh[j][threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int j = 0; j < kPart; j++) sh[j][threadIdx.x] += sh[j][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        BodyDev &B = p.body[c];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            B.F[a] = sh[a][0];
+            B.T[a] = sh[3 + a][0];
+            B.Fp[a] = sh[6 + a][0];
+        }
+    }
+}
+
+// l = 1: H(x) += sum_k dh_k W(x - X_k) dS_k with int64 fixed-point atomics
+// (order-independent, hence bitwise reproducible).  The first cycle spreads
+// h_k itself; later cycles spread the l = 4 increment, which by linearity of
+// the spreading yields the spread of the updated h_k.
+__global__ void __launch_bounds__(256) k_spread(DevPtrs p, int Mtot)
+{
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= Mtot) return;
+    const int c = p.mcase[k];
+    const CaseDev &cd = p.cases[c];
+    const BodyDev &B = p.body[c];
+    const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
+    const Node nd = stencil_node(X, lane, cd, B);
+    if (nd.q < 0) return;
+    const int L3 = cd.L * cd.L * cd.L;
+    long long *H = p.H + cd.reg_off * 3;
+    const double wS = nd.W * p.dS[k];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double v = p.dh[3 * k + a] * wS;
+        long long fx = 0;
+        if (fabs(v) < 1.0e6) fx = __double2ll_rn(v * kFixScale);
+        else atomicOr(&p.body[c].err, 2);
+        atomicAdd((unsigned long long *)&H[a * L3 + nd.q], (unsigned long long)fx);
+    }
+}
+
+// l = 2..4: u3(X_k) = I[u* + H](X_k); e = U_k - u3; with update: h_k += e and
+// the next spread source is e.  The per-marker residual max |e| is kept.
+__global__ void __launch_bounds__(256) k_interp_update(DevPtrs p, int Mtot, int update)
+{
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= Mtot) return;
+    const int c = p.mcase[k];
+    const CaseDev &cd = p.cases[c];
+    const BodyDev &B = p.body[c];
+    const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
+    const Node nd = stencil_node(X, lane, cd, B);
+    const int L3 = cd.L * cd.L * cd.L;
+    const float *R = p.reg + cd.reg_off * kRegFields;
+    const long long *H = p.H + cd.reg_off * 3;
+    double v[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+        v[a] = nd.q >= 0 ? nd.W * ((double)R[(1 + a) * L3 + nd.q] + (double)H[a * L3 + nd.q] * kFixInv) : 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) v[a] = wave_sum(v[a]);
+    if (lane != 0) return;
+    double res = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double e = p.U[3 * k + a] - v[a];
+        res = fmax(res, fabs(e));
+        if (update) {
+            p.hk[3 * k + a] += e;
+            p.dh[3 * k + a] = e;
+        }
+    }
+    p.res[k] = res;
+}
+
+__global__ void __launch_bounds__(256) k_reduce_resid(DevPtrs p)
+{
+    __shared__ double sh[256];
+    const int c = blockIdx.x;
+    const CaseDev &cd = p.cases[c];
+    if (cd.M == 0) return;
+    double m = 0.0;
+    for (int k = threadIdx.x; k < cd.M; k += blockDim.x) m = fmax(m, p.res[cd.marker_off + k]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) p.body[c].resid = sh[0];
+}
+
+// Forced collision of Sec. 2.2: the lattice kernel wrote
+// f0(rho, u) + (1 - 1/tau) f1; cells carrying an immersed force get
+// f0(rho, u + tau h) - f0(rho, u) added.
+template <class CD>
+__global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
+{
+    const int c = blockIdx.y;
+    const CaseDev &cd = p.cases[c];
+    if (cd.M == 0) return;
+    const int L = cd.L, L3 = L * L * L;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= L3) return;
+    const BodyDev &B = p.body[c];
+    const int a = q % L, b = (q / L) % L, cc = q / (L * L);
+    const int gz = B.org[2] + cc;
+    if (gz < 0 || gz >= cd.nz) return;
+    const long long *H = p.H + cd.reg_off * 3;
+    const long long h0 = H[q], h1 = H[L3 + q], h2 = H[2 * L3 + q];
+    if ((h0 | h1 | h2) == 0) return;
+    const float *R = p.reg + cd.reg_off * kRegFields;
+    const float rho = 1.0f + R[q];
+    const float u[3] = {R[L3 + q], R[2 * L3 + q], R[3 * L3 + q]};
+    const float tau = tau_at(cd.tau0, cd.nz, cd.sponge, gz);
+    const float us[3] = {u[0] + tau * (float)((double)h0 * kFixInv), u[1] + tau * (float)((double)h1 * kFixInv),
+                         u[2] + tau * (float)((double)h2 * kFixInv)};
+    float A[Q], d[Q];
+    shift_coeffs(rho, u, us, A);
+    hermite_to_populations(A, d);
+    const int gx = wrapi(B.org[0] + a, cd.nx), gy = wrapi(B.org[1] + b, cd.ny);
+    int zc = gz + B.z0;
+    if (zc >= cd.nz) zc -= cd.nz;
+    const int off = (zc * cd.ny + gy) * cd.nx + gx;
+    typename CD::T *dst = cur + cd.pop_off;
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        typename CD::T &ref = dst[(long long)i * cd.plane + off];
+        ref = CD::template enc<i>(CD::template dec<i>(ref) + d[i]);
+    });
+}
+
+// ----------------------------------------------------------------- window
+// Sec. 2.5: below h_end the content and the body move up by dz rows.  With
+// the ring layout the move is the origin change z0 -> z0 - dz; the dz rows
+// that now form the bottom (the former top rows) restart at rest.
+__global__ void k_window_trigger(DevPtrs p, int n_cases)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cases) return;
+    const CaseDev &cd = p.cases[c];
+    BodyDev &B = p.body[c];
+    B.shift_now = 0;
+    if (cd.M == 0 || cd.dz <= 0 || !(cd.h_end > 0.0) || !(B.r[2] < cd.h_end)) return;
+    B.r[2] += (double)cd.dz;
+    B.z0 = wrapi(B.z0 - cd.dz, cd.nz);
+    B.shift_now = 1;
+    B.shifts += 1;
+}
+
+template <class CD>
+__global__ void k_window_reset(typename CD::T *__restrict__ cur, DevPtrs p)
+{
+    const int c = blockIdx.y;
+    const CaseDev &cd = p.cases[c];
+    const BodyDev &B = p.body[c];
+    if (!B.shift_now) return;
+    const int slab = cd.nx * cd.ny;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= cd.dz * slab) return;
+    const int zrow = idx / slab, rem = idx - zrow * slab;
+    int zc = zrow + B.z0;
+    if (zc >= cd.nz) zc -= cd.nz;
+    typename CD::T *dst = cur + cd.pop_off + (long long)zc * slab + rem;
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        dst[(long long)i * cd.plane] = CD::template enc<i>(0.0f);
+    });
+}
+
+// ------------------------------------------------------------ copy kernel
+// Plain 16-byte-per-lane streaming copy, grid-strided.
+__global__ void __launch_bounds__(256) k_copy(int4 *__restrict__ dst, const int4 *__restrict__ src, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s)
+{
+    const long long n = bytes / 16;
+    long long grid = (n + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(256), 0, s, (int4 *)dst, (const int4 *)src, n);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- launchers
+template <class CD>
+static hipError_t stream_collide_impl(const void *src, void *dst, const DevPtrs &p, int ntiles, int block,
+                                      int schedule, int persist_wgs, hipStream_t s)
+{
+    using T = typename CD::T;
+    int grid = ntiles;
+    if (schedule == 1) grid = (ntiles + 7) / 8 * 8;
+    if (schedule == 2) grid = persist_wgs > 0 ? persist_wgs : 2048;
+    hipLaunchKernelGGL(k_stream_collide<CD>, dim3(grid), dim3(block), 0, s, (const T *)src, (T *)dst, p.cases,
+                       p.body, p.tiles, ntiles, schedule);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_collide(int storage, const void *src, void *dst, const DevPtrs &p, int ntiles,
+                                 int block, int schedule, int persist_wgs, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F16: return stream_collide_impl<CodecF16>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
+    case ST_BF16: return stream_collide_impl<CodecBF16>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
+    default: return stream_collide_impl<CodecF32>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
+    }
+}
+
+hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_body_advance, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
+    return hipGetLastError();
+}
+
+template <class CD>
+static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3,
+                           int cycles, hipStream_t s)
+{
+    using T = typename CD::T;
+    const dim3 blk(256);
+    const dim3 reg_grid((maxL3 + 255) / 256, n_cases);
+    const dim3 wave_grid((Mtot + 3) / 4);
+    hipLaunchKernelGGL(k_markers, dim3((Mtot + 255) / 256), blk, 0, s, p, Mtot);
+    hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
+    hipLaunchKernelGGL(k_interp_force, wave_grid, blk, 0, s, p, Mtot);
+    hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), blk, 0, s, p);
+    for (int cyc = 1; cyc <= cycles; cyc++) {
+        hipLaunchKernelGGL(k_spread, wave_grid, blk, 0, s, p, Mtot);
+        hipLaunchKernelGGL(k_interp_update, wave_grid, blk, 0, s, p, Mtot, cyc < cycles ? 1 : 0);
+    }
+    hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p);
+    hipLaunchKernelGGL(k_correct<CD>, reg_grid, blk, 0, s, (T *)cur, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
+                      int maxL3, int cycles, hipStream_t s)
+{
+    if (Mtot == 0) return hipSuccess;
+    switch (storage) {
+    case ST_F16: return ibm_impl<CodecF16>(prev, cur, p, n_cases, Mtot, maxL3, cycles, s);
+    case ST_BF16: return ibm_impl<CodecBF16>(prev, cur, p, n_cases, Mtot, maxL3, cycles, s);
+    default: return ibm_impl<CodecF32>(prev, cur, p, n_cases, Mtot, maxL3, cycles, s);
+    }
+}
+
+template <class CD>
+static hipError_t window_impl(void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_window_trigger, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
+    if (max_slab > 0)
+        hipLaunchKernelGGL(k_window_reset<CD>, dim3((max_slab + 255) / 256, n_cases), dim3(256), 0, s,
+                           (typename CD::T *)cur, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F16: return window_impl<CodecF16>(cur, p, n_cases, max_slab, s);
+    case ST_BF16: return window_impl<CodecBF16>(cur, p, n_cases, max_slab, s);
+    default: return window_impl<CodecF32>(cur, p, n_cases, max_slab, s);
+    }
+}
+
+}  // namespace turret

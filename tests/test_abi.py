@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports every function include/turret.h declares,
+and rejects invalid arguments on the host before touching the GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2408_15115_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "turret.h")
+LIB = os.path.join(ROOT, "paper_2408_15115_amd", "libturret.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["lbm_init", "lbm_step", "ibm_couple", "body_advance", "window_shift", "lbm_required_bytes",
+              "lbm_graph_capture", "lbm_graph_launch", "body_get_state", "lbm_destroy", "lbm_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first"
+    lib = C.CDLL(LIB)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert set(declared_functions()) <= exported
+
+
+def test_binding_covers_the_header():
+    from paper_2408_15115_amd import turret as T
+    assert set(declared_functions()) == set(T.exported_symbols())
+
+
+def test_required_bytes_of_the_sphere_case():
+    from paper_2408_15115_amd import turret as T
+    case, body = W.case_sphere48()
+    a, b, aux = T.required_bytes([case], [body])
+    assert a == b == 27 * 48 ** 3 * 4
+    a16, _, _ = T.required_bytes([case], [body], storage="f16")
+    assert a16 == a // 2
+    assert aux > 400 * 8 * 3
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda c, b: c.update(tau=0.5), "tau"),
+    (lambda c, b: c.update(nx=7), "dimension"),
+    (lambda c, b: c.update(sponge=1), "sponge"),
+    (lambda c, b: b.update(r0=np.array([23.5, 23.5, 4.0])), "wall"),
+    (lambda c, b: c.update(bc_zlo=0), "periodic"),
+    (lambda c, b: c.update(nx=12, ny=12), "region"),
+])
+def test_invalid_cases_rejected_on_host(mutate, needle):
+    from paper_2408_15115_amd import turret as T
+    case, body = W.case_sphere48()
+    mutate(case, body)
+    with pytest.raises(T.TurretError) as e:
+        T.required_bytes([case], [body])
+    assert e.value.code == T.LBM_EINVAL
+    assert needle in str(e.value)
+
+
+def test_init_rejects_null_buffers_without_gpu():
+    from paper_2408_15115_amd import turret as T
+    case, body = W.case_sphere48()
+    keep = []
+    ca = (T.lbm_case * 1)(T.make_case(case))
+    ba = (T.lbm_body * 1)(T.make_body(body, keep))
+    o = T.make_options()
+    bufs = T.lbm_buffers(None, None, None)
+    sizes = (C.c_int64 * 3)(1, 1, 1)
+    ctx = C.c_void_p()
+    rc = T.lbm_init(ca, ba, 1, C.byref(o), C.byref(bufs), sizes, None, C.byref(ctx))
+    assert rc == T.LBM_EINVAL and not ctx.value
+    assert b"NULL" in T.lbm_last_error(None)
+
+
+def test_bad_options_rejected():
+    from paper_2408_15115_amd import turret as T
+    case, body = W.case_sphere48()
+    for kw in ({"storage": 7}, {"block": 96}, {"schedule": 5}, {"ibm_cycles": 40}):
+        with pytest.raises(T.TurretError):
+            T.required_bytes([case], [body], **kw)

@@ -1,0 +1,184 @@
+"""GPU parity of the whole coupled time step (Table 1) against the FP64
+oracle: the plain-method sphere case (48^3, tau 0.6, 400 markers, 200
+steps) in FP32 storage -- populations within 1e-5 relative, force and
+torque within 1e-4 -- plus the falling-frame window, graph replay,
+determinism, checkpoints and the call-order checks."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2408_15115_amd import workloads as W
+from tests.gpu_util import max_rel, oracle_to_soa, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_2408_15115_amd import turret
+    return turret
+
+
+@pytest.fixture(scope="module")
+def sphere_oracle(orc):
+    """Oracle trajectory of the 48^3 sphere case: states at 50 and 200 steps
+    and F, T, v, r at every step."""
+    case, body = W.case_sphere48()
+    say("oracle: 48^3 sphere, 200 steps")
+    s = orc.OracleSim(case, body)
+    hist = []
+    snaps = {}
+    for n in range(1, 201):
+        s.step(1)
+        hist.append(s.body_state())
+        if n in (50, 200):
+            snaps[n] = oracle_to_soa(s.post_collision())
+    return case, body, hist, snaps
+
+
+def force_scale(hist):
+    return max(np.linalg.norm(h["F"]) for h in hist)
+
+
+def test_sphere_case_matches_oracle(T, sphere_oracle):
+    case, body, hist, snaps = sphere_oracle
+    say("gpu: 48^3 sphere, 200 steps, f32")
+    S = T.Solver([case], [body])
+    Fs = force_scale(hist)
+    R = 4.0
+    worst_F = worst_T = 0.0
+    for n in range(1, 201):
+        S.run(1)
+        st = S.body_state()
+        h = hist[n - 1]
+        worst_F = max(worst_F, np.max(np.abs(st["F"] - h["F"])) / Fs)
+        worst_T = max(worst_T, np.max(np.abs(st["T"] - h["T"])) / (R * Fs))
+        if n in snaps:
+            err = max_rel(S.populations(), snaps[n])
+            say(f"  step {n}: populations max rel err {err:.3e}")
+            assert err < 1e-5
+    say(f"  force err {worst_F:.3e} torque err {worst_T:.3e}")
+    assert worst_F < 1e-4 and worst_T < 1e-4
+    final = S.body_state()
+    assert abs(final["v"][2] - hist[-1]["v"][2]) < 1e-4 * abs(hist[-1]["v"][2])
+    assert np.allclose(final["r"], hist[-1]["r"], atol=1e-8)
+    assert final["v"][2] < 0 and final["F"][2] > 0
+    assert final["err"] == 0
+
+
+def small_sphere(nz=40, zc=19.5, h_end=0.0, h_ini=0.0, markers=200, R=3.0, gravity=2e-5, bc=W.BC_FREESLIP,
+                 sponge=0, n=24, tau=0.7, w0=None):
+    case = W.make_case(n, n, nz, tau, bc, bc, sponge, gravity, h_ini=h_ini, h_end=h_end)
+    body = W.sphere_fibonacci_body(R, markers, 2.0, [(n - 1) / 2 + 0.3, (n - 1) / 2 - 0.2, zc],
+                                   w0=w0)
+    return case, body
+
+
+def test_window_shift_matches_oracle(T, orc):
+    """Shift fires at step 1 (Delta = 6 rows), then the run continues."""
+    case, body = small_sphere(h_end=19.5 - 1e-6, h_ini=25.5, sponge=5)
+    say("window shift parity")
+    o = orc.OracleSim(case, body)
+    S = T.Solver([case], [body])
+    for n in (1, 4, 12):
+        while o.body_state()["steps"] < n:
+            o.step(1)
+            S.run(1)
+        ref = oracle_to_soa(o.post_collision())
+        st, ost = S.body_state(), o.body_state()
+        assert st["shifts"] == ost["shifts"] == 1
+        assert max_rel(S.populations(), ref) < 1e-5
+        assert np.allclose(st["r"], ost["r"], atol=1e-9)
+
+
+def test_rotating_sphere_matches_oracle(T, orc):
+    case, body = small_sphere(gravity=0.0, w0=np.array([1e-3, -2e-3, 3e-3]), markers=300, R=4.0, n=28)
+    o = orc.OracleSim(case, body)
+    S = T.Solver([case], [body])
+    o.step(30)
+    S.run(30)
+    st, ost = S.body_state(), o.body_state()
+    Ts = np.linalg.norm(ost["T"])
+    assert np.max(np.abs(st["T"] - ost["T"])) < 1e-4 * Ts
+    assert np.allclose(st["w"], ost["w"], rtol=1e-6, atol=1e-12)
+    assert np.allclose(st["d"], ost["d"], atol=1e-10)
+    assert max_rel(S.populations(), oracle_to_soa(o.post_collision())) < 1e-5
+
+
+def test_graph_replay_equals_eager(T):
+    import torch
+    case, body = small_sphere()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        A = T.Solver([case], [body], stream=stream)
+        B = T.Solver([case], [body], stream=stream)
+        A.run(2)
+        B.graph_capture(2)
+        B.graph_launch()
+        stream.synchronize()
+        assert np.array_equal(A.populations(), B.populations())
+        for _ in range(3):
+            A.run(2)
+            B.graph_launch()
+            # eager host work and a synchronization between replays
+            _ = torch.zeros(1000, device="cuda").sum().item()
+            assert np.array_equal(A.populations(), B.populations())
+            sa, sb = A.body_state(), B.body_state()
+            assert np.array_equal(sa["F"], sb["F"]) and np.array_equal(sa["r"], sb["r"])
+
+
+def test_runs_are_bitwise_deterministic(T):
+    case, body = small_sphere()
+    outs = []
+    for _ in range(2):
+        S = T.Solver([case], [body])
+        S.run(15)
+        outs.append((S.populations(), S.body_state()["F"]))
+        S.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_checkpoint_resume_is_bitwise(T, tmp_path):
+    case, body = small_sphere()
+    A = T.Solver([case], [body])
+    A.run(7)
+    path = os.path.join(tmp_path, "ck.bin")
+    A.save(path)
+    A.run(6)
+    B = T.Solver([case], [body])
+    B.load(path)
+    B.run(6)
+    assert np.array_equal(A.populations(), B.populations())
+    assert np.array_equal(A.body_state()["r"], B.body_state()["r"])
+
+
+def test_call_order_is_checked(T):
+    case, body = small_sphere()
+    S = T.Solver([case], [body])
+    with pytest.raises(T.TurretError) as e:
+        S.ibm_couple()
+    assert e.value.code == T.LBM_ESTATE
+    S.body_advance()
+    S.lbm_step()
+    with pytest.raises(T.TurretError) as e:
+        S.lbm_step()
+    assert e.value.code == T.LBM_ESTATE
+    S.ibm_couple()
+    S.window_shift()
+    with pytest.raises(T.TurretError):
+        S.graph_launch()
+
+
+def test_stencil_leaving_the_box_is_reported(T):
+    """A body dropped with a large velocity reaches the bottom wall; the
+    marker kernel flags it and the next synchronizing call reports it."""
+    case, body = small_sphere(zc=6.0, nz=40)
+    body["v0"] = np.array([0.0, 0.0, -0.3])
+    S = T.Solver([case], [body])
+    S.run(8)
+    with pytest.raises(T.TurretError) as e:
+        S.body_state()
+    assert e.value.code == T.LBM_EUNSTABLE
