@@ -118,6 +118,32 @@ def copy_bandwidth(T, torch, nbytes=4 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def batch_run(T, W, torch, steps, storage):
+    """The batched form: 64 independent cases (64^3 .. 192x192x384; spheres,
+    spheroids, perturbed spheres) in one context; schedule from the autotuner."""
+    from paper_2408_15115_amd import autotune
+    batch = W.batch_cases(64)
+    cases = [c for c, _ in batch]
+    bodies = [b for _, b in batch]
+    tuned = autotune.tune(cases, storage=storage)
+    log(f"batch: schedule {tuned['best']} ({'cached' if tuned['cached'] else 'tuned'}, "
+        f"{tuned['ms']:.3f} ms per lattice launch)")
+    S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), **tuned["best"])
+    total_ms, k1_ms = timed_steps(S, torch, steps, 3)
+    errs = [S.body_state(c, check=False)["err"] for c in range(len(cases))]
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    cells = sum(c["nx"] * c["ny"] * c["nz"] for c in cases)
+    eb = T.ELEM_BYTES[T.STORAGE[storage]]
+    k1_gbps = 54 * eb * cells / (k1_ms * 1e-3) / 1e9
+    return {"cases": len(cases), "cells": cells, "markers": int(sum(b["x_body"].shape[0] for b in bodies)),
+            "steps": steps, "mlups": round(cells * steps / (total_ms * 1e-3) / 1e6, 1),
+            "ms_per_step": round(total_ms / steps, 4), "k1_gbps": round(k1_gbps, 1),
+            "k1_frac": round(k1_gbps / HBM_PEAK_GBPS, 4), "schedule": tuned["best"],
+            "schedule_cached": tuned["cached"], "masked_cases": int(sum(1 for e in errs if e))}
+
+
 def cpu_baseline(case, body, steps):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the
     same body, relaxation time and walls in a 128^3 window."""
@@ -149,6 +175,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=40)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -205,6 +233,12 @@ def main():
             log(f"  {sto}: {r['mlups']:.0f} MLUPS, kernel {r['k1_gbps']:.0f} GB/s, drag diff vs f32 "
                 f"{variants[sto]['drag_rel_diff_vs_f32']:.2e}")
         variants["f32_same_steps"] = {"mlups": round(ref["mlups"], 1), "k1_gbps": round(ref["k1_gbps"], 1)}
+
+    if not args.no_batch:
+        b = batch_run(T, W, torch, args.batch_steps, args.storage)
+        variants["batch64"] = b
+        log(f"  batch: {b['mlups']:.0f} MLUPS, {b['ms_per_step']:.2f} ms/step, kernel {b['k1_gbps']:.0f} GB/s, "
+            f"masked {b['masked_cases']}")
 
     cpu = None
     if not args.no_cpu_baseline:

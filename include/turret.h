@@ -90,18 +90,31 @@ typedef struct {
 /* Options.
  *   storage     LBM_F32, LBM_F16 or LBM_BF16
  *   ibm_cycles  multi-direct forcing cycles n (the paper uses 4), 1..16
- *   block       threads per block of the lattice kernel: 64, 128 or 256
- *               (0 = default 256)
- *   schedule    lattice kernel tile schedule: 0 = one tile per workgroup,
- *               1 = XCD-grouped tiles, 2 = persistent workgroups (grid =
- *               persist_wgs) striding over the tile table */
+ *               (0 = default 4)
+ *   block       threads per block of the lattice kernel, which is also the
+ *               tile size in cells: 64, 128 or 256 (0 = default 256)
+ *   schedule    lattice kernel schedule over the tile table:
+ *               0 = one workgroup per tile;
+ *               1 = one workgroup per tile, consecutive tiles grouped on one
+ *                   XCD (workgroups are dealt round-robin over the 8 XCDs);
+ *               2 = persistent: persist_wgs workgroups stride over the table;
+ *               3 = persistent work queue: persist_wgs workgroups take tiles
+ *                   from a device counter (dynamic balance across uneven
+ *                   cases; the counter is reset by a kernel, graph-safe)
+ *   persist_wgs workgroups of schedules 2 and 3 (0 = 2048)
+ *   tile_order  0 = case after case; 1 = tiles of all cases interleaved
+ *               round-robin; 2 = largest case first
+ *   ibm_diag    1 = keep the residual max |U_k - I[u* + H](X_k)| after every
+ *               multi-direct forcing cycle (lbm_ibm_stats), 0 = only the last */
 typedef struct {
     int32_t storage;
     int32_t ibm_cycles;
     int32_t block;
     int32_t schedule;
     int32_t persist_wgs;
-    int32_t reserved[3];
+    int32_t tile_order;
+    int32_t ibm_diag;
+    int32_t reserved;
 } lbm_options;
 
 /* Caller-owned device buffers (byte sizes from lbm_required_bytes):
@@ -163,6 +176,14 @@ int32_t window_shift(lbm_ctx *ctx);
 /* The four calls above, nsteps times. */
 int32_t lbm_run(lbm_ctx *ctx, int32_t nsteps);
 
+/* Change the lattice kernel's launch schedule (block, schedule, persist_wgs,
+ * tile_order of opt; storage and ibm_cycles must equal the context's) on a
+ * live context, e.g. from an autotuner.  Rebuilds the tile table
+ * (synchronizing) and drops a captured graph.  Results are bitwise
+ * independent of the schedule.  Errors: LBM_EINVAL, LBM_ESTATE (between
+ * lbm_step and ibm_couple), LBM_EHIP. */
+int32_t lbm_set_schedule(lbm_ctx *ctx, const lbm_options *opt);
+
 /* Capture steps_per_graph (even, >= 2) full steps into a HIP graph, and
  * replay it.  The graph reads all changing state from device memory, so one
  * capture serves any number of replays. */
@@ -178,7 +199,11 @@ int32_t lbm_set_populations(lbm_ctx *ctx, int32_t case_id, const double *host_in
 /* Body state of a case (synchronizing), out[32]:
  *   r(3) d(9) v(3) w(3) F(3) T(3) F_pressure(3) ibm_residual steps shifts
  *   z0 err.  F, T are the latest stress-integral force and torque
- *   (Sec. 2.2); F_pressure is the -pI part of F. */
+ *   (Sec. 2.2); F_pressure is the -pI part of F.  err is a bit set: 1 = a
+ *   marker stencil left the box in z, 2 = a non-finite or huge IBM value,
+ *   4 = non-finite density or |u| > 0.5 in the lattice kernel.  A case with
+ *   err != 0 is masked: its populations and body are frozen while the other
+ *   cases of the batch go on; the call then returns LBM_EUNSTABLE. */
 int32_t body_get_state(lbm_ctx *ctx, int32_t case_id, double out[32]);
 
 /* Checkpoint: populations (storage format), body states, ring origins and
@@ -190,6 +215,78 @@ int32_t lbm_load(lbm_ctx *ctx, const char *path);
  * device pointer of the current buffer (for tests that read raw storage). */
 int64_t lbm_pop_offset(const lbm_ctx *ctx, int32_t case_id);
 void *lbm_current_buffer(const lbm_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start of the multi-direct forcing.
+ *
+ * A network (12 -> 64 -> 64 -> 3, SiLU hidden layers, FP16 weights, FP32
+ * accumulation) maps each marker's features -- the interpolated velocity
+ * I[u*](X_k), the marker velocity U_k, the normal n_k and the previous
+ * step's final force h_k, velocities scaled by 50 (1 / the lattice terminal
+ * velocity 0.02) -- to the correction the cycles add to the plain l = 0
+ * start U_k - I[u*](X_k) of Sec. 2.2; start + correction replaces it.  The solver runs mlp_cycles cycles from it;
+ * a case whose residual max_k |U_k - I[u* + H](X_k)| then exceeds its gate
+ * (lbm_set_ibm_gate, default 1e-6) reruns the plain ibm_cycles cycles from
+ * the plain start.  All decisions are made on the device, so graphs stay
+ * valid.  The network is trained on samples of the solver's own plain runs
+ * (lbm_ibm_samples) by the library's forward/backward kernels and Adam.
+ *
+ * Flat FP32 parameter layout (5187 values): W1[64][12] b1[64] W2[64][64]
+ * b2[64] W3[3][64] b3[3].
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_mlp lbm_mlp;
+
+/* Device bytes of a network object able to train on batches of up to
+ * max_batch samples (1..2^20).  Errors: LBM_EINVAL. */
+int32_t mlp_required_bytes(int32_t max_batch, int64_t *out_bytes);
+
+/* Network over a caller device buffer (zeroed here; synchronizing).  Errors:
+ * LBM_EINVAL, LBM_ENOMEM (buffer too small), LBM_EHIP. */
+int32_t mlp_create(void *dev_buf, int64_t bytes, int32_t max_batch, void *hip_stream, lbm_mlp **out);
+
+/* Parameters from / to host FP32 arrays of 5187 values (synchronizing).
+ * Setting them rounds the FP16 compute copy (nearest even) and resets Adam. */
+int32_t mlp_set_params(lbm_mlp *m, const float *host_params);
+int32_t mlp_get_params(lbm_mlp *m, float *host_params);
+
+/* Device arrays: X (n x 12 FP32) -> Y (n x 3 FP32). */
+int32_t mlp_forward(lbm_mlp *m, const float *dev_x, int32_t n, float *dev_y);
+
+/* Loss L = 1/(2n) sum |Y - T|^2 and its gradient (5187 FP32 values), into
+ * device arrays (either may be NULL); n <= max_batch.  The gradient is
+ * bitwise reproducible (fixed-order sums). */
+int32_t mlp_grad(lbm_mlp *m, const float *dev_x, const float *dev_t, int32_t n, float *dev_grad, float *dev_loss);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the batch (X, T); the loss
+ * before the step goes to dev_loss when not NULL. */
+int32_t mlp_train_step(lbm_mlp *m, const float *dev_x, const float *dev_t, int32_t n, float lr, float *dev_loss);
+
+int32_t mlp_destroy(lbm_mlp *m);
+const char *mlp_last_error(const lbm_mlp *m);
+
+/* Start of ibm_couple's multi-direct forcing: LBM_WARM_NONE (the plain
+ * l = 0 start of Sec. 2.2), LBM_WARM_PREVIOUS (the previous step's final
+ * h_k, a control without network) or LBM_WARM_MLP (network m), with
+ * `cycles` (1..8) cycles before the gate.  Drops a captured graph. */
+enum { LBM_WARM_NONE = 0, LBM_WARM_PREVIOUS = 1, LBM_WARM_MLP = 2 };
+int32_t lbm_set_warm_start(lbm_ctx *ctx, int32_t mode, const lbm_mlp *m, int32_t cycles);
+
+/* Gate of a case's learned start (residual threshold, >= 0; synchronizing). */
+int32_t lbm_set_ibm_gate(lbm_ctx *ctx, int32_t case_id, double threshold);
+
+/* Samples of the last ibm_couple, to caller device arrays: features
+ * (markers x 12 FP32) and the training target, the final force h_k minus
+ * the plain start U_k - I[u*](X_k), scaled by 50 (markers x 3), markers of
+ * all cases in case order (lbm_marker_count of them).  Take them from plain
+ * runs (no warm start). */
+int32_t lbm_ibm_samples(lbm_ctx *ctx, float *dev_features, float *dev_targets);
+int32_t lbm_marker_count(const lbm_ctx *ctx);
+
+/* IBM statistics of a case (synchronizing), out[20]: last residual,
+ * residual after each cycle of the first sequence (8) and of the fallback
+ * sequence (8), learned starts accepted, rejected, and whether the last
+ * step fell back. */
+int32_t lbm_ibm_stats(lbm_ctx *ctx, int32_t case_id, double out[20]);
 
 /* Measurement helper: copy `bytes` (a multiple of 16) from src to dst, both
  * device pointers, with a plain streaming kernel on hip_stream (NULL =

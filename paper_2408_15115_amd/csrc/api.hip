@@ -14,6 +14,7 @@
 #include "../../include/turret.h"
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "mlp.hpp"
 
 using namespace turret;
 
@@ -26,10 +27,11 @@ int elem_bytes(int storage) { return storage == LBM_F32 ? 4 : 2; }
 struct Plan {
     std::vector<CaseDev> cd;
     std::vector<Tile> tiles;
+    long long max_tiles = 0;    // tile table capacity: the count at the smallest block (64)
     int Mtot = 0, maxL3 = 0, max_slab = 0;
     long long pop_elems = 0, reg_cells = 0;
-    size_t off_cases, off_body, off_tiles, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
-        off_dh, off_part, off_res, off_reg, off_H, aux_bytes;
+    size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
+        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, aux_bytes;
     int block = 256;
 };
 
@@ -74,9 +76,37 @@ std::string check_options(const lbm_options *o)
     if (o->storage < LBM_F32 || o->storage > LBM_BF16) return "unknown storage";
     if (o->ibm_cycles < 0 || o->ibm_cycles > 16) return "ibm_cycles must be 1..16 (0 = default 4)";
     if (o->block && o->block != 64 && o->block != 128 && o->block != 256) return "block must be 64, 128 or 256";
-    if (o->schedule < 0 || o->schedule > 2) return "schedule must be 0, 1 or 2";
-    if (o->persist_wgs < 0) return "persist_wgs must be >= 0";
+    if (o->schedule < 0 || o->schedule > 3) return "schedule must be 0..3";
+    if (o->persist_wgs < 0 || o->persist_wgs > (1 << 20)) return "persist_wgs must be 0..2^20";
+    if (o->tile_order < 0 || o->tile_order > 2) return "tile_order must be 0, 1 or 2";
+    if (o->ibm_diag < 0 || o->ibm_diag > 1) return "ibm_diag must be 0 or 1";
     return "";
+}
+
+// Tile table of the lattice kernel: tiles of `block` consecutive cells, in
+// case order (0), interleaved round-robin over the cases (1), or with the
+// largest cases first (2).
+void build_tiles(Plan &P, int block, int order)
+{
+    const int n = (int)P.cd.size();
+    std::vector<int> nt(n), ord(n);
+    for (int c = 0; c < n; c++) {
+        nt[c] = (int)((P.cd[c].cells + block - 1) / block);
+        ord[c] = c;
+    }
+    if (order == 2)
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return P.cd[a].cells > P.cd[b].cells; });
+    auto tile = [&](int c, int t) { return Tile{c, t * block}; };
+    P.tiles.clear();
+    if (order == 1) {
+        const int most = *std::max_element(nt.begin(), nt.end());
+        for (int t = 0; t < most; t++)
+            for (int c = 0; c < n; c++)
+                if (t < nt[c]) P.tiles.push_back(tile(c, t));
+    } else {
+        for (int c : ord)
+            for (int t = 0; t < nt[c]; t++) P.tiles.push_back(tile(c, t));
+    }
 }
 
 std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, const lbm_options *opt, Plan &P)
@@ -128,9 +158,9 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         reg += (long long)d.L * d.L * d.L;
         P.maxL3 = std::max(P.maxL3, d.L * d.L * d.L);
         if (d.M > 0) P.max_slab = std::max(P.max_slab, d.dz * k.nx * k.ny);
-        const int nt = (int)((d.cells + P.block - 1) / P.block);
-        for (int t = 0; t < nt; t++) P.tiles.push_back(Tile{c, t * P.block});
+        P.max_tiles += (d.cells + 63) / 64;
     }
+    build_tiles(P, P.block, opt ? opt->tile_order : 0);
     P.pop_elems = pop;
     P.reg_cells = reg;
     P.Mtot = moff;
@@ -143,7 +173,8 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     const size_t M = (size_t)std::max(P.Mtot, 1);
     P.off_cases = take(sizeof(CaseDev) * n);
     P.off_body = take(sizeof(BodyDev) * n);
-    P.off_tiles = take(sizeof(Tile) * P.tiles.size());
+    P.off_tiles = take(sizeof(Tile) * P.max_tiles);
+    P.off_counter = take(8 * sizeof(int));
     P.off_mcase = take(sizeof(int) * M);
     P.off_xb = take(sizeof(double) * 3 * M);
     P.off_nb = take(sizeof(double) * 3 * M);
@@ -157,6 +188,8 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_res = take(sizeof(double) * M);
     P.off_reg = take(sizeof(float) * kRegFields * std::max<long long>(reg, 1));
     P.off_H = take(sizeof(long long) * 3 * std::max<long long>(reg, 1));
+    P.off_feat = take(sizeof(float) * kMlpIn * M);
+    P.off_h0 = take(sizeof(double) * 3 * M);
     P.aux_bytes = o;
     (void)eb;
     return "";
@@ -179,6 +212,19 @@ struct lbm_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int gsteps = 0;
+    int warm_mode = LBM_WARM_NONE;        // start of the multi-direct forcing
+    const _Float16 *mlp_th16 = nullptr;   // warm-start network (FP16 weights)
+    int mlp_cycles = 0;
+    std::string err;
+};
+
+struct lbm_mlp {
+    hipStream_t stream = nullptr;
+    int max_batch = 0;
+    int step = 0;
+    float *th32 = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
+    _Float16 *th16 = nullptr;
+    MlpScratch sc{};
     std::string err;
 };
 
@@ -235,6 +281,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     ctx->opt = opt ? *opt : lbm_options{};
     if (ctx->opt.ibm_cycles == 0) ctx->opt.ibm_cycles = 4;
     if (ctx->opt.block == 0) ctx->opt.block = 256;
+    if (ctx->opt.schedule >= 2 && ctx->opt.persist_wgs == 0) ctx->opt.persist_wgs = 2048;
     const int eb = elem_bytes(ctx->opt.storage);
     const Plan &P = ctx->plan;
     if (buf_bytes[0] < P.pop_elems * eb || buf_bytes[1] < P.pop_elems * eb || buf_bytes[2] < (int64_t)P.aux_bytes)
@@ -250,6 +297,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.cases = (CaseDev *)(a + P.off_cases);
     p.body = (BodyDev *)(a + P.off_body);
     p.tiles = (Tile *)(a + P.off_tiles);
+    p.counter = (int *)(a + P.off_counter);
     p.mcase = (int *)(a + P.off_mcase);
     p.xb = (double *)(a + P.off_xb);
     p.nb = (double *)(a + P.off_nb);
@@ -263,6 +311,8 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.res = (double *)(a + P.off_res);
     p.reg = (float *)(a + P.off_reg);
     p.H = (long long *)(a + P.off_H);
+    p.feat = (float *)(a + P.off_feat);
+    p.h0 = (double *)(a + P.off_h0);
 
     // host images of the descriptors, body states and markers
     std::vector<BodyDev> bd(n_cases);
@@ -273,6 +323,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
         std::memset(&B, 0, sizeof B);
         const CaseDev &d = P.cd[c];
         B.gravity = cases[c].gravity;
+        B.gate = 1e-6;
         B.kappa = 1.0;
         B.vol = 1.0;
         B.d[0] = B.d[4] = B.d[8] = 1.0;
@@ -353,7 +404,8 @@ static int32_t do_ibm(lbm_ctx *ctx)
     if (!ctx->has_body) return LBM_OK;
     HIPCHK(ctx,
            launch_ibm(ctx->opt.storage, ctx->pop[1 - ctx->cur], ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.Mtot,
-                      ctx->plan.maxL3, ctx->opt.ibm_cycles, ctx->stream),
+                      ctx->plan.maxL3, ctx->opt.ibm_cycles, ctx->warm_mode, ctx->mlp_th16, ctx->mlp_cycles,
+                      ctx->opt.ibm_diag, ctx->stream),
            "ibm_couple");
     ctx->needs_ibm = false;
     return LBM_OK;
@@ -410,6 +462,31 @@ int32_t lbm_run(lbm_ctx *ctx, int32_t nsteps)
         int32_t r = full_step(ctx);
         if (r) return r;
     }
+    return LBM_OK;
+}
+
+static void drop_graph(lbm_ctx *ctx);
+
+int32_t lbm_set_schedule(lbm_ctx *ctx, const lbm_options *opt)
+{
+    if (!ctx || !opt) return LBM_EINVAL;
+    std::string e = check_options(opt);
+    if (!e.empty()) return fail(ctx, LBM_EINVAL, e);
+    const int cyc = opt->ibm_cycles ? opt->ibm_cycles : 4;
+    if (opt->storage != ctx->opt.storage || cyc != ctx->opt.ibm_cycles)
+        return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage or ibm_cycles");
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "lbm_set_schedule between lbm_step and ibm_couple");
+    const int block = opt->block ? opt->block : 256;
+    build_tiles(ctx->plan, block, opt->tile_order);
+    ctx->plan.block = block;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->p.tiles, ctx->plan.tiles.data(), sizeof(Tile) * ctx->plan.tiles.size(),
+                               hipMemcpyHostToDevice, ctx->stream), "upload tile table");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    drop_graph(ctx);
+    ctx->opt.block = block;
+    ctx->opt.schedule = opt->schedule;
+    ctx->opt.persist_wgs = opt->schedule >= 2 && opt->persist_wgs == 0 ? 2048 : opt->persist_wgs;
+    ctx->opt.tile_order = opt->tile_order;
     return LBM_OK;
 }
 
@@ -614,6 +691,207 @@ int32_t lbm_load(lbm_ctx *ctx, const char *path)
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     return LBM_OK;
 }
+
+// ------------------------------------------------------- learned warm start
+static size_t mlp_layout(int max_batch, size_t off[12])
+{
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    const size_t P = kMlpParams, n = (size_t)max_batch;
+    const size_t slices = (n + kMlpSlice - 1) / kMlpSlice, blocks = (n + 255) / 256;
+    off[0] = take(4 * P);                      // th32
+    off[1] = take(2 * P);                      // th16
+    off[2] = take(4 * P);                      // m
+    off[3] = take(4 * P);                      // v
+    off[4] = take(4 * P);                      // grad
+    off[5] = take(4);                          // loss
+    off[6] = take(4 * n * 4 * kMlpH);          // a1 a2 d1 d2
+    off[7] = take(4 * n * 2 * kMlpH);          // dz1 dz2
+    off[8] = take(4 * n * kMlpOut);            // dy
+    off[9] = take(4 * slices * P);             // gradient partials
+    off[10] = take(4 * blocks);                // loss partials
+    return o;
+}
+
+int32_t mlp_required_bytes(int32_t max_batch, int64_t *out_bytes)
+{
+    if (max_batch < 1 || max_batch > (1 << 20) || !out_bytes) {
+        g_init_error = "mlp_required_bytes: max_batch must be 1..2^20";
+        return LBM_EINVAL;
+    }
+    size_t off[12];
+    *out_bytes = (int64_t)mlp_layout(max_batch, off);
+    return LBM_OK;
+}
+
+int32_t mlp_create(void *dev_buf, int64_t bytes, int32_t max_batch, void *hip_stream, lbm_mlp **out)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    int64_t need = 0;
+    if (mlp_required_bytes(max_batch, &need)) return LBM_EINVAL;
+    if (!dev_buf) {
+        g_init_error = "mlp_create: NULL buffer";
+        return LBM_EINVAL;
+    }
+    if (bytes < need) {
+        g_init_error = "mlp_create: buffer smaller than mlp_required_bytes";
+        return LBM_ENOMEM;
+    }
+    lbm_mlp *m = new lbm_mlp();
+    size_t off[12];
+    mlp_layout(max_batch, off);
+    char *b = (char *)dev_buf;
+    m->stream = (hipStream_t)hip_stream;
+    m->max_batch = max_batch;
+    m->th32 = (float *)(b + off[0]);
+    m->th16 = (_Float16 *)(b + off[1]);
+    m->m = (float *)(b + off[2]);
+    m->v = (float *)(b + off[3]);
+    m->grad = (float *)(b + off[4]);
+    m->loss = (float *)(b + off[5]);
+    const size_t n = (size_t)max_batch;
+    float *act = (float *)(b + off[6]);
+    m->sc.a1 = act;
+    m->sc.a2 = act + n * kMlpH;
+    m->sc.d1 = act + 2 * n * kMlpH;
+    m->sc.d2 = act + 3 * n * kMlpH;
+    float *dz = (float *)(b + off[7]);
+    m->sc.dz1 = dz;
+    m->sc.dz2 = dz + n * kMlpH;
+    m->sc.dy = (float *)(b + off[8]);
+    m->sc.part = (float *)(b + off[9]);
+    m->sc.loss_part = (float *)(b + off[10]);
+    hipError_t e = hipMemsetAsync(dev_buf, 0, (size_t)need, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) {
+        g_init_error = std::string("mlp_create: ") + hipGetErrorString(e);
+        delete m;
+        return LBM_EHIP;
+    }
+    *out = m;
+    return LBM_OK;
+}
+
+static int32_t mlp_fail(lbm_mlp *m, int32_t code, const std::string &msg)
+{
+    if (m) m->err = msg;
+    return code;
+}
+
+int32_t mlp_set_params(lbm_mlp *m, const float *host_params)
+{
+    if (!m || !host_params) return LBM_EINVAL;
+    hipError_t e = hipMemcpyAsync(m->th32, host_params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->m, 0, sizeof(float) * kMlpParams, m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->v, 0, sizeof(float) * kMlpParams, m->stream);
+    if (e == hipSuccess) e = launch_mlp_round(m->th32, m->th16, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) return mlp_fail(m, LBM_EHIP, std::string("mlp_set_params: ") + hipGetErrorString(e));
+    m->step = 0;
+    return LBM_OK;
+}
+
+int32_t mlp_get_params(lbm_mlp *m, float *host_params)
+{
+    if (!m || !host_params) return LBM_EINVAL;
+    hipError_t e = hipMemcpyAsync(host_params, m->th32, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) return mlp_fail(m, LBM_EHIP, std::string("mlp_get_params: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int32_t mlp_forward(lbm_mlp *m, const float *dev_x, int32_t n, float *dev_y)
+{
+    if (!m || !dev_x || !dev_y || n < 1) return m ? mlp_fail(m, LBM_EINVAL, "mlp_forward: bad arguments") : LBM_EINVAL;
+    hipError_t e = launch_mlp_forward(m->th16, dev_x, n, dev_y, m->stream);
+    if (e != hipSuccess) return mlp_fail(m, LBM_EHIP, std::string("mlp_forward: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int32_t mlp_grad(lbm_mlp *m, const float *dev_x, const float *dev_t, int32_t n, float *dev_grad, float *dev_loss)
+{
+    if (!m || !dev_x || !dev_t || n < 1 || n > m->max_batch)
+        return m ? mlp_fail(m, LBM_EINVAL, "mlp_grad: bad arguments or n > max_batch") : LBM_EINVAL;
+    hipError_t e = launch_mlp_grad(m->th16, dev_x, dev_t, n, m->sc, dev_grad ? dev_grad : m->grad,
+                                   dev_loss ? dev_loss : m->loss, m->stream);
+    if (e != hipSuccess) return mlp_fail(m, LBM_EHIP, std::string("mlp_grad: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int32_t mlp_train_step(lbm_mlp *m, const float *dev_x, const float *dev_t, int32_t n, float lr, float *dev_loss)
+{
+    int32_t r = mlp_grad(m, dev_x, dev_t, n, nullptr, dev_loss);
+    if (r) return r;
+    m->step += 1;
+    hipError_t e = launch_mlp_adam(m->th32, m->th16, m->m, m->v, m->grad, lr, m->step, m->stream);
+    if (e != hipSuccess) return mlp_fail(m, LBM_EHIP, std::string("mlp_train_step: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+const char *mlp_last_error(const lbm_mlp *m) { return m ? m->err.c_str() : g_init_error.c_str(); }
+
+int32_t mlp_destroy(lbm_mlp *m)
+{
+    delete m;
+    return LBM_OK;
+}
+
+int32_t lbm_set_warm_start(lbm_ctx *ctx, int32_t mode, const lbm_mlp *m, int32_t cycles)
+{
+    if (!ctx) return LBM_EINVAL;
+    if (mode < LBM_WARM_NONE || mode > LBM_WARM_MLP) return fail(ctx, LBM_EINVAL, "unknown warm-start mode");
+    if (mode == LBM_WARM_MLP && !m) return fail(ctx, LBM_EINVAL, "network warm start needs a network");
+    if (mode != LBM_WARM_NONE && (cycles < 1 || cycles > 8)) return fail(ctx, LBM_EINVAL, "cycles must be 1..8");
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "warm-start change between lbm_step and ibm_couple");
+    drop_graph(ctx);
+    ctx->warm_mode = mode;
+    ctx->mlp_th16 = mode == LBM_WARM_MLP ? m->th16 : nullptr;
+    ctx->mlp_cycles = mode == LBM_WARM_NONE ? 0 : cycles;
+    return LBM_OK;
+}
+
+int32_t lbm_set_ibm_gate(lbm_ctx *ctx, int32_t c, double threshold)
+{
+    if (!ctx || c < 0 || c >= ctx->n || !(threshold >= 0)) return fail(ctx, LBM_EINVAL, "bad case or threshold");
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "set_ibm_gate between lbm_step and ibm_couple");
+    HIPCHK(ctx, hipMemcpyAsync(&ctx->p.body[c].gate, &threshold, sizeof(double), hipMemcpyHostToDevice, ctx->stream),
+           "set gate");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    return LBM_OK;
+}
+
+int32_t lbm_ibm_samples(lbm_ctx *ctx, float *dev_features, float *dev_targets)
+{
+    if (!ctx || !dev_features || !dev_targets) return fail(ctx, LBM_EINVAL, "NULL output");
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "samples between lbm_step and ibm_couple");
+    const int M = ctx->plan.Mtot;
+    if (M == 0) return LBM_OK;
+    HIPCHK(ctx, hipMemcpyAsync(dev_features, ctx->p.feat, sizeof(float) * kMlpIn * M, hipMemcpyDeviceToDevice,
+                               ctx->stream), "copy features");
+    HIPCHK(ctx, launch_targets(ctx->p, M, dev_targets, ctx->stream), "targets");
+    return LBM_OK;
+}
+
+int32_t lbm_ibm_stats(lbm_ctx *ctx, int32_t c, double out[20])
+{
+    if (!ctx || !out || c < 0 || c >= ctx->n) return fail(ctx, LBM_EINVAL, "bad case or NULL output");
+    BodyDev B;
+    int32_t r = read_body(ctx, c, B);
+    if (r) return r;
+    out[0] = B.resid;
+    for (int k = 0; k < 16; k++) out[1 + k] = B.resid_hist[k];
+    out[17] = B.accepts;
+    out[18] = B.rejects;
+    out[19] = B.fallback;
+    return LBM_OK;
+}
+
+int32_t lbm_marker_count(const lbm_ctx *ctx) { return ctx ? ctx->plan.Mtot : -1; }
 
 int64_t lbm_pop_offset(const lbm_ctx *ctx, int32_t c)
 {

@@ -31,8 +31,13 @@ struct BodyDev {
     int z0;          // ring origin: physical row z is stored in slot (z + z0) mod nz
     int shift_now;   // 1 if the window moved during the last window_shift
     int shifts, steps;
+    double gate;                // learned start accepted while its residual is <= gate
+    double resid_hist[16];      // per-cycle residuals: [0..7] first sequence, [8..15] fallback
+    int accepts, rejects;       // learned-start decisions so far
+    int fallback;               // 1 if the last step fell back to the plain start
     int org[3];      // IBM region origin (physical cell coordinates, x/y unwrapped)
-    int err;         // bit 0: a marker stencil left the box in z; bit 1: non-finite IBM value
+    int err;         // 1: a marker stencil left the box in z; 2: non-finite or huge IBM value;
+                     // 4: non-finite density or |u| > 0.5.  Nonzero masks (freezes) the case.
 };
 
 struct Tile {
@@ -58,14 +63,23 @@ struct DevPtrs {
     double *X, *N, *U, *hk, *dh, *part, *res;
     float *reg;
     long long *H;
+    int *counter;    // 8 work-queue counters of the persistent lattice schedule
+    float *feat;     // per-marker warm-start features (12), velocities scaled by kFeatScale
+    double *h0;      // per-marker plain start U - I[u*] (3)
 };
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_stream_collide(int storage, const void *src, void *dst, const DevPtrs &p, int ntiles,
                                  int block, int schedule, int persist_wgs, hipStream_t s);
 hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
+// IBM coupling.  With a warm start (warm_mode 1: the previous step's final
+// h_k; 2: the network th16) the first sequence runs warm_cycles cycles from
+// that start; cases whose residual exceeds their gate then rerun `cycles`
+// plain cycles.  diag keeps the residual of every cycle.
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
-                      int maxL3, int cycles, hipStream_t s);
+                      int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles, int diag,
+                      hipStream_t s);
+hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s);
 hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s);
 

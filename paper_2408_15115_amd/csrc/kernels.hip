@@ -17,6 +17,7 @@
 // stencil node (l & 3, (l >> 2) & 3, l >> 4) of the 4 x 4 x 4 weight support.
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "mlp.hpp"
 
 namespace turret {
 
@@ -70,57 +71,99 @@ __device__ inline void pull(const typename CD::T *__restrict__ src, long long pl
     });
 }
 
+// Every population is written once per step and not read again before the
+// next step: the stores carry the non-temporal hint (measured faster; the
+// same hint on the loads is not).
 template <class CD>
-__device__ inline void store_all(typename CD::T *__restrict__ dst, long long plane, int off, const float out[Q])
+__device__ __forceinline__ void store_all(typename CD::T *__restrict__ dst, long long plane, int off, const float out[Q])
 {
     Unroll<0, Q>::run([&](auto I) {
         constexpr int i = decltype(I)::value;
-        dst[(long long)i * plane + off] = CD::template enc<i>(out[i]);
+        __builtin_nontemporal_store(CD::template enc<i>(out[i]), &dst[(long long)i * plane + off]);
     });
 }
 
 // ------------------------------------------------------------ stream-collide
-// schedule 0: tile = block; 1: tiles grouped per XCD (consecutive tiles on
-// one XCD, so neighbouring rows share its L2); 2: persistent blocks striding
-// over the tile table.
+// One tile = blockDim.x consecutive cells of one case.  A case whose error
+// bits are set is masked (frozen) so the rest of a batch goes on.  The guard
+// flags non-finite density or |u| > 0.5 (bit 4) with one atomic per wave.
 template <class CD>
+__device__ __forceinline__ void stream_collide_tile(const typename CD::T *__restrict__ src, typename CD::T *__restrict__ dst,
+                                                    const CaseDev *__restrict__ cases, BodyDev *__restrict__ body, Tile tl)
+{
+    const CaseDev &cd = cases[tl.c];
+    const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
+    const int cell = tl.first + (int)threadIdx.x;
+    if (body[tl.c].err != 0 || cell >= (int)cd.cells) return;
+    const int z0 = body[tl.c].z0;
+    const int x = cell % nx;
+    const int t2 = cell / nx;
+    const int y = t2 % ny;
+    const int z = t2 / ny;
+    float g[Q];
+    pull<CD>(src + cd.pop_off, cd.plane, nx, ny, nz, z0, cd.bc_lo, cd.bc_hi, x, y, z, g);
+    const Macro M = macro(raw_moments(g));
+    const float u2 = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
+    const bool bad = !(fabsf(M.r1) < 1.0f) || !(u2 < 0.25f);
+    const unsigned long long m = __ballot(bad);
+    if (m != 0ull && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)m) - 1) atomicOr(&body[tl.c].err, 4);
+    const float tau = tau_at(cd.tau0, nz, cd.sponge, z);
+    const float om = 1.0f - 1.0f / tau;
+    float A[Q], out[Q];
+    post_collision_coeffs(M, M.u, om, A);
+    hermite_to_populations(A, out);
+    int zc = z + z0;
+    if (zc >= nz) zc -= nz;
+    store_all<CD>(dst + cd.pop_off, cd.plane, (zc * ny + y) * nx + x, out);
+}
+
+// SCHED 0: tile = workgroup; 1: XCD-grouped tiles (workgroups go
+// round-robin over the 8 XCDs, so workgroup b handles tile
+// (b mod 8) * (grid / 8) + b / 8 and neighbouring rows share one L2);
+// 2: persistent workgroups striding over the table; 3: persistent work
+// queue.  The queue is split in 8 contiguous segments with one counter each
+// (a single device-wide counter serializes every grab across the XCDs);
+// workgroup b starts on segment b mod 8, takes kQueueChunk tiles per grab and
+// moves on to the other segments when its own is exhausted.  Counters only
+// grow, so every workgroup leaves the loop.  One instantiation per schedule
+// keeps the register allocation of the plain schedules free of the loops.
+constexpr int kQueueChunk = 4;
+
+template <class CD, int SCHED>
 __global__ void __launch_bounds__(256) k_stream_collide(const typename CD::T *__restrict__ src,
                                                         typename CD::T *__restrict__ dst,
-                                                        const CaseDev *__restrict__ cases,
-                                                        const BodyDev *__restrict__ body,
-                                                        const Tile *__restrict__ tiles, int ntiles, int schedule)
+                                                        const CaseDev *__restrict__ cases, BodyDev *__restrict__ body,
+                                                        const Tile *__restrict__ tiles, int ntiles,
+                                                        int *__restrict__ counter)
 {
-    int t = blockIdx.x, tstep = 0x40000000;
-    if (schedule == 1) {
-        const int per = gridDim.x >> 3;
-        t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    } else if (schedule == 2) {
-        tstep = gridDim.x;
+    if constexpr (SCHED == 3) {
+        __shared__ int s_t;
+        const int per = (ntiles + 7) >> 3;
+        for (int k = 0; k < 8; k++) {
+            const int grp = (blockIdx.x + k) & 7;
+            const int lo = grp * per, hi = min(ntiles, lo + per);
+            for (;;) {
+                if (threadIdx.x == 0) s_t = lo + kQueueChunk * atomicAdd(&counter[grp], 1);
+                __syncthreads();
+                const int t0 = __builtin_amdgcn_readfirstlane(s_t);
+                __syncthreads();
+                if (t0 >= hi) break;
+                const int t1 = min(t0 + kQueueChunk, hi);
+                for (int t = t0; t < t1; t++) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
+            }
+        }
+    } else if constexpr (SCHED == 2) {
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
+    } else {
+        int t = blockIdx.x;
+        if constexpr (SCHED == 1) t = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+        if (t < ntiles) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
     }
-    for (; t < ntiles; t += tstep) {
-        const Tile tl = tiles[t];
-        const CaseDev &cd = cases[tl.c];
-        const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
-        const int cell = tl.first + (int)threadIdx.x;
-        if (cell >= (int)cd.cells) continue;
-        const int z0 = body[tl.c].z0;
-        const int x = cell % nx;
-        const int t2 = cell / nx;
-        const int y = t2 % ny;
-        const int z = t2 / ny;
-        const typename CD::T *s = src + cd.pop_off;
-        float g[Q];
-        pull<CD>(s, cd.plane, nx, ny, nz, z0, cd.bc_lo, cd.bc_hi, x, y, z, g);
-        const Macro M = macro(raw_moments(g));
-        const float tau = tau_at(cd.tau0, nz, cd.sponge, z);
-        const float om = 1.0f - 1.0f / tau;
-        float A[Q], out[Q];
-        post_collision_coeffs(M, M.u, om, A);
-        hermite_to_populations(A, out);
-        int zc = z + z0;
-        if (zc >= nz) zc -= nz;
-        store_all<CD>(dst + cd.pop_off, cd.plane, (zc * ny + y) * nx + x, out);
-    }
+}
+
+__global__ void k_reset_counter(int *counter)
+{
+    if (threadIdx.x < 8) counter[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------- body
@@ -162,8 +205,8 @@ __global__ void k_body_advance(DevPtrs p, int n_cases)
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cases) return;
     const CaseDev &cd = p.cases[c];
-    if (cd.M == 0) return;
     BodyDev &B = p.body[c];
+    if (cd.M == 0 || B.err != 0) return;
     const double kv = B.kappa * B.vol;
     const double a[3] = {B.F[0] / kv, B.F[1] / kv, B.F[2] / kv - B.gravity};
 #pragma unroll
@@ -200,6 +243,7 @@ __global__ void k_markers(DevPtrs p, int Mtot)
     if (k >= Mtot) return;
     const int c = p.mcase[k];
     const BodyDev &B = p.body[c];
+    if (B.err != 0) return;
     const double xb[3] = {p.xb[3 * k], p.xb[3 * k + 1], p.xb[3 * k + 2]};
     const double nb[3] = {p.nb[3 * k], p.nb[3 * k + 1], p.nb[3 * k + 2]};
     double X[3], N[3], rel[3], wr[3];
@@ -230,11 +274,11 @@ __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs 
 {
     const int c = blockIdx.y;
     const CaseDev &cd = p.cases[c];
-    if (cd.M == 0) return;
+    const BodyDev &B = p.body[c];
+    if (cd.M == 0 || B.err != 0) return;
     const int L = cd.L, L3 = L * L * L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= L3) return;
-    const BodyDev &B = p.body[c];
     float *R = p.reg + cd.reg_off * kRegFields;
     long long *H = p.H + cd.reg_off * 3;
     H[q] = 0;
@@ -321,6 +365,7 @@ __global__ void __launch_bounds__(256) k_interp_force(DevPtrs p, int Mtot)
     const int c = p.mcase[k];
     const CaseDev &cd = p.cases[c];
     const BodyDev &B = p.body[c];
+    if (B.err != 0) return;
     const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
     const Node nd = stencil_node(X, lane, cd, B);
     const int L3 = cd.L * cd.L * cd.L;
@@ -337,11 +382,18 @@ __global__ void __launch_bounds__(256) k_interp_force(DevPtrs p, int Mtot)
     const double nk[3] = {p.N[3 * k], p.N[3 * k + 1], p.N[3 * k + 2]};
     const double dS = p.dS[k];
     double s[3], rel[3], ts[3];
+    float *ft = p.feat + (long long)kMlpIn * k;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         s[a] = sg[a][0] * nk[0] + sg[a][1] * nk[1] + sg[a][2] * nk[2];
         rel[a] = X[a] - B.r[a];
         const double h0 = p.U[3 * k + a] - v[1 + a];
+        // warm-start features: I[u*], U, n and the previous step's final h
+        ft[a] = (float)(v[1 + a] * kFeatScale);
+        ft[3 + a] = (float)(p.U[3 * k + a] * kFeatScale);
+        ft[6 + a] = (float)nk[a];
+        ft[9 + a] = (float)(p.hk[3 * k + a] * kFeatScale);
+        p.h0[3 * k + a] = h0;
         p.hk[3 * k + a] = h0;
         p.dh[3 * k + a] = h0;
     }
@@ -361,7 +413,7 @@ __global__ void __launch_bounds__(256) k_reduce_ft(DevPtrs p)
     __shared__ double sh[kPart][256];
     const int c = blockIdx.x;
     const CaseDev &cd = p.cases[c];
-    if (cd.M == 0) return;
+    if (cd.M == 0 || p.body[c].err != 0) return;
     double acc[kPart];
 #pragma unroll
     for (int j = 0; j < kPart; j++) acc[j] = 0.0;
@@ -394,7 +446,7 @@ __global__ void __launch_bounds__(256) k_reduce_ft(DevPtrs p)
 // (order-independent, hence bitwise reproducible).  The first cycle spreads
 // h_k itself; later cycles spread the l = 4 increment, which by linearity of
 // the spreading yields the spread of the updated h_k.
-__global__ void __launch_bounds__(256) k_spread(DevPtrs p, int Mtot)
+__global__ void __launch_bounds__(256) k_spread(DevPtrs p, int Mtot, int only_fallback)
 {
     const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -402,6 +454,7 @@ __global__ void __launch_bounds__(256) k_spread(DevPtrs p, int Mtot)
     const int c = p.mcase[k];
     const CaseDev &cd = p.cases[c];
     const BodyDev &B = p.body[c];
+    if (B.err != 0 || (only_fallback && !B.fallback)) return;
     const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
     const Node nd = stencil_node(X, lane, cd, B);
     if (nd.q < 0) return;
@@ -420,7 +473,7 @@ __global__ void __launch_bounds__(256) k_spread(DevPtrs p, int Mtot)
 
 // l = 2..4: u3(X_k) = I[u* + H](X_k); e = U_k - u3; with update: h_k += e and
 // the next spread source is e.  The per-marker residual max |e| is kept.
-__global__ void __launch_bounds__(256) k_interp_update(DevPtrs p, int Mtot, int update)
+__global__ void __launch_bounds__(256) k_interp_update(DevPtrs p, int Mtot, int update, int only_fallback)
 {
     const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -428,6 +481,7 @@ __global__ void __launch_bounds__(256) k_interp_update(DevPtrs p, int Mtot, int 
     const int c = p.mcase[k];
     const CaseDev &cd = p.cases[c];
     const BodyDev &B = p.body[c];
+    if (B.err != 0 || (only_fallback && !B.fallback)) return;
     const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
     const Node nd = stencil_node(X, lane, cd, B);
     const int L3 = cd.L * cd.L * cd.L;
@@ -453,12 +507,13 @@ __global__ void __launch_bounds__(256) k_interp_update(DevPtrs p, int Mtot, int 
     p.res[k] = res;
 }
 
-__global__ void __launch_bounds__(256) k_reduce_resid(DevPtrs p)
+// Max residual over the markers of a case: into resid and resid_hist[slot].
+__global__ void __launch_bounds__(256) k_reduce_resid(DevPtrs p, int slot, int only_fallback)
 {
     __shared__ double sh[256];
     const int c = blockIdx.x;
     const CaseDev &cd = p.cases[c];
-    if (cd.M == 0) return;
+    if (cd.M == 0 || p.body[c].err != 0 || (only_fallback && !p.body[c].fallback)) return;
     double m = 0.0;
     for (int k = threadIdx.x; k < cd.M; k += blockDim.x) m = fmax(m, p.res[cd.marker_off + k]);
     sh[threadIdx.x] = m;
@@ -467,7 +522,78 @@ __global__ void __launch_bounds__(256) k_reduce_resid(DevPtrs p)
         if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) p.body[c].resid = sh[0];
+    if (threadIdx.x == 0) {
+        p.body[c].resid = sh[0];
+        if (slot >= 0 && slot < 16) p.body[c].resid_hist[slot] = sh[0];
+    }
+}
+
+// Gate of the learned start: a case whose residual after the learned-start
+// cycles exceeds its gate falls back to the plain start.
+__global__ void k_gate(DevPtrs p, int n_cases)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cases) return;
+    BodyDev &B = p.body[c];
+    if (p.cases[c].M == 0 || B.err != 0) return;
+    B.fallback = !(B.resid <= B.gate);
+    if (B.fallback) B.rejects += 1;
+    else B.accepts += 1;
+}
+
+// Warm start without a network: the previous step's final h_k (kept in the
+// features, scaled).
+__global__ void k_warm_previous(DevPtrs p, int Mtot)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Mtot || p.body[p.mcase[k]].err != 0) return;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double h = (double)p.feat[(long long)kMlpIn * k + 9 + a] / kFeatScale;
+        p.hk[3 * k + a] = h;
+        p.dh[3 * k + a] = h;
+    }
+}
+
+// Fallback preparation: plain start h_k = U_k - I[u*](X_k) ...
+__global__ void k_fallback_markers(DevPtrs p, int Mtot)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Mtot) return;
+    const BodyDev &B = p.body[p.mcase[k]];
+    if (B.err != 0 || !B.fallback) return;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        p.hk[3 * k + a] = p.h0[3 * k + a];
+        p.dh[3 * k + a] = p.h0[3 * k + a];
+    }
+}
+
+// ... and an empty immersed-force accumulator.
+__global__ void k_fallback_zero(DevPtrs p)
+{
+    const int c = blockIdx.y;
+    const CaseDev &cd = p.cases[c];
+    const BodyDev &B = p.body[c];
+    if (cd.M == 0 || B.err != 0 || !B.fallback) return;
+    const int L3 = cd.L * cd.L * cd.L;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= L3) return;
+    long long *H = p.H + cd.reg_off * 3;
+    H[q] = 0;
+    H[L3 + q] = 0;
+    H[2 * L3 + q] = 0;
+}
+
+// Training targets: what the cycles added to the plain start, scaled like
+// the features: (h_k - (U_k - I[u*](X_k))) * scale.
+__global__ void k_targets(DevPtrs p, int Mtot, float *out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Mtot) return;
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+        out[3 * k + a] = (float)((p.hk[3 * k + a] - p.h0[3 * k + a]) * kFeatScale);
 }
 
 // Forced collision of Sec. 2.2: the lattice kernel wrote
@@ -478,11 +604,11 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
 {
     const int c = blockIdx.y;
     const CaseDev &cd = p.cases[c];
-    if (cd.M == 0) return;
+    const BodyDev &B = p.body[c];
+    if (cd.M == 0 || B.err != 0) return;
     const int L = cd.L, L3 = L * L * L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= L3) return;
-    const BodyDev &B = p.body[c];
     const int a = q % L, b = (q / L) % L, cc = q / (L * L);
     const int gz = B.org[2] + cc;
     if (gz < 0 || gz >= cd.nz) return;
@@ -521,7 +647,7 @@ __global__ void k_window_trigger(DevPtrs p, int n_cases)
     const CaseDev &cd = p.cases[c];
     BodyDev &B = p.body[c];
     B.shift_now = 0;
-    if (cd.M == 0 || cd.dz <= 0 || !(cd.h_end > 0.0) || !(B.r[2] < cd.h_end)) return;
+    if (cd.M == 0 || B.err != 0 || cd.dz <= 0 || !(cd.h_end > 0.0) || !(B.r[2] < cd.h_end)) return;
     B.r[2] += (double)cd.dz;
     B.z0 = wrapi(B.z0 - cd.dz, cd.nz);
     B.shift_now = 1;
@@ -574,9 +700,27 @@ static hipError_t stream_collide_impl(const void *src, void *dst, const DevPtrs 
     using T = typename CD::T;
     int grid = ntiles;
     if (schedule == 1) grid = (ntiles + 7) / 8 * 8;
-    if (schedule == 2) grid = persist_wgs > 0 ? persist_wgs : 2048;
-    hipLaunchKernelGGL(k_stream_collide<CD>, dim3(grid), dim3(block), 0, s, (const T *)src, (T *)dst, p.cases,
-                       p.body, p.tiles, ntiles, schedule);
+    if (schedule >= 2) grid = persist_wgs > 0 ? persist_wgs : 2048;
+    const T *a = (const T *)src;
+    T *b = (T *)dst;
+    switch (schedule) {
+    case 1:
+        hipLaunchKernelGGL((k_stream_collide<CD, 1>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
+                           ntiles, p.counter);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_stream_collide<CD, 2>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
+                           ntiles, p.counter);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, p.counter);
+        hipLaunchKernelGGL((k_stream_collide<CD, 3>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
+                           ntiles, p.counter);
+        break;
+    default:
+        hipLaunchKernelGGL((k_stream_collide<CD, 0>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
+                           ntiles, p.counter);
+    }
     return hipGetLastError();
 }
 
@@ -598,34 +742,65 @@ hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s)
 
 template <class CD>
 static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3,
-                           int cycles, hipStream_t s)
+                           int cycles, int warm_mode, const _Float16 *th16, int warm_cycles, int diag, hipStream_t s)
 {
     using T = typename CD::T;
     const dim3 blk(256);
     const dim3 reg_grid((maxL3 + 255) / 256, n_cases);
     const dim3 wave_grid((Mtot + 3) / 4);
-    hipLaunchKernelGGL(k_markers, dim3((Mtot + 255) / 256), blk, 0, s, p, Mtot);
+    const dim3 mark_grid((Mtot + 255) / 256);
+    hipLaunchKernelGGL(k_markers, mark_grid, blk, 0, s, p, Mtot);
     hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
     hipLaunchKernelGGL(k_interp_force, wave_grid, blk, 0, s, p, Mtot);
     hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), blk, 0, s, p);
-    for (int cyc = 1; cyc <= cycles; cyc++) {
-        hipLaunchKernelGGL(k_spread, wave_grid, blk, 0, s, p, Mtot);
-        hipLaunchKernelGGL(k_interp_update, wave_grid, blk, 0, s, p, Mtot, cyc < cycles ? 1 : 0);
+    // one sequence of multi-direct forcing cycles (Sec. 2.2, l = 1..4): spread,
+    // then interpolate and update, except after the last spread
+    auto sequence = [&](int ncyc, int slot0, int only_fallback) {
+        for (int cyc = 1; cyc <= ncyc; cyc++) {
+            hipLaunchKernelGGL(k_spread, wave_grid, blk, 0, s, p, Mtot, only_fallback);
+            hipLaunchKernelGGL(k_interp_update, wave_grid, blk, 0, s, p, Mtot, cyc < ncyc ? 1 : 0, only_fallback);
+            if (diag || cyc == ncyc)
+                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p, slot0 + cyc - 1, only_fallback);
+        }
+    };
+    if (warm_mode != 0) {
+        if (warm_mode == 2) {
+            hipError_t e = launch_mlp_warm_start(th16, p, Mtot, s);   // the network lives in mlp.hip
+            if (e != hipSuccess) return e;
+        } else {
+            hipLaunchKernelGGL(k_warm_previous, mark_grid, blk, 0, s, p, Mtot);
+        }
+        sequence(warm_cycles, 0, 0);
+        hipLaunchKernelGGL(k_gate, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
+        hipLaunchKernelGGL(k_fallback_markers, mark_grid, blk, 0, s, p, Mtot);
+        hipLaunchKernelGGL(k_fallback_zero, reg_grid, blk, 0, s, p);
+        sequence(cycles, 8, 1);
+    } else {
+        sequence(cycles, 0, 0);
     }
-    hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p);
     hipLaunchKernelGGL(k_correct<CD>, reg_grid, blk, 0, s, (T *)cur, p);
     return hipGetLastError();
 }
 
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
-                      int maxL3, int cycles, hipStream_t s)
+                      int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles, int diag,
+                      hipStream_t s)
 {
     if (Mtot == 0) return hipSuccess;
     switch (storage) {
-    case ST_F16: return ibm_impl<CodecF16>(prev, cur, p, n_cases, Mtot, maxL3, cycles, s);
-    case ST_BF16: return ibm_impl<CodecBF16>(prev, cur, p, n_cases, Mtot, maxL3, cycles, s);
-    default: return ibm_impl<CodecF32>(prev, cur, p, n_cases, Mtot, maxL3, cycles, s);
+    case ST_F16:
+        return ibm_impl<CodecF16>(prev, cur, p, n_cases, Mtot, maxL3, cycles, warm_mode, th16, warm_cycles, diag, s);
+    case ST_BF16:
+        return ibm_impl<CodecBF16>(prev, cur, p, n_cases, Mtot, maxL3, cycles, warm_mode, th16, warm_cycles, diag, s);
+    default:
+        return ibm_impl<CodecF32>(prev, cur, p, n_cases, Mtot, maxL3, cycles, warm_mode, th16, warm_cycles, diag, s);
     }
+}
+
+hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_targets, dim3((Mtot + 255) / 256), dim3(256), 0, s, p, Mtot, out);
+    return hipGetLastError();
 }
 
 template <class CD>

@@ -1,0 +1,283 @@
+// mlp.hip -- the warm-start network of the learned IBM form: a
+// 12 -> 64 -> 64 -> 3 multilayer perceptron with SiLU hidden activations,
+// FP16 weights and FP32 accumulation; inference for every marker, and
+// training (per-sample forward/backward, deterministic weight-gradient sums,
+// Adam) on samples the solver produced.
+//
+// Parameter layout (flat): W1[64][12] b1[64] W2[64][64] b2[64] W3[3][64] b3[3].
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "mlp.hpp"
+
+namespace turret {
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+// Weights: FP16 in HBM, widened once per workgroup into LDS.
+__device__ __forceinline__ void load_weights(const _Float16 *__restrict__ th16, float *w)
+{
+    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) w[i] = (float)th16[i];
+    __syncthreads();
+}
+
+// Forward pass of one sample; optionally keeps a1, a2, silu'(z1), silu'(z2).
+__device__ __forceinline__ void mlp_forward_one(const float *w, const float x[kMlpIn], float y[kMlpOut],
+                                                float *a1o, float *a2o, float *d1o, float *d2o, int stride)
+{
+    const float *W1 = w + kOffW1, *b1 = w + kOffB1, *W2 = w + kOffW2, *b2 = w + kOffB2, *W3 = w + kOffW3,
+                *b3 = w + kOffB3;
+    float a1[kMlpH];
+#pragma unroll
+    for (int o = 0; o < kMlpH; o++) {
+        float z = b1[o];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; i++) z = fmaf(W1[o * kMlpIn + i], x[i], z);
+        const float s = sigmoidf(z);
+        a1[o] = z * s;
+        if (a1o) {
+            a1o[o * stride] = a1[o];
+            d1o[o * stride] = s + z * s * (1.0f - s);
+        }
+    }
+    float y0 = b3[0], y1 = b3[1], y2 = b3[2];
+    for (int o = 0; o < kMlpH; o++) {
+        float z = b2[o];
+#pragma unroll
+        for (int i = 0; i < kMlpH; i++) z = fmaf(W2[o * kMlpH + i], a1[i], z);
+        const float s = sigmoidf(z);
+        const float a = z * s;
+        if (a2o) {
+            a2o[o * stride] = a;
+            d2o[o * stride] = s + z * s * (1.0f - s);
+        }
+        y0 = fmaf(W3[o], a, y0);
+        y1 = fmaf(W3[kMlpH + o], a, y1);
+        y2 = fmaf(W3[2 * kMlpH + o], a, y2);
+    }
+    y[0] = y0;
+    y[1] = y1;
+    y[2] = y2;
+}
+
+// Inference on caller arrays: X (n x 12) -> Y (n x 3).
+__global__ void __launch_bounds__(256) k_mlp_forward(const _Float16 *__restrict__ th16, const float *__restrict__ X,
+                                                     int n, float *__restrict__ Y)
+{
+    __shared__ float w[kMlpParams];
+    load_weights(th16, w);
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    float x[kMlpIn], y[kMlpOut];
+#pragma unroll
+    for (int i = 0; i < kMlpIn; i++) x[i] = X[(long long)s * kMlpIn + i];
+    mlp_forward_one(w, x, y, nullptr, nullptr, nullptr, nullptr, 0);
+#pragma unroll
+    for (int j = 0; j < kMlpOut; j++) Y[(long long)s * kMlpOut + j] = y[j];
+}
+
+// Warm start inside the IBM coupling: the network predicts the correction the
+// multi-direct forcing cycles add to the plain start, h_k = U_k - I[u*](X_k)
+// + MLP(features_k) / scale (U and I[u*] are features 3..5 and 0..2), for
+// every marker of an unmasked case; the first spread then spreads it.
+__global__ void __launch_bounds__(256) k_mlp_warm_start(const _Float16 *__restrict__ th16, DevPtrs p, int Mtot)
+{
+    __shared__ float w[kMlpParams];
+    load_weights(th16, w);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Mtot || p.body[p.mcase[k]].err != 0) return;
+    float x[kMlpIn], y[kMlpOut];
+#pragma unroll
+    for (int i = 0; i < kMlpIn; i++) x[i] = p.feat[(long long)k * kMlpIn + i];
+    mlp_forward_one(w, x, y, nullptr, nullptr, nullptr, nullptr, 0);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double h = (double)(x[3 + a] - x[a] + y[a]) / kFeatScale;
+        p.hk[3 * k + a] = h;
+        p.dh[3 * k + a] = h;
+    }
+}
+
+// Training, pass 1: forward of every sample, keeping the activations and
+// SiLU derivatives (scratch, layout [field][sample]), dY = (Y - T)/N and the
+// per-block loss partial 1/(2N) sum |Y - T|^2.
+__global__ void __launch_bounds__(256) k_mlp_fwd_train(const _Float16 *__restrict__ th16, const float *__restrict__ X,
+                                                       const float *__restrict__ Tg, int n, MlpScratch sc)
+{
+    __shared__ float w[kMlpParams];
+    __shared__ float red[256];
+    load_weights(th16, w);
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.0f;
+    if (s < n) {
+        float x[kMlpIn], y[kMlpOut];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; i++) x[i] = X[(long long)s * kMlpIn + i];
+        mlp_forward_one(w, x, y, sc.a1 + s, sc.a2 + s, sc.d1 + s, sc.d2 + s, n);
+#pragma unroll
+        for (int j = 0; j < kMlpOut; j++) {
+            const float e = y[j] - Tg[(long long)s * kMlpOut + j];
+            sc.dy[j * n + s] = e / (float)n;
+            l += e * e;
+        }
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc.loss_part[blockIdx.x] = red[0] * 0.5f / (float)n;
+}
+
+// Training, pass 2: back-propagate dY to dz2 = (W3^T dY) silu'(z2) and
+// dz1 = (W2^T dz2) silu'(z1) per sample.
+__global__ void __launch_bounds__(256) k_mlp_bwd_train(const _Float16 *__restrict__ th16, int n, MlpScratch sc)
+{
+    __shared__ float w[kMlpParams];
+    load_weights(th16, w);
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const float *W2 = w + kOffW2, *W3 = w + kOffW3;
+    const float dy0 = sc.dy[s], dy1 = sc.dy[n + s], dy2 = sc.dy[2 * n + s];
+    float dz2[kMlpH];
+#pragma unroll
+    for (int o = 0; o < kMlpH; o++) {
+        const float g = W3[o] * dy0 + W3[kMlpH + o] * dy1 + W3[2 * kMlpH + o] * dy2;
+        dz2[o] = g * sc.d2[o * n + s];
+        sc.dz2[o * n + s] = dz2[o];
+    }
+    for (int i = 0; i < kMlpH; i++) {
+        float g = 0.0f;
+#pragma unroll
+        for (int o = 0; o < kMlpH; o++) g = fmaf(W2[o * kMlpH + i], dz2[o], g);
+        sc.dz1[i * n + s] = g * sc.d1[i * n + s];
+    }
+}
+
+// Training, pass 3: weight gradients as sums over samples of outer products,
+// one thread per parameter per slice of samples (partial[slice][param]); the
+// sums over slices are taken in a fixed order by k_mlp_reduce, so the
+// gradient is bitwise reproducible.
+__global__ void __launch_bounds__(256) k_mlp_wgrad(const float *__restrict__ X, int n, int slice, MlpScratch sc)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlpParams) return;
+    const int s0 = blockIdx.y * slice, s1 = min(n, s0 + slice);
+    const float *u = nullptr, *v = nullptr;   // gradient = sum_s u[s] * v[s]
+    int vstride = 0;
+    const float *vX = nullptr;
+    int xi = 0;
+    if (p < kOffB1) {                 // W1[o][i] = sum dz1[o] x[i]
+        const int o = p / kMlpIn;
+        xi = p - o * kMlpIn;
+        u = sc.dz1 + (long long)o * n;
+        vX = X;
+    } else if (p < kOffW2) {          // b1[o] = sum dz1[o]
+        u = sc.dz1 + (long long)(p - kOffB1) * n;
+    } else if (p < kOffB2) {          // W2[o][i] = sum dz2[o] a1[i]
+        const int q = p - kOffW2, o = q / kMlpH, i = q - o * kMlpH;
+        u = sc.dz2 + (long long)o * n;
+        v = sc.a1 + (long long)i * n;
+        vstride = 1;
+    } else if (p < kOffW3) {          // b2[o] = sum dz2[o]
+        u = sc.dz2 + (long long)(p - kOffB2) * n;
+    } else if (p < kOffB3) {          // W3[j][i] = sum dy[j] a2[i]
+        const int q = p - kOffW3, j = q / kMlpH, i = q - j * kMlpH;
+        u = sc.dy + (long long)j * n;
+        v = sc.a2 + (long long)i * n;
+        vstride = 1;
+    } else {                          // b3[j] = sum dy[j]
+        u = sc.dy + (long long)(p - kOffB3) * n;
+    }
+    float acc = 0.0f;
+    if (vX) {
+        for (int s = s0; s < s1; s++) acc = fmaf(u[s], vX[(long long)s * kMlpIn + xi], acc);
+    } else if (vstride) {
+        for (int s = s0; s < s1; s++) acc = fmaf(u[s], v[s], acc);
+    } else {
+        for (int s = s0; s < s1; s++) acc += u[s];
+    }
+    sc.part[(long long)blockIdx.y * kMlpParams + p] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_reduce(int nslices, int nloss, MlpScratch sc, float *__restrict__ grad,
+                                                    float *__restrict__ loss)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kMlpParams) {
+        float g = 0.0f;
+        for (int k = 0; k < nslices; k++) g += sc.part[(long long)k * kMlpParams + p];
+        grad[p] = g;
+    }
+    if (p == 0 && loss) {
+        float l = 0.0f;
+        for (int k = 0; k < nloss; k++) l += sc.loss_part[k];
+        *loss = l;
+    }
+}
+
+// Adam (Kingma & Ba): FP32 master weights and moments; the FP16 copy used by
+// the forward passes is refreshed (round to nearest even).
+__global__ void __launch_bounds__(256) k_mlp_adam(float *__restrict__ th32, _Float16 *__restrict__ th16,
+                                                  float *__restrict__ m, float *__restrict__ v,
+                                                  const float *__restrict__ g, float lr, float c1, float c2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlpParams) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float mm = b1 * m[p] + (1.0f - b1) * g[p];
+    const float vv = b2 * v[p] + (1.0f - b2) * g[p] * g[p];
+    m[p] = mm;
+    v[p] = vv;
+    const float t = th32[p] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    th32[p] = t;
+    th16[p] = (_Float16)t;
+}
+
+__global__ void k_mlp_round(const float *__restrict__ th32, _Float16 *__restrict__ th16)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kMlpParams) th16[p] = (_Float16)th32[p];
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_mlp_forward(const _Float16 *th16, const float *X, int n, float *Y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_forward, dim3((n + 255) / 256), dim3(256), 0, s, th16, X, n, Y);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_warm_start(const _Float16 *th16, const DevPtrs &p, int Mtot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_warm_start, dim3((Mtot + 255) / 256), dim3(256), 0, s, th16, p, Mtot);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const _Float16 *th16, const float *X, const float *Tg, int n, const MlpScratch &sc,
+                           float *grad, float *loss, hipStream_t s)
+{
+    const int nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_mlp_fwd_train, dim3(nb), dim3(256), 0, s, th16, X, Tg, n, sc);
+    hipLaunchKernelGGL(k_mlp_bwd_train, dim3(nb), dim3(256), 0, s, th16, n, sc);
+    const int slices = (n + kMlpSlice - 1) / kMlpSlice;
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3((kMlpParams + 255) / 256, slices), dim3(256), 0, s, X, n, kMlpSlice, sc);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, slices, nb, sc, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *th32, _Float16 *th16, float *m, float *v, const float *g, float lr, int step,
+                           hipStream_t s)
+{
+    const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, th32, th16, m, v, g, lr, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_round(const float *th32, _Float16 *th16, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_round, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, th32, th16);
+    return hipGetLastError();
+}
+
+}  // namespace turret

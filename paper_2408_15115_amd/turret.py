@@ -18,6 +18,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "turret.h")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
+LBM_WARM_NONE, LBM_WARM_PREVIOUS, LBM_WARM_MLP = 0, 1, 2
+MLP_PARAMS = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
 STORAGE = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
 ELEM_BYTES = {LBM_F32: 4, LBM_F16: 2, LBM_BF16: 2}
 ERRNAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE", -5: "LBM_ESTATE"}
@@ -38,7 +40,8 @@ class lbm_body(C.Structure):
 
 class lbm_options(C.Structure):
     _fields_ = [("storage", C.c_int32), ("ibm_cycles", C.c_int32), ("block", C.c_int32),
-                ("schedule", C.c_int32), ("persist_wgs", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("schedule", C.c_int32), ("persist_wgs", C.c_int32), ("tile_order", C.c_int32),
+                ("ibm_diag", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lbm_buffers(C.Structure):
@@ -60,6 +63,7 @@ _sig = {
     "ibm_couple": (C.c_int32, [_ctx]),
     "window_shift": (C.c_int32, [_ctx]),
     "lbm_run": (C.c_int32, [_ctx, C.c_int32]),
+    "lbm_set_schedule": (C.c_int32, [_ctx, _P(lbm_options)]),
     "lbm_graph_capture": (C.c_int32, [_ctx, C.c_int32]),
     "lbm_graph_launch": (C.c_int32, [_ctx]),
     "lbm_get_populations": (C.c_int32, [_ctx, C.c_int32, _P(C.c_double)]),
@@ -70,6 +74,20 @@ _sig = {
     "lbm_pop_offset": (C.c_int64, [_ctx, C.c_int32]),
     "lbm_current_buffer": (C.c_void_p, [_ctx]),
     "lbm_stream_copy": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "mlp_required_bytes": (C.c_int32, [C.c_int32, _P(C.c_int64)]),
+    "mlp_create": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, _P(C.c_void_p)]),
+    "mlp_set_params": (C.c_int32, [C.c_void_p, _P(C.c_float)]),
+    "mlp_get_params": (C.c_int32, [C.c_void_p, _P(C.c_float)]),
+    "mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "mlp_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "mlp_train_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_void_p]),
+    "mlp_destroy": (C.c_int32, [C.c_void_p]),
+    "mlp_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_set_warm_start": (C.c_int32, [_ctx, C.c_int32, C.c_void_p, C.c_int32]),
+    "lbm_set_ibm_gate": (C.c_int32, [_ctx, C.c_int32, C.c_double]),
+    "lbm_ibm_samples": (C.c_int32, [_ctx, C.c_void_p, C.c_void_p]),
+    "lbm_marker_count": (C.c_int32, [_ctx]),
+    "lbm_ibm_stats": (C.c_int32, [_ctx, C.c_int32, _P(C.c_double)]),
     "lbm_destroy": (C.c_int32, [_ctx]),
     "lbm_last_error": (C.c_char_p, [_ctx]),
 }
@@ -119,10 +137,12 @@ def make_body(d: dict | None, keep: list) -> lbm_body:
     return b
 
 
-def make_options(storage="f32", ibm_cycles=4, block=256, schedule=0, persist_wgs=0) -> lbm_options:
+def make_options(storage="f32", ibm_cycles=4, block=256, schedule=0, persist_wgs=0, tile_order=0,
+                 ibm_diag=0) -> lbm_options:
     o = lbm_options()
     o.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     o.ibm_cycles, o.block, o.schedule, o.persist_wgs = int(ibm_cycles), int(block), int(schedule), int(persist_wgs)
+    o.tile_order, o.ibm_diag = int(tile_order), int(ibm_diag)
     return o
 
 
@@ -153,7 +173,7 @@ class Solver:
     only).  ``cases``/``bodies`` are lists of the workload dicts."""
 
     def __init__(self, cases, bodies=None, storage="f32", ibm_cycles=4, block=256, schedule=0,
-                 persist_wgs=0, stream=None, device="cuda"):
+                 persist_wgs=0, tile_order=0, ibm_diag=0, stream=None, device="cuda"):
         import torch
 
         self.torch = torch
@@ -162,7 +182,7 @@ class Solver:
         self._cases = (lbm_case * self.n)(*[make_case(c) for c in cases])
         self._bodies = ((lbm_body * self.n)(*[make_body(b, self._keep) for b in bodies])
                         if bodies is not None else None)
-        self._opt = make_options(storage, ibm_cycles, block, schedule, persist_wgs)
+        self._opt = make_options(storage, ibm_cycles, block, schedule, persist_wgs, tile_order, ibm_diag)
         self.dims = [(int(c["nx"]), int(c["ny"]), int(c["nz"])) for c in cases]
         sizes = (C.c_int64 * 3)()
         rc = lbm_required_bytes(self._cases, self._bodies, self.n, C.byref(self._opt), sizes)
@@ -198,6 +218,12 @@ class Solver:
     def run(self, nsteps=1):
         self._chk("lbm_run", lbm_run(self._ctx, int(nsteps)))
 
+    def set_schedule(self, block=256, schedule=0, persist_wgs=0, tile_order=0):
+        o = make_options(self._opt.storage, self._opt.ibm_cycles, block, schedule, persist_wgs, tile_order,
+                         self._opt.ibm_diag)
+        self._chk("lbm_set_schedule", lbm_set_schedule(self._ctx, C.byref(o)))
+        self._opt = o
+
     def graph_capture(self, steps=2):
         self._chk("lbm_graph_capture", lbm_graph_capture(self._ctx, int(steps)))
 
@@ -226,6 +252,31 @@ class Solver:
                 "F_pressure": o[24:27].copy(), "ibm_residual": o[27], "steps": int(o[28]),
                 "shifts": int(o[29]), "z0": int(o[30]), "err": int(o[31])}
 
+    # --- learned warm start
+    def set_warm_start(self, mode, mlp=None, cycles=4):
+        mp = C.c_void_p(mlp._m.value) if mlp is not None else None
+        self._chk("lbm_set_warm_start", lbm_set_warm_start(self._ctx, int(mode), mp, int(cycles)))
+
+    def set_ibm_gate(self, case, threshold):
+        self._chk("lbm_set_ibm_gate", lbm_set_ibm_gate(self._ctx, int(case), float(threshold)))
+
+    def marker_count(self):
+        return int(lbm_marker_count(self._ctx))
+
+    def ibm_samples(self):
+        """(features, targets) of the last ibm_couple as new device tensors."""
+        M = self.marker_count()
+        f = self.torch.empty((M, 12), dtype=self.torch.float32, device="cuda")
+        t = self.torch.empty((M, 3), dtype=self.torch.float32, device="cuda")
+        self._chk("lbm_ibm_samples", lbm_ibm_samples(self._ctx, C.c_void_p(f.data_ptr()), C.c_void_p(t.data_ptr())))
+        return f, t
+
+    def ibm_stats(self, case=0):
+        o = np.zeros(20)
+        self._chk("lbm_ibm_stats", lbm_ibm_stats(self._ctx, case, _dptr(o)))
+        return {"resid": o[0], "resid_hist": o[1:9].copy(), "resid_hist_fallback": o[9:17].copy(),
+                "accepts": int(o[17]), "rejects": int(o[18]), "fallback": int(o[19])}
+
     def save(self, path):
         self._chk("lbm_save", lbm_save(self._ctx, str(path).encode()))
 
@@ -242,6 +293,83 @@ class Solver:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             lbm_destroy(self._ctx)
             self._ctx = _ctx()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlp_init_params(seed):
+    """He-uniform weights (bound sqrt(6 / fan_in)) and zero biases, FP32, in
+    the library's flat layout."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((12, 64), (64, 64), (64, 3)):
+        b = np.sqrt(6.0 / fan_in)
+        parts += [rng.uniform(-b, b, size=fan_out * fan_in), np.zeros(fan_out)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+class MLP:
+    """The warm-start network object over a torch device buffer (marshalling
+    only; all arithmetic runs in the library's kernels)."""
+
+    def __init__(self, max_batch=65536, params=None, seed=0, stream=None):
+        import torch
+
+        self.torch = torch
+        self.max_batch = int(max_batch)
+        nb = C.c_int64()
+        if mlp_required_bytes(self.max_batch, C.byref(nb)):
+            raise TurretError("mlp_required_bytes", LBM_EINVAL, mlp_last_error(None).decode())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.buf = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        self._m = C.c_void_p()
+        rc = mlp_create(C.c_void_p(self.buf.data_ptr()), nb.value, self.max_batch,
+                        C.c_void_p(self.stream.cuda_stream), C.byref(self._m))
+        if rc:
+            raise TurretError("mlp_create", rc, mlp_last_error(None).decode())
+        self.set_params(mlp_init_params(seed) if params is None else params)
+
+    def _chk(self, where, rc):
+        if rc:
+            raise TurretError(where, rc, mlp_last_error(self._m).decode())
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(params, np.float32)
+        assert a.size == MLP_PARAMS
+        self._chk("mlp_set_params", mlp_set_params(self._m, a.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def params(self):
+        a = np.empty(MLP_PARAMS, np.float32)
+        self._chk("mlp_get_params", mlp_get_params(self._m, a.ctypes.data_as(C.POINTER(C.c_float))))
+        return a
+
+    def forward(self, X):
+        X = X.contiguous()
+        Y = self.torch.empty((X.shape[0], 3), dtype=self.torch.float32, device="cuda")
+        self._chk("mlp_forward", mlp_forward(self._m, C.c_void_p(X.data_ptr()), X.shape[0], C.c_void_p(Y.data_ptr())))
+        return Y
+
+    def grad(self, X, Tg):
+        X, Tg = X.contiguous(), Tg.contiguous()
+        g = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device="cuda")
+        loss = self.torch.empty(1, dtype=self.torch.float32, device="cuda")
+        self._chk("mlp_grad", mlp_grad(self._m, C.c_void_p(X.data_ptr()), C.c_void_p(Tg.data_ptr()), X.shape[0],
+                                       C.c_void_p(g.data_ptr()), C.c_void_p(loss.data_ptr())))
+        return g, loss
+
+    def train_step(self, X, Tg, lr=1e-3, loss=None):
+        lp = C.c_void_p(loss.data_ptr()) if loss is not None else None
+        self._chk("mlp_train_step", mlp_train_step(self._m, C.c_void_p(X.data_ptr()), C.c_void_p(Tg.data_ptr()),
+                                                   X.shape[0], float(lr), lp))
+
+    def close(self):
+        if getattr(self, "_m", None) is not None and self._m.value:
+            mlp_destroy(self._m)
+            self._m = C.c_void_p()
 
     def __del__(self):
         try:

@@ -285,9 +285,15 @@ def batch_cases(n_cases=64, seed0=2408, max_h=384):
             vol, _, _ = mesh_mass_properties(V, F)
             scale = D / 2.0 / (3.0 * vol / (4.0 * math.pi)) ** (1.0 / 3.0)
             body = mesh_body(V * scale, F, kappa, r0)
+        # keep the marker stencils two cells inside the walls: start at most
+        # 0.75 h high and re-inject 32 rows lower, or above R_b + 4
+        rb = float(np.linalg.norm(body["x_body"], axis=1).max())
+        z_start = min(z0, h - rb - 4.0)
+        z_end = max(z_start - 32.0, rb + 4.0)
+        body["r0"] = np.array([body["r0"][0], body["r0"][1], z_start])
         nu, tau, g = lattice_scaling(D, re, kappa)
         case = make_case(w, w, h, tau, BC_FREESLIP, BC_FREESLIP, int(round(0.08 * h)), g,
-                         h_ini=z0, h_end=z0 - 32.0)
+                         h_ini=z_start, h_end=z_end if z_start - z_end >= 1.0 else 0.0)
         case["re"], case["d_eq"], case["shape"] = re, D, ("sphere", "spheroid", "irregular")[shape]
         out.append((case, body))
     return out
