@@ -144,6 +144,79 @@ def batch_run(T, W, torch, steps, storage):
             "schedule_cached": tuned["cached"], "masked_cases": int(sum(1 for e in errs if e))}
 
 
+def learned_run(T, W, torch, storage, steps=100, train_iters=1500):
+    """The learned form on the 64-case batch: a plain run from rest gives
+    samples and reference drags; the network is trained on them by the
+    library's kernels; a second run from rest starts every multi-direct
+    forcing from the network with one cycle, gated per case against the plain
+    four-cycle residual (fallback to the plain cycles)."""
+    import numpy as np
+    from paper_2408_15115_amd import autotune, learn
+    batch = W.batch_cases(64)
+    cases = [c for c, _ in batch]
+    bodies = [b for _, b in batch]
+    sched = autotune.tune(cases, storage=storage)["best"]
+    nc = len(cases)
+
+    def ibm_timed(S, collect):
+        st = S.stream
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        X, Y, r4 = [], [], []
+        for k in range(steps):
+            S.body_advance()
+            S.lbm_step()
+            ev[k][0].record(st)
+            S.ibm_couple()
+            ev[k][1].record(st)
+            S.window_shift()
+            if collect and k >= 10 and k % 3 == 0:
+                f, t = S.ibm_samples()
+                sel = torch.arange(0, f.shape[0], 2, device="cuda")
+                X.append(f[sel].cpu().numpy())
+                Y.append(t[sel].cpu().numpy())
+                r4.append([S.ibm_stats(c)["resid_hist"][3] for c in range(nc)])
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(b) for a, b in ev[5:]]
+        stats = [S.ibm_stats(c) for c in range(nc)]
+        Fz = np.array([S.body_state(c, check=False)["F"][2] for c in range(nc)])
+        errs = np.array([S.body_state(c, check=False)["err"] for c in range(nc)])
+        return sum(ms) / len(ms), X, Y, stats, Fz, errs, np.array(r4)
+
+    S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), ibm_diag=1, **sched)
+    plain_ms, X, Y, pstats, Fz_plain, perr, r4 = ibm_timed(S, True)
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    X, Y = np.concatenate(X), np.concatenate(Y)
+    net = T.MLP(max_batch=8192, seed=0)
+    t0 = time.perf_counter()
+    loss = learn.fit(net, X, Y, iters=train_iters)
+    train_s = time.perf_counter() - t0
+    S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), ibm_diag=1, **sched)
+    S.set_warm_start(T.LBM_WARM_MLP, net, 1)
+    # gate: the largest four-cycle residual of the plain run for that case
+    gates = np.nan_to_num(r4.max(0), nan=1e-6)
+    for c in range(nc):
+        S.set_ibm_gate(c, float(gates[c]) if gates[c] > 0 else 1e-6)
+    mlp_ms, _, _, mstats, Fz_mlp, merr, _ = ibm_timed(S, False)
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    ok = (perr == 0) & (merr == 0)
+    acc = sum(st["accepts"] for st in mstats)
+    rej = sum(st["rejects"] for st in mstats)
+    dev = np.abs(Fz_mlp[ok] - Fz_plain[ok]) / np.abs(Fz_plain[ok])
+    return {"cases": nc, "steps": steps, "train_samples": int(X.shape[0]), "train_iters": train_iters,
+            "train_seconds": round(train_s, 2), "train_loss_standardized": loss,
+            "ibm_ms_per_step_plain_4cycles": round(plain_ms, 4), "ibm_ms_per_step_learned_1cycle_gated": round(mlp_ms, 4),
+            "accepted": int(acc), "rejected": int(rej), "acceptance": round(acc / max(1, acc + rej), 4),
+            "plain_resid_after_1_4_cycles_median": [float(np.median([st["resid_hist"][k] for st in pstats]))
+                                                    for k in (0, 3)],
+            "drag_rel_dev_vs_plain_median": float(np.median(dev)) if dev.size else None,
+            "drag_rel_dev_vs_plain_max": float(dev.max()) if dev.size else None,
+            "masked_cases": int((~ok).sum())}
+
+
 def cpu_baseline(case, body, steps):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the
     same body, relaxation time and walls in a 128^3 window."""
@@ -177,6 +250,7 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -239,6 +313,12 @@ def main():
         variants["batch64"] = b
         log(f"  batch: {b['mlups']:.0f} MLUPS, {b['ms_per_step']:.2f} ms/step, kernel {b['k1_gbps']:.0f} GB/s, "
             f"masked {b['masked_cases']}")
+
+    if not args.no_learned:
+        lr = learned_run(T, W, torch, args.storage)
+        variants["learned_batch64"] = lr
+        log(f"  learned: IBM {lr['ibm_ms_per_step_plain_4cycles']:.3f} -> {lr['ibm_ms_per_step_learned_1cycle_gated']:.3f}"
+            f" ms/step, acceptance {lr['acceptance']:.2f}, drag dev median {lr['drag_rel_dev_vs_plain_median']}")
 
     cpu = None
     if not args.no_cpu_baseline:
