@@ -245,6 +245,7 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=400)
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
@@ -294,7 +295,7 @@ def main():
         f"{main_run['k1_ms']:.3f} ms = {main_run['k1_gbps']:.0f} GB/s")
 
     variants = {}
-    if not args.no_variants:
+    if not args.no_variants and not args.no_precision:
         ref = run_storage("f32", args.variant_steps, 5, False)
         for sto in ("f16", "bf16"):
             r = run_storage(sto, args.variant_steps, 5, False)
@@ -308,13 +309,13 @@ def main():
                 f"{variants[sto]['drag_rel_diff_vs_f32']:.2e}")
         variants["f32_same_steps"] = {"mlups": round(ref["mlups"], 1), "k1_gbps": round(ref["k1_gbps"], 1)}
 
-    if not args.no_batch:
+    if not args.no_variants and not args.no_batch:
         b = batch_run(T, W, torch, args.batch_steps, args.storage)
         variants["batch64"] = b
         log(f"  batch: {b['mlups']:.0f} MLUPS, {b['ms_per_step']:.2f} ms/step, kernel {b['k1_gbps']:.0f} GB/s, "
             f"masked {b['masked_cases']}")
 
-    if not args.no_learned:
+    if not args.no_variants and not args.no_learned:
         lr = learned_run(T, W, torch, args.storage)
         variants["learned_batch64"] = lr
         log(f"  learned: IBM {lr['ibm_ms_per_step_plain_4cycles']:.3f} -> {lr['ibm_ms_per_step_learned_1cycle_gated']:.3f}"

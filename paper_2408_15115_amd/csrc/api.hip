@@ -27,11 +27,13 @@ int elem_bytes(int storage) { return storage == LBM_F32 ? 4 : 2; }
 struct Plan {
     std::vector<CaseDev> cd;
     std::vector<Tile> tiles;
+    std::vector<int> morder;          // internal marker slot -> index in the caller's marker array
+    std::vector<MarkerTile> mtiles;
     long long max_tiles = 0;    // tile table capacity: the count at the smallest block (64)
     int Mtot = 0, maxL3 = 0, max_slab = 0;
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
-        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, aux_bytes;
+        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_mtiles, aux_bytes;
     int block = 256;
 };
 
@@ -109,6 +111,52 @@ void build_tiles(Plan &P, int block, int order)
     }
 }
 
+// Marker order and tiles of one case: sort the markers along a Morton curve
+// of their body-frame positions (1.5-cell quantization), then cut the
+// sequence into tiles of at most kTileMarkers markers spanning at most
+// kTileSpan cells per axis.  The body is rigid, so markers close in the body
+// frame stay close in the lab frame.
+void tile_markers(const lbm_body &b, int c, int off, std::vector<int> &order, std::vector<MarkerTile> &tiles)
+{
+    const int M = b.n_markers;
+    double lo[3] = {1e300, 1e300, 1e300};
+    for (int q = 0; q < M; q++)
+        for (int a = 0; a < 3; a++) lo[a] = std::min(lo[a], b.x_body[3 * q + a]);
+    std::vector<std::pair<uint64_t, int>> key(M);
+    for (int q = 0; q < M; q++) {
+        uint64_t k = 0;
+        uint32_t cq[3];
+        for (int a = 0; a < 3; a++) cq[a] = (uint32_t)std::min(1023.0, (b.x_body[3 * q + a] - lo[a]) / 1.5);
+        for (int bit = 9; bit >= 0; bit--)
+            for (int a = 0; a < 3; a++) k = (k << 1) | ((cq[a] >> bit) & 1u);
+        key[q] = {k, q};
+    }
+    std::stable_sort(key.begin(), key.end());
+    int start = 0;
+    double bmin[3], bmax[3];
+    for (int j = 0; j < M; j++) {
+        const int q = key[j].second;
+        bool cut = j - start >= kTileMarkers;
+        if (!cut && j > start)
+            for (int a = 0; a < 3; a++) {
+                const double v = b.x_body[3 * q + a];
+                if (std::max(bmax[a], v) - std::min(bmin[a], v) > kTileSpan) cut = true;
+            }
+        if (cut) {
+            tiles.push_back(MarkerTile{c, off + start, j - start, 0});
+            start = j;
+        }
+        if (j == start)
+            for (int a = 0; a < 3; a++) bmin[a] = bmax[a] = b.x_body[3 * q + a];
+        for (int a = 0; a < 3; a++) {
+            bmin[a] = std::min(bmin[a], b.x_body[3 * q + a]);
+            bmax[a] = std::max(bmax[a], b.x_body[3 * q + a]);
+        }
+        order.push_back(q);
+    }
+    if (M > start) tiles.push_back(MarkerTile{c, off + start, M - start, 0});
+}
+
 std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, const lbm_options *opt, Plan &P)
 {
     if (n < 1 || !cases) return "need at least one case";
@@ -142,6 +190,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         pop += Q * d.plane;
         d.M = b ? std::max(0, b->n_markers) : 0;
         d.marker_off = moff;
+        if (d.M > 0) tile_markers(*b, c, moff, P.morder, P.mtiles);
         moff += d.M;
         if (d.M > 0) {
             double rb = 0;
@@ -190,6 +239,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_H = take(sizeof(long long) * 3 * std::max<long long>(reg, 1));
     P.off_feat = take(sizeof(float) * kMlpIn * M);
     P.off_h0 = take(sizeof(double) * 3 * M);
+    P.off_mtiles = take(sizeof(MarkerTile) * std::max<size_t>(P.mtiles.size(), 1));
     P.aux_bytes = o;
     (void)eb;
     return "";
@@ -311,6 +361,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.res = (double *)(a + P.off_res);
     p.reg = (float *)(a + P.off_reg);
     p.H = (long long *)(a + P.off_H);
+    p.mtiles = (MarkerTile *)(a + P.off_mtiles);
     p.feat = (float *)(a + P.off_feat);
     p.h0 = (double *)(a + P.off_h0);
 
@@ -345,15 +396,16 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
                                   c02 * inv, (J[1] * J[6] - J[0] * J[7]) * inv, (J[0] * J[4] - J[1] * J[3]) * inv};
             std::memcpy(B.Jm_inv, Ji, sizeof Ji);
             double rb = 0;
-            for (int q = 0; q < d.M; q++) {
+            for (int j = 0; j < d.M; j++) {
+                const int g = d.marker_off + j, q = P.morder[g];   // internal slot g holds marker q
                 double s = 0;
                 for (int k = 0; k < 3; k++) {
-                    xb[3 * (d.marker_off + q) + k] = b.x_body[3 * q + k];
-                    nb[3 * (d.marker_off + q) + k] = b.n_body[3 * q + k];
+                    xb[3 * g + k] = b.x_body[3 * q + k];
+                    nb[3 * g + k] = b.n_body[3 * q + k];
                     s += b.x_body[3 * q + k] * b.x_body[3 * q + k];
                 }
-                dS[d.marker_off + q] = b.dS[q];
-                mcase[d.marker_off + q] = c;
+                dS[g] = b.dS[q];
+                mcase[g] = c;
                 rb = std::max(rb, std::sqrt(s));
             }
             B.Rb = 1.001 * rb + 0.01;
@@ -373,6 +425,9 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
         (he = hipMemcpyAsync(p.xb, xb.data(), sizeof(double) * xb.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (he = hipMemcpyAsync(p.nb, nb.data(), sizeof(double) * nb.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (he = hipMemcpyAsync(p.dS, dS.data(), sizeof(double) * dS.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (P.mtiles.size() &&
+         (he = hipMemcpyAsync(p.mtiles, P.mtiles.data(), sizeof(MarkerTile) * P.mtiles.size(), hipMemcpyHostToDevice,
+                              s)) != hipSuccess) ||
         (he = hipStreamSynchronize(s)) != hipSuccess)
         return bail(LBM_EHIP, std::string("init: ") + hipGetErrorString(he));
     *out = ctx;
@@ -404,7 +459,7 @@ static int32_t do_ibm(lbm_ctx *ctx)
     if (!ctx->has_body) return LBM_OK;
     HIPCHK(ctx,
            launch_ibm(ctx->opt.storage, ctx->pop[1 - ctx->cur], ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.Mtot,
-                      ctx->plan.maxL3, ctx->opt.ibm_cycles, ctx->warm_mode, ctx->mlp_th16, ctx->mlp_cycles,
+                      (int)ctx->plan.mtiles.size(), ctx->plan.maxL3, ctx->opt.ibm_cycles, ctx->warm_mode, ctx->mlp_th16, ctx->mlp_cycles,
                       ctx->opt.ibm_diag, ctx->stream),
            "ibm_couple");
     ctx->needs_ibm = false;

@@ -45,6 +45,19 @@ struct Tile {
     int first;       // first cell (flat index inside the case) of the tile
 };
 
+// A marker tile: up to kTileMarkers markers of one case that lie close
+// together on the body (sorted along a Morton curve of their body-frame
+// positions, at most kTileSpan lattice units apart per axis), handled by one
+// workgroup whose stencils share a box of at most kBoxMax^3 cells staged in
+// LDS.
+struct MarkerTile {
+    int c, first, count, pad;
+};
+constexpr int kTileMarkers = 16;
+constexpr double kTileSpan = 3.0;
+constexpr int kBoxMax = 11;
+constexpr int kBoxCells = kBoxMax * kBoxMax * kBoxMax;
+
 // Fixed-point scale of the deterministic immersed-force accumulator.
 constexpr double kFixScale = 1099511627776.0;   // 2^40
 constexpr double kFixInv = 1.0 / 1099511627776.0;
@@ -64,6 +77,7 @@ struct DevPtrs {
     float *reg;
     long long *H;
     int *counter;    // 8 work-queue counters of the persistent lattice schedule
+    MarkerTile *mtiles;
     float *feat;     // per-marker warm-start features (12), velocities scaled by kFeatScale
     double *h0;      // per-marker plain start U - I[u*] (3)
 };
@@ -77,8 +91,8 @@ hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
 // that start; cases whose residual exceeds their gate then rerun `cycles`
 // plain cycles.  diag keeps the residual of every cycle.
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
-                      int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles, int diag,
-                      hipStream_t s);
+                      int n_mtiles, int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles,
+                      int diag, hipStream_t s);
 hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s);
 hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s);

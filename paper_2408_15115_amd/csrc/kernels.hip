@@ -354,29 +354,71 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-// l = 0 and the stress integral: u*(X_k), h_k = U_k - u*(X_k); the traction
-// s = sigma(X_k) n_k gives F_k = dS s, T_k = dS (X_k - r) x s and the
-// pressure part dS (-p) n_k (FP64 per marker, summed by k_reduce_ft).
-__global__ void __launch_bounds__(256) k_interp_force(DevPtrs p, int Mtot)
+// ------------------------------------------------------------ marker tiles
+// One workgroup per marker tile (markers close together on the body): the
+// tile's stencils share a box of region cells.  Interpolations stage the
+// box's fields in LDS once and read every stencil node from there; spreading
+// accumulates into an LDS copy of the box (int64 fixed point) and adds each
+// touched cell to HBM once.  A box larger than kBoxMax^3 (not expected for
+// the tile span) falls back to per-node HBM access.
+struct TileBox {
+    int lo[3];    // first stencil node of the box (physical cell coordinates, x/y unwrapped)
+    int o[3];     // the same as region coordinates
+    int e[3];     // box extent
+    bool fits;
+};
+
+__device__ inline TileBox tile_box(const DevPtrs &p, const MarkerTile &mt, const BodyDev &B, int L)
 {
-    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (k >= Mtot) return;
-    const int c = p.mcase[k];
-    const CaseDev &cd = p.cases[c];
-    const BodyDev &B = p.body[c];
-    if (B.err != 0) return;
+    int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    for (int j = 0; j < mt.count; j++) {
+        const int k = mt.first + j;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const int f = (int)floor(p.X[3 * k + d]);
+            mn[d] = min(mn[d], f);
+            mx[d] = max(mx[d], f);
+        }
+    }
+    TileBox b;
+    b.fits = true;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        b.lo[d] = mn[d] - 1;
+        b.o[d] = b.lo[d] - B.org[d];
+        b.e[d] = mx[d] - mn[d] + 4;
+        b.fits = b.fits && b.e[d] <= kBoxMax && b.o[d] >= 0 && b.o[d] + b.e[d] <= L;
+    }
+    return b;
+}
+
+// Box-local index of a lane's stencil node, and its weight.
+__device__ inline int box_node(const double X[3], int lane, const TileBox &b, double &W)
+{
+    const int off[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+    int r[3];
+    W = 1.0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int node = (int)floor(X[d]) - 1 + off[d];
+        W *= phi4((double)node - X[d]);
+        r[d] = node - b.lo[d];
+    }
+    return r[0] + b.e[0] * (r[1] + b.e[1] * r[2]);
+}
+
+// Region cell index of box cell i.
+__device__ inline int box_region_cell(int i, const TileBox &b, int L)
+{
+    const int bx = i % b.e[0], t = i / b.e[0], by = t % b.e[1], bz = t / b.e[1];
+    return (b.o[0] + bx) + L * ((b.o[1] + by) + L * (b.o[2] + bz));
+}
+
+// Per-marker epilogue of the l = 0 interpolation: plain start, features and
+// the stress-integral parts (v = interpolated rho - 1, u*, sigma).
+__device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B, const double v[kRegFields])
+{
     const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
-    const Node nd = stencil_node(X, lane, cd, B);
-    const int L3 = cd.L * cd.L * cd.L;
-    const float *R = p.reg + cd.reg_off * kRegFields;
-    double v[kRegFields];
-#pragma unroll
-    for (int f = 0; f < kRegFields; f++) v[f] = nd.q >= 0 ? nd.W * (double)R[f * L3 + nd.q] : 0.0;
-#pragma unroll
-    for (int f = 0; f < kRegFields; f++) v[f] = wave_sum(v[f]);
-    if (nd.q < 0) atomicOr(&p.body[c].err, 1);
-    if (lane != 0) return;
     const double pr = (double)CS2 * v[0];
     const double sg[3][3] = {{v[4], v[7], v[8]}, {v[7], v[5], v[9]}, {v[8], v[9], v[6]}};
     const double nk[3] = {p.N[3 * k], p.N[3 * k + 1], p.N[3 * k + 2]};
@@ -407,10 +449,155 @@ __global__ void __launch_bounds__(256) k_interp_force(DevPtrs p, int Mtot)
     }
 }
 
-// Deterministic FP64 sums of the per-marker parts of one case.
-__global__ void __launch_bounds__(256) k_reduce_ft(DevPtrs p)
+// l = 0 and the stress integral over a tile (wave w takes markers w, w+4, ...).
+__global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p)
 {
-    __shared__ double sh[kPart][256];
+    __shared__ float box[kRegFields][kBoxCells];
+    const MarkerTile mt = p.mtiles[blockIdx.x];
+    const CaseDev &cd = p.cases[mt.c];
+    const BodyDev &B = p.body[mt.c];
+    if (B.err != 0) return;
+    const int L = cd.L, L3 = L * L * L;
+    const float *R = p.reg + cd.reg_off * kRegFields;
+    const TileBox tb = tile_box(p, mt, B, L);
+    const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
+    if (tb.fits) {
+        for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+            const int q = box_region_cell(i, tb, L);
+#pragma unroll
+            for (int f = 0; f < kRegFields; f++) box[f][i] = R[f * L3 + q];
+        }
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
+        const int k = mt.first + j;
+        const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
+        double v[kRegFields];
+        if (tb.fits) {
+            double W;
+            const int i = box_node(X, lane, tb, W);
+#pragma unroll
+            for (int f = 0; f < kRegFields; f++) v[f] = W * (double)box[f][i];
+        } else {
+            const Node nd = stencil_node(X, lane, cd, B);
+#pragma unroll
+            for (int f = 0; f < kRegFields; f++) v[f] = nd.q >= 0 ? nd.W * (double)R[f * L3 + nd.q] : 0.0;
+        }
+#pragma unroll
+        for (int f = 0; f < kRegFields; f++) v[f] = wave_sum(v[f]);
+        if (lane == 0) force_epilogue(p, k, B, v);
+    }
+}
+
+// l = 1 over a tile: LDS accumulation, then one HBM atomic per touched cell.
+__global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int only_fallback)
+{
+    __shared__ unsigned long long acc[3][kBoxCells];
+    const MarkerTile mt = p.mtiles[blockIdx.x];
+    const CaseDev &cd = p.cases[mt.c];
+    const BodyDev &B = p.body[mt.c];
+    if (B.err != 0 || (only_fallback && !B.fallback)) return;
+    const int L = cd.L, L3 = L * L * L;
+    long long *H = p.H + cd.reg_off * 3;
+    const TileBox tb = tile_box(p, mt, B, L);
+    const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
+    if (tb.fits)
+        for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[0][i] = acc[1][i] = acc[2][i] = 0ull;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
+        const int k = mt.first + j;
+        const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
+        double W;
+        int i = 0;
+        int q = -1;
+        if (tb.fits) {
+            i = box_node(X, lane, tb, W);
+        } else {
+            const Node nd = stencil_node(X, lane, cd, B);
+            W = nd.W;
+            q = nd.q;
+        }
+        const double wS = W * p.dS[k];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const double v = p.dh[3 * k + a] * wS;
+            long long fx = 0;
+            if (fabs(v) < 1.0e6) fx = __double2ll_rn(v * kFixScale);
+            else atomicOr(&p.body[mt.c].err, 2);
+            if (tb.fits) atomicAdd(&acc[a][i], (unsigned long long)fx);
+            else if (q >= 0) atomicAdd((unsigned long long *)&H[a * L3 + q], (unsigned long long)fx);
+        }
+    }
+    __syncthreads();
+    if (!tb.fits) return;
+    for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+        const int q = box_region_cell(i, tb, L);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+            if (acc[a][i] != 0ull) atomicAdd((unsigned long long *)&H[a * L3 + q], acc[a][i]);
+    }
+}
+
+// l = 2..4 over a tile: u* + H staged in LDS (FP64), interpolation, update.
+__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int update, int only_fallback)
+{
+    __shared__ double box[3][kBoxCells];
+    const MarkerTile mt = p.mtiles[blockIdx.x];
+    const CaseDev &cd = p.cases[mt.c];
+    const BodyDev &B = p.body[mt.c];
+    if (B.err != 0 || (only_fallback && !B.fallback)) return;
+    const int L = cd.L, L3 = L * L * L;
+    const float *R = p.reg + cd.reg_off * kRegFields;
+    const long long *H = p.H + cd.reg_off * 3;
+    const TileBox tb = tile_box(p, mt, B, L);
+    const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
+    if (tb.fits) {
+        for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+            const int q = box_region_cell(i, tb, L);
+#pragma unroll
+            for (int a = 0; a < 3; a++) box[a][i] = (double)R[(1 + a) * L3 + q] + (double)H[a * L3 + q] * kFixInv;
+        }
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
+        const int k = mt.first + j;
+        const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
+        double v[3];
+        if (tb.fits) {
+            double W;
+            const int i = box_node(X, lane, tb, W);
+#pragma unroll
+            for (int a = 0; a < 3; a++) v[a] = W * box[a][i];
+        } else {
+            const Node nd = stencil_node(X, lane, cd, B);
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+                v[a] = nd.q >= 0 ? nd.W * ((double)R[(1 + a) * L3 + nd.q] + (double)H[a * L3 + nd.q] * kFixInv) : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) v[a] = wave_sum(v[a]);
+        if (lane != 0) continue;
+        double res = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const double e = p.U[3 * k + a] - v[a];
+            res = fmax(res, fabs(e));
+            if (update) {
+                p.hk[3 * k + a] += e;
+                p.dh[3 * k + a] = e;
+            }
+        }
+        p.res[k] = res;
+    }
+}
+
+// Deterministic FP64 sums of the per-marker parts of one case.
+__global__ void __launch_bounds__(1024) k_reduce_ft(DevPtrs p)
+{
+    __shared__ double sh[kPart][1024];
     const int c = blockIdx.x;
     const CaseDev &cd = p.cases[c];
     if (cd.M == 0 || p.body[c].err != 0) return;
@@ -425,7 +612,7 @@ __global__ void __launch_bounds__(256) k_reduce_ft(DevPtrs p)
 #pragma unroll
     for (int j = 0; j < kPart; j++) sh[j][threadIdx.x] = acc[j];
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s)
 #pragma unroll
             for (int j = 0; j < kPart; j++) sh[j][threadIdx.x] += sh[j][threadIdx.x + s];
@@ -442,75 +629,10 @@ __global__ void __launch_bounds__(256) k_reduce_ft(DevPtrs p)
     }
 }
 
-// l = 1: H(x) += sum_k dh_k W(x - X_k) dS_k with int64 fixed-point atomics
-// (order-independent, hence bitwise reproducible).  The first cycle spreads
-// h_k itself; later cycles spread the l = 4 increment, which by linearity of
-// the spreading yields the spread of the updated h_k.
-__global__ void __launch_bounds__(256) k_spread(DevPtrs p, int Mtot, int only_fallback)
-{
-    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (k >= Mtot) return;
-    const int c = p.mcase[k];
-    const CaseDev &cd = p.cases[c];
-    const BodyDev &B = p.body[c];
-    if (B.err != 0 || (only_fallback && !B.fallback)) return;
-    const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
-    const Node nd = stencil_node(X, lane, cd, B);
-    if (nd.q < 0) return;
-    const int L3 = cd.L * cd.L * cd.L;
-    long long *H = p.H + cd.reg_off * 3;
-    const double wS = nd.W * p.dS[k];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const double v = p.dh[3 * k + a] * wS;
-        long long fx = 0;
-        if (fabs(v) < 1.0e6) fx = __double2ll_rn(v * kFixScale);
-        else atomicOr(&p.body[c].err, 2);
-        atomicAdd((unsigned long long *)&H[a * L3 + nd.q], (unsigned long long)fx);
-    }
-}
-
-// l = 2..4: u3(X_k) = I[u* + H](X_k); e = U_k - u3; with update: h_k += e and
-// the next spread source is e.  The per-marker residual max |e| is kept.
-__global__ void __launch_bounds__(256) k_interp_update(DevPtrs p, int Mtot, int update, int only_fallback)
-{
-    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (k >= Mtot) return;
-    const int c = p.mcase[k];
-    const CaseDev &cd = p.cases[c];
-    const BodyDev &B = p.body[c];
-    if (B.err != 0 || (only_fallback && !B.fallback)) return;
-    const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
-    const Node nd = stencil_node(X, lane, cd, B);
-    const int L3 = cd.L * cd.L * cd.L;
-    const float *R = p.reg + cd.reg_off * kRegFields;
-    const long long *H = p.H + cd.reg_off * 3;
-    double v[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-        v[a] = nd.q >= 0 ? nd.W * ((double)R[(1 + a) * L3 + nd.q] + (double)H[a * L3 + nd.q] * kFixInv) : 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; a++) v[a] = wave_sum(v[a]);
-    if (lane != 0) return;
-    double res = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const double e = p.U[3 * k + a] - v[a];
-        res = fmax(res, fabs(e));
-        if (update) {
-            p.hk[3 * k + a] += e;
-            p.dh[3 * k + a] = e;
-        }
-    }
-    p.res[k] = res;
-}
-
 // Max residual over the markers of a case: into resid and resid_hist[slot].
-__global__ void __launch_bounds__(256) k_reduce_resid(DevPtrs p, int slot, int only_fallback)
+__global__ void __launch_bounds__(1024) k_reduce_resid(DevPtrs p, int slot, int only_fallback)
 {
-    __shared__ double sh[256];
+    __shared__ double sh[1024];
     const int c = blockIdx.x;
     const CaseDev &cd = p.cases[c];
     if (cd.M == 0 || p.body[c].err != 0 || (only_fallback && !p.body[c].fallback)) return;
@@ -518,7 +640,7 @@ __global__ void __launch_bounds__(256) k_reduce_resid(DevPtrs p, int slot, int o
     for (int k = threadIdx.x; k < cd.M; k += blockDim.x) m = fmax(m, p.res[cd.marker_off + k]);
     sh[threadIdx.x] = m;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
@@ -741,26 +863,27 @@ hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s)
 }
 
 template <class CD>
-static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3,
-                           int cycles, int warm_mode, const _Float16 *th16, int warm_cycles, int diag, hipStream_t s)
+static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot, int n_mtiles,
+                           int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles, int diag,
+                           hipStream_t s)
 {
     using T = typename CD::T;
     const dim3 blk(256);
     const dim3 reg_grid((maxL3 + 255) / 256, n_cases);
-    const dim3 wave_grid((Mtot + 3) / 4);
+    const dim3 tile_grid(n_mtiles);
     const dim3 mark_grid((Mtot + 255) / 256);
     hipLaunchKernelGGL(k_markers, mark_grid, blk, 0, s, p, Mtot);
     hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
-    hipLaunchKernelGGL(k_interp_force, wave_grid, blk, 0, s, p, Mtot);
-    hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), blk, 0, s, p);
+    hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p);
+    hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), dim3(1024), 0, s, p);
     // one sequence of multi-direct forcing cycles (Sec. 2.2, l = 1..4): spread,
     // then interpolate and update, except after the last spread
     auto sequence = [&](int ncyc, int slot0, int only_fallback) {
         for (int cyc = 1; cyc <= ncyc; cyc++) {
-            hipLaunchKernelGGL(k_spread, wave_grid, blk, 0, s, p, Mtot, only_fallback);
-            hipLaunchKernelGGL(k_interp_update, wave_grid, blk, 0, s, p, Mtot, cyc < ncyc ? 1 : 0, only_fallback);
+            hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, only_fallback);
+            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, cyc < ncyc ? 1 : 0, only_fallback);
             if (diag || cyc == ncyc)
-                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p, slot0 + cyc - 1, only_fallback);
+                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, slot0 + cyc - 1, only_fallback);
         }
     };
     if (warm_mode != 0) {
@@ -783,17 +906,20 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
 }
 
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
-                      int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles, int diag,
-                      hipStream_t s)
+                      int n_mtiles, int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles,
+                      int diag, hipStream_t s)
 {
     if (Mtot == 0) return hipSuccess;
     switch (storage) {
     case ST_F16:
-        return ibm_impl<CodecF16>(prev, cur, p, n_cases, Mtot, maxL3, cycles, warm_mode, th16, warm_cycles, diag, s);
+        return ibm_impl<CodecF16>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16, warm_cycles,
+                                  diag, s);
     case ST_BF16:
-        return ibm_impl<CodecBF16>(prev, cur, p, n_cases, Mtot, maxL3, cycles, warm_mode, th16, warm_cycles, diag, s);
+        return ibm_impl<CodecBF16>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16,
+                                   warm_cycles, diag, s);
     default:
-        return ibm_impl<CodecF32>(prev, cur, p, n_cases, Mtot, maxL3, cycles, warm_mode, th16, warm_cycles, diag, s);
+        return ibm_impl<CodecF32>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16, warm_cycles,
+                                  diag, s);
     }
 }
 
