@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & % HBM peak, D3Q27 RR+IBM; FP16-store vs FP32 at equal drag error"
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_ellipsoid256x256x768.txt")
-KERNEL_SOURCES = ["paper_2408_15115_amd/csrc/kernels.hip", "paper_2408_15115_amd/csrc/lattice.hpp"]
+KERNEL_SOURCES = ["paper_2408_15115_amd/csrc/stream_collide.hip", "paper_2408_15115_amd/csrc/lattice.hpp",
+                  "paper_2408_15115_amd/csrc/pull.hpp", "paper_2408_15115_amd/csrc/internal.hpp"]
 
 
 def log(*a):
@@ -131,6 +132,10 @@ def batch_run(T, W, torch, steps, storage):
     S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), **tuned["best"])
     total_ms, k1_ms = timed_steps(S, torch, steps, 3)
     errs = [S.body_state(c, check=False)["err"] for c in range(len(cases))]
+    for c, e in enumerate(errs):
+        if e:
+            log(f"  batch case {c} ({cases[c]['nx']}x{cases[c]['ny']}x{cases[c]['nz']}, tau {cases[c]['tau']:.4f}) "
+                f"masked, error bits {e}")
     S.close()
     del S
     torch.cuda.empty_cache()
@@ -144,24 +149,36 @@ def batch_run(T, W, torch, steps, storage):
             "schedule_cached": tuned["cached"], "masked_cases": int(sum(1 for e in errs if e))}
 
 
-def learned_run(T, W, torch, storage, steps=100, train_iters=1500):
-    """The learned form on the 64-case batch: a plain run from rest gives
-    samples and reference drags; the network is trained on them by the
-    library's kernels; a second run from rest starts every multi-direct
-    forcing from the network with one cycle, gated per case against the plain
-    four-cycle residual (fallback to the plain cycles)."""
+def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, train_iters=2000, max_cycles=3):
+    """The learned form on the batched cases.  The network is trained by the
+    library's kernels on samples of a plain run of the 64-case batch (seeds
+    2408..2471) and evaluated on a held-out batch of 64 other seeds
+    (2472..2535): the residual after k = 1..4 cycles from the plain start,
+    from the previous step's h and from the network (gate 0, so those runs
+    follow the plain trajectory), then the gated run -- cycles from the
+    network start until the case's residual is at or below the largest plain
+    four-cycle residual of that case, at most `max_cycles`, else the plain
+    cycles -- with its IBM time per step, acceptance and drag deviation
+    against the plain run."""
     import numpy as np
     from paper_2408_15115_amd import autotune, learn
-    batch = W.batch_cases(64)
-    cases = [c for c, _ in batch]
-    bodies = [b for _, b in batch]
-    sched = autotune.tune(cases, storage=storage)["best"]
-    nc = len(cases)
+    seed_train, seed_eval, nc = 2408, 2408 + 64, 64
 
-    def ibm_timed(S, collect):
+    def solver(seed0, diag, cycles=4):
+        batch = W.batch_cases(nc, seed0=seed0)
+        cases = [c for c, _ in batch]
+        sched = autotune.tune(cases, storage=storage)["best"]
+        return T.Solver(cases, [b for _, b in batch], storage=storage, stream=torch.cuda.Stream(), ibm_diag=diag,
+                        ibm_cycles=cycles, **sched)
+
+    def close(S):
+        S.close()
+        torch.cuda.empty_cache()
+
+    def run(S, steps, collect=False, hist=False):
         st = S.stream
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        X, Y, r4 = [], [], []
+        X, Y, H = [], [], []
         for k in range(steps):
             S.body_advance()
             S.lbm_step()
@@ -169,51 +186,92 @@ def learned_run(T, W, torch, storage, steps=100, train_iters=1500):
             S.ibm_couple()
             ev[k][1].record(st)
             S.window_shift()
-            if collect and k >= 10 and k % 3 == 0:
+            if k >= skip and collect and k % 3 == 0:
                 f, t = S.ibm_samples()
                 sel = torch.arange(0, f.shape[0], 2, device="cuda")
                 X.append(f[sel].cpu().numpy())
                 Y.append(t[sel].cpu().numpy())
-                r4.append([S.ibm_stats(c)["resid_hist"][3] for c in range(nc)])
+            if k >= skip and hist:
+                sts = [S.ibm_stats(c) for c in range(nc)]
+                H.append([np.concatenate([x["resid_hist"], x["resid_hist_fallback"]]) for x in sts])
         torch.cuda.synchronize()
-        ms = [a.elapsed_time(b) for a, b in ev[5:]]
+        ms = [a.elapsed_time(b) for a, b in ev[skip:]]
         stats = [S.ibm_stats(c) for c in range(nc)]
-        Fz = np.array([S.body_state(c, check=False)["F"][2] for c in range(nc)])
-        errs = np.array([S.body_state(c, check=False)["err"] for c in range(nc)])
-        return sum(ms) / len(ms), X, Y, stats, Fz, errs, np.array(r4)
+        bs = [S.body_state(c, check=False) for c in range(nc)]
+        return {"ms": sum(ms) / len(ms), "X": X, "Y": Y, "H": np.array(H), "stats": stats,
+                "Fz": np.array([b["F"][2] for b in bs]), "vz": np.array([b["v"][2] for b in bs]),
+                "errs": np.array([b["err"] for b in bs])}
 
-    S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), ibm_diag=1, **sched)
-    plain_ms, X, Y, pstats, Fz_plain, perr, r4 = ibm_timed(S, True)
-    S.close()
-    del S
-    torch.cuda.empty_cache()
-    X, Y = np.concatenate(X), np.concatenate(Y)
+    # training data: plain run of the training batch
+    S = solver(seed_train, 0)
+    tr = run(S, train_steps, collect=True)
+    close(S)
+    X, Y = np.concatenate(tr["X"]), np.concatenate(tr["Y"])
     net = T.MLP(max_batch=8192, seed=0)
     t0 = time.perf_counter()
     loss = learn.fit(net, X, Y, iters=train_iters)
     train_s = time.perf_counter() - t0
-    S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), ibm_diag=1, **sched)
-    S.set_warm_start(T.LBM_WARM_MLP, net, 1)
-    # gate: the largest four-cycle residual of the plain run for that case
-    gates = np.nan_to_num(r4.max(0), nan=1e-6)
-    for c in range(nc):
-        S.set_ibm_gate(c, float(gates[c]) if gates[c] > 0 else 1e-6)
-    mlp_ms, _, _, mstats, Fz_mlp, merr, _ = ibm_timed(S, False)
-    S.close()
-    del S
-    torch.cuda.empty_cache()
-    ok = (perr == 0) & (merr == 0)
-    acc = sum(st["accepts"] for st in mstats)
-    rej = sum(st["rejects"] for st in mstats)
-    dev = np.abs(Fz_mlp[ok] - Fz_plain[ok]) / np.abs(Fz_plain[ok])
-    return {"cases": nc, "steps": steps, "train_samples": int(X.shape[0]), "train_iters": train_iters,
-            "train_seconds": round(train_s, 2), "train_loss_standardized": loss,
-            "ibm_ms_per_step_plain_4cycles": round(plain_ms, 4), "ibm_ms_per_step_learned_1cycle_gated": round(mlp_ms, 4),
-            "accepted": int(acc), "rejected": int(rej), "acceptance": round(acc / max(1, acc + rej), 4),
-            "plain_resid_after_1_4_cycles_median": [float(np.median([st["resid_hist"][k] for st in pstats]))
-                                                    for k in (0, 3)],
-            "drag_rel_dev_vs_plain_median": float(np.median(dev)) if dev.size else None,
-            "drag_rel_dev_vs_plain_max": float(dev.max()) if dev.size else None,
+    # held-out batch: plain run (timing, per-step four-cycle residual)
+    S = solver(seed_eval, 0)
+    plain = run(S, eval_steps, hist=True)
+    close(S)
+    # residuals after k cycles on the plain trajectory
+    diag = {}
+    for name, mode, m in (("mlp", T.LBM_WARM_MLP, net), ("previous_h", T.LBM_WARM_PREVIOUS, None)):
+        S = solver(seed_eval, 1)
+        S.set_warm_start(mode, m, 4)
+        for c in range(nc):
+            S.set_ibm_gate(c, 0.0)
+        diag[name] = run(S, eval_steps, hist=True)
+        close(S)
+    # gated runs: the network start, and the previous step's h without a
+    # network (control)
+    ok0 = plain["errs"] == 0
+    r4 = plain["H"][:, :, 3]
+    gates = np.where(ok0, r4.max(0), 0.0)
+    gated = {}
+    for name, mode, m in (("mlp", T.LBM_WARM_MLP, net), ("previous_h", T.LBM_WARM_PREVIOUS, None)):
+        S = solver(seed_eval, 0)
+        S.set_warm_start(mode, m, max_cycles)
+        for c in range(nc):
+            S.set_ibm_gate(c, float(gates[c]))
+        gated[name] = run(S, eval_steps)
+        close(S)
+    # sensitivity of the drag to the IBM residual: plain start, 3 cycles
+    S = solver(seed_eval, 0, cycles=3)
+    plain3 = run(S, eval_steps)
+    close(S)
+    ok = ok0 & (gated["mlp"]["errs"] == 0) & (gated["previous_h"]["errs"] == 0) & (plain3["errs"] == 0)
+    live = np.where(ok)[0]
+
+    def dev(r, key):
+        d = np.abs(r[key][ok] - plain[key][ok]) / np.abs(plain[key][ok])
+        return {"median": float(np.median(d)), "max": float(d.max())} if d.size else None
+
+    def gated_report(r):
+        acc = sum(st["accepts"] for st in r["stats"])
+        rej = sum(st["rejects"] for st in r["stats"])
+        cyc = sum(st["warm_cycles_accepted"] for st in r["stats"])
+        return {"ibm_ms_per_step": round(r["ms"], 4), "accepted": int(acc), "rejected": int(rej),
+                "acceptance": round(acc / max(1, acc + rej), 4), "mean_cycles_accepted": round(cyc / max(1, acc), 3),
+                "drag_rel_dev_vs_plain": dev(r, "Fz"), "vz_rel_dev_vs_plain": dev(r, "vz")}
+
+    med = lambda Hs, k: float(np.median(Hs[:, live, k]))
+    Hm, Hp = diag["mlp"]["H"], diag["previous_h"]["H"]
+    return {"train_batch_seeds": f"{seed_train}..{seed_train + nc - 1}",
+            "eval_batch_seeds": f"{seed_eval}..{seed_eval + nc - 1}", "cases": nc,
+            "train_steps": train_steps, "eval_steps": eval_steps, "train_samples": int(X.shape[0]),
+            "train_iters": train_iters, "train_seconds": round(train_s, 2), "train_loss_standardized": loss,
+            "resid_after_k_cycles_median": {"plain": [med(Hm, 8 + k) for k in range(4)],
+                                            "previous_h": [med(Hp, k) for k in range(4)],
+                                            "mlp": [med(Hm, k) for k in range(4)]},
+            "gate": "largest plain four-cycle residual of the case in the plain run",
+            "max_learned_cycles": max_cycles,
+            "ibm_ms_per_step_plain_4cycles": round(plain["ms"], 4),
+            "learned_gated": gated_report(gated["mlp"]),
+            "previous_h_gated": gated_report(gated["previous_h"]),
+            "plain_3cycles": {"ibm_ms_per_step": round(plain3["ms"], 4),
+                              "drag_rel_dev_vs_plain": dev(plain3, "Fz"), "vz_rel_dev_vs_plain": dev(plain3, "vz")},
             "masked_cases": int((~ok).sum())}
 
 
@@ -318,8 +376,16 @@ def main():
     if not args.no_variants and not args.no_learned:
         lr = learned_run(T, W, torch, args.storage)
         variants["learned_batch64"] = lr
-        log(f"  learned: IBM {lr['ibm_ms_per_step_plain_4cycles']:.3f} -> {lr['ibm_ms_per_step_learned_1cycle_gated']:.3f}"
-            f" ms/step, acceptance {lr['acceptance']:.2f}, drag dev median {lr['drag_rel_dev_vs_plain_median']}")
+        rk = lr["resid_after_k_cycles_median"]
+        log(f"  learned: residual after 1..4 cycles plain {['%.2e' % v for v in rk['plain']]}, "
+            f"previous h {['%.2e' % v for v in rk['previous_h']]}, network {['%.2e' % v for v in rk['mlp']]}")
+        for k in ("learned_gated", "previous_h_gated"):
+            g = lr[k]
+            log(f"  {k}: IBM {lr['ibm_ms_per_step_plain_4cycles']:.3f} -> {g['ibm_ms_per_step']:.3f} ms/step, "
+                f"acceptance {g['acceptance']:.2f}, mean cycles {g['mean_cycles_accepted']}, "
+                f"drag dev {g['drag_rel_dev_vs_plain']}, v_z dev {g['vz_rel_dev_vs_plain']}")
+        log(f"  plain 3 cycles: drag dev {lr['plain_3cycles']['drag_rel_dev_vs_plain']}, "
+            f"v_z dev {lr['plain_3cycles']['vz_rel_dev_vs_plain']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -220,15 +220,21 @@ void *lbm_current_buffer(const lbm_ctx *ctx);
  * Learned warm start of the multi-direct forcing.
  *
  * A network (12 -> 64 -> 64 -> 3, SiLU hidden layers, FP16 weights, FP32
- * accumulation) maps each marker's features -- the interpolated velocity
- * I[u*](X_k), the marker velocity U_k, the normal n_k and the previous
- * step's final force h_k, velocities scaled by 50 (1 / the lattice terminal
- * velocity 0.02) -- to the correction the cycles add to the plain l = 0
- * start U_k - I[u*](X_k) of Sec. 2.2; start + correction replaces it.  The solver runs mlp_cycles cycles from it;
- * a case whose residual max_k |U_k - I[u* + H](X_k)| then exceeds its gate
- * (lbm_set_ibm_gate, default 1e-6) reruns the plain ibm_cycles cycles from
- * the plain start.  All decisions are made on the device, so graphs stay
- * valid.  The network is trained on samples of the solver's own plain runs
+ * accumulation) maps each marker's features -- the plain l = 0 start
+ * h0_k = U_k - I[u*](X_k) of Sec. 2.2 and the previous step's final force
+ * h_k(t-1), both divided by the marker scale s_k = |h0_k| + |h_k(t-1)|, the
+ * marker velocity U_k times 50 (1 / the largest lattice terminal velocity
+ * 0.02) and the normal n_k -- to the change of h from h_k(t-1), over s_k;
+ * the start is s_k (h_k(t-1) / s_k + output).  (h0 and U are an invertible
+ * linear map of I[u*] and U that keeps their small difference out of
+ * cancellation; the per-marker scale makes the map independent of the
+ * case's velocity scale, and a zero network gives the previous-h start.)
+ * From that start the solver runs cycles until the case's residual
+ * max_k |U_k - I[u* + H](X_k)| is at or below its gate
+ * (lbm_set_ibm_gate, default 1e-6), at most `cycles` of them; a case that
+ * does not get there reruns the plain ibm_cycles cycles from the plain
+ * start.  All decisions are made on the device, so graphs stay valid.  The
+ * network is trained on samples of the solver's own plain runs
  * (lbm_ibm_samples) by the library's forward/backward kernels and Adam.
  *
  * Flat FP32 parameter layout (5187 values): W1[64][12] b1[64] W2[64][64]
@@ -266,8 +272,11 @@ const char *mlp_last_error(const lbm_mlp *m);
 
 /* Start of ibm_couple's multi-direct forcing: LBM_WARM_NONE (the plain
  * l = 0 start of Sec. 2.2), LBM_WARM_PREVIOUS (the previous step's final
- * h_k, a control without network) or LBM_WARM_MLP (network m), with
- * `cycles` (1..8) cycles before the gate.  Drops a captured graph. */
+ * h_k, a control without network) or LBM_WARM_MLP (network m), with at
+ * most `cycles` (1..8) gated cycles from that start before the plain
+ * fallback.  Gate 0 never accepts: the run is then the plain run, with the
+ * warm start's residuals after each of its cycles recorded (a diagnostic).
+ * Drops a captured graph. */
 enum { LBM_WARM_NONE = 0, LBM_WARM_PREVIOUS = 1, LBM_WARM_MLP = 2 };
 int32_t lbm_set_warm_start(lbm_ctx *ctx, int32_t mode, const lbm_mlp *m, int32_t cycles);
 
@@ -276,17 +285,19 @@ int32_t lbm_set_ibm_gate(lbm_ctx *ctx, int32_t case_id, double threshold);
 
 /* Samples of the last ibm_couple, to caller device arrays: features
  * (markers x 12 FP32) and the training target, the final force h_k minus
- * the plain start U_k - I[u*](X_k), scaled by 50 (markers x 3), markers of
- * all cases in case order (lbm_marker_count of them).  Take them from plain
- * runs (no warm start). */
+ * the previous step's, over the marker scale s_k (markers x 3), markers of
+ * all cases in case order (lbm_marker_count of them; inside a case in the
+ * library's own marker order).  Take them from plain runs (no warm start). */
 int32_t lbm_ibm_samples(lbm_ctx *ctx, float *dev_features, float *dev_targets);
 int32_t lbm_marker_count(const lbm_ctx *ctx);
 
-/* IBM statistics of a case (synchronizing), out[20]: last residual,
- * residual after each cycle of the first sequence (8) and of the fallback
- * sequence (8), learned starts accepted, rejected, and whether the last
- * step fell back. */
-int32_t lbm_ibm_stats(lbm_ctx *ctx, int32_t case_id, double out[20]);
+/* IBM statistics of a case (synchronizing), out[24]: [0] last residual,
+ * [1..8] residual after each cycle of the first sequence (of the last step
+ * that ran that cycle), [9..16] the same for the fallback sequence, [17]
+ * learned starts accepted, [18] rejected, [19] whether the last step fell
+ * back, [20] cycles used by the accepted learned starts (summed), [21..23]
+ * zero. */
+int32_t lbm_ibm_stats(lbm_ctx *ctx, int32_t case_id, double out[24]);
 
 /* Measurement helper: copy `bytes` (a multiple of 16) from src to dst, both
  * device pointers, with a plain streaming kernel on hip_stream (NULL =

@@ -1,7 +1,8 @@
 // api.hip -- the C ABI of libturret (declared in include/turret.h): argument
 // checks, the device memory plan over caller buffers, the Table 1 call
 // sequence with its state checks, HIP graph capture, host copies and
-// checkpoints.  All arithmetic of the time step runs in kernels.hip.
+// checkpoints.  All arithmetic of the time step runs in stream_collide.hip,
+// kernels.hip and mlp.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,7 +34,7 @@ struct Plan {
     int Mtot = 0, maxL3 = 0, max_slab = 0;
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
-        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_mtiles, aux_bytes;
+        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_mtiles, aux_bytes;
     int block = 256;
 };
 
@@ -239,6 +240,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_H = take(sizeof(long long) * 3 * std::max<long long>(reg, 1));
     P.off_feat = take(sizeof(float) * kMlpIn * M);
     P.off_h0 = take(sizeof(double) * 3 * M);
+    P.off_hs = take(sizeof(double) * M);
     P.off_mtiles = take(sizeof(MarkerTile) * std::max<size_t>(P.mtiles.size(), 1));
     P.aux_bytes = o;
     (void)eb;
@@ -364,6 +366,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.mtiles = (MarkerTile *)(a + P.off_mtiles);
     p.feat = (float *)(a + P.off_feat);
     p.h0 = (double *)(a + P.off_h0);
+    p.hs = (double *)(a + P.off_hs);
 
     // host images of the descriptors, body states and markers
     std::vector<BodyDev> bd(n_cases);
@@ -932,7 +935,7 @@ int32_t lbm_ibm_samples(lbm_ctx *ctx, float *dev_features, float *dev_targets)
     return LBM_OK;
 }
 
-int32_t lbm_ibm_stats(lbm_ctx *ctx, int32_t c, double out[20])
+int32_t lbm_ibm_stats(lbm_ctx *ctx, int32_t c, double out[24])
 {
     if (!ctx || !out || c < 0 || c >= ctx->n) return fail(ctx, LBM_EINVAL, "bad case or NULL output");
     BodyDev B;
@@ -943,6 +946,8 @@ int32_t lbm_ibm_stats(lbm_ctx *ctx, int32_t c, double out[20])
     out[17] = B.accepts;
     out[18] = B.rejects;
     out[19] = B.fallback;
+    out[20] = B.warm_cyc_sum;
+    out[21] = out[22] = out[23] = 0.0;
     return LBM_OK;
 }
 

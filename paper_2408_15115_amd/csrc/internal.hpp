@@ -35,6 +35,8 @@ struct BodyDev {
     double resid_hist[16];      // per-cycle residuals: [0..7] first sequence, [8..15] fallback
     int accepts, rejects;       // learned-start decisions so far
     int fallback;               // 1 if the last step fell back to the plain start
+    int active;                 // 1 while the case still runs cycles of the current sequence
+    int warm_cyc_sum;           // cycles used by the accepted learned starts, summed
     int org[3];      // IBM region origin (physical cell coordinates, x/y unwrapped)
     int err;         // 1: a marker stencil left the box in z; 2: non-finite or huge IBM value;
                      // 4: non-finite density or |u| > 0.5.  Nonzero masks (freezes) the case.
@@ -78,8 +80,9 @@ struct DevPtrs {
     long long *H;
     int *counter;    // 8 work-queue counters of the persistent lattice schedule
     MarkerTile *mtiles;
-    float *feat;     // per-marker warm-start features (12), velocities scaled by kFeatScale
+    float *feat;     // per-marker warm-start features (12)
     double *h0;      // per-marker plain start U - I[u*] (3)
+    double *hs;      // per-marker scale of the warm-start features, |h0| + |h(t-1)|
 };
 
 // ---------------------------------------------------------------- launchers
@@ -87,9 +90,10 @@ hipError_t launch_stream_collide(int storage, const void *src, void *dst, const 
                                  int block, int schedule, int persist_wgs, hipStream_t s);
 hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
 // IBM coupling.  With a warm start (warm_mode 1: the previous step's final
-// h_k; 2: the network th16) the first sequence runs warm_cycles cycles from
-// that start; cases whose residual exceeds their gate then rerun `cycles`
-// plain cycles.  diag keeps the residual of every cycle.
+// h_k; 2: the network th16) cycles run from that start until a case's
+// residual is at or below its gate, at most warm_cycles of them; cases that
+// do not get there rerun `cycles` plain cycles.  diag keeps the residual of
+// every cycle.
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
                       int n_mtiles, int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles,
                       int diag, hipStream_t s);

@@ -1,170 +1,28 @@
 // kernels.hip -- gfx950 kernels of the settling-particle time step
-// (arXiv 2408.15115, Sec. 2) and their stream launchers.
+// (arXiv 2408.15115, Sec. 2) other than the lattice kernel (stream_collide.hip),
+// and their stream launchers.
 //
-//   k_stream_collide  Sec. 2.1: fused pull streaming + recursive-regularized
-//                     collision (App. A), one thread per cell, SoA storage
-//   k_body_advance    Sec. 2.3: leapfrog / predictor-corrector, FP64
-//   k_markers         Sec. 2.3: marker position, normal and rigid velocity
-//   k_region_gather   Sec. 2.1 stress and Sec. 2.2 u* on the particle region
-//   k_interp_force    Sec. 2.2: l = 0 interpolation and the stress integral
-//   k_reduce_ft       FP64 force / torque sums (deterministic tree)
-//   k_spread          Sec. 2.2 l = 1 (deterministic fixed-point atomics)
-//   k_interp_update   Sec. 2.2 l = 2..4
-//   k_correct         Sec. 2.2 forced rule: add f0(u + tau h) - f0(u)
-//   k_window_*        Sec. 2.5 re-injection as a ring-origin shift
+//   k_body_advance        Sec. 2.3: leapfrog / predictor-corrector, FP64
+//   k_markers             Sec. 2.3: marker position, normal and rigid velocity
+//   k_region_gather       Sec. 2.1 stress and Sec. 2.2 u* on the particle region
+//   k_interp_force_tiles  Sec. 2.2: l = 0 interpolation and the stress integral
+//   k_reduce_ft           FP64 force / torque sums (deterministic tree)
+//   k_spread_tiles        Sec. 2.2 spreading (deterministic fixed-point atomics)
+//   k_interp_update_tiles Sec. 2.2 interpolation of u* + H and the residual
+//   k_correct             Sec. 2.2 forced rule: add f0(u + tau h) - f0(u)
+//   k_window_*            Sec. 2.5 re-injection as a ring-origin shift
 //
 // IBM kernels give one 64-lane wavefront to each marker: lane l is the
-// stencil node (l & 3, (l >> 2) & 3, l >> 4) of the 4 x 4 x 4 weight support.
+// stencil node (l & 3, (l >> 2) & 3, l >> 4) of the 4 x 4 x 4 weight support;
+// a workgroup takes one tile of nearby markers and stages their common box of
+// region cells in LDS.
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "pull.hpp"
 #include "mlp.hpp"
 
 namespace turret {
 
-__device__ inline int wrapi(int v, int n)
-{
-    v %= n;
-    return v < 0 ? v + n : v;
-}
-
-// ------------------------------------------------------------------ pull
-// The 27 populations arriving at cell (x, y, z): g_i = C_i(x - xi_i) from the
-// previous post-collision buffer.  x, y periodic; at the z walls the missing
-// population comes from specular reflection (free-slip: C_{mirror_z(i)} of the
-// lateral neighbour in the same row) or bounce-back (no-slip: C_{opposite(i)}
-// of the cell itself); periodic z wraps.  Physical row z sits in ring slot
-// (z + z0) mod nz.
-template <class CD>
-__device__ inline void pull(const typename CD::T *__restrict__ src, long long plane, int nx, int ny, int nz,
-                            int z0, int bc_lo, int bc_hi, int x, int y, int z, float g[Q])
-{
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-    int zc = z + z0;
-    if (zc >= nz) zc -= nz;
-    const int zlo = zc == 0 ? nz - 1 : zc - 1;
-    const int zhi = zc == nz - 1 ? 0 : zc + 1;
-    const bool wlo = (z == 0) && bc_lo != BC_PERIODIC;
-    const bool whi = (z == nz - 1) && bc_hi != BC_PERIODIC;
-    const int rowc = zc * ny, rowlo = zlo * ny, rowhi = zhi * ny;
-    Unroll<0, Q>::run([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        int sx = cx(i) == 1 ? xm : (cx(i) == -1 ? xp : x);
-        int sy = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
-        int srow = cz(i) == 1 ? rowlo : (cz(i) == -1 ? rowhi : rowc);
-        int dir = i;
-        if constexpr (cz(i) != 0) {
-            const bool wall = cz(i) == 1 ? wlo : whi;
-            const int bc = cz(i) == 1 ? bc_lo : bc_hi;
-            if (wall) {
-                srow = rowc;
-                if (bc == BC_FREESLIP) {
-                    dir = mirror_z(i);
-                } else {
-                    dir = opposite(i);
-                    sx = x;
-                    sy = y;
-                }
-            }
-        }
-        g[i] = CD::template dec<i>(src[(long long)dir * plane + (long long)((srow + sy) * nx + sx)]);
-    });
-}
-
-// Every population is written once per step and not read again before the
-// next step: the stores carry the non-temporal hint (measured faster; the
-// same hint on the loads is not).
-template <class CD>
-__device__ __forceinline__ void store_all(typename CD::T *__restrict__ dst, long long plane, int off, const float out[Q])
-{
-    Unroll<0, Q>::run([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        __builtin_nontemporal_store(CD::template enc<i>(out[i]), &dst[(long long)i * plane + off]);
-    });
-}
-
-// ------------------------------------------------------------ stream-collide
-// One tile = blockDim.x consecutive cells of one case.  A case whose error
-// bits are set is masked (frozen) so the rest of a batch goes on.  The guard
-// flags non-finite density or |u| > 0.5 (bit 4) with one atomic per wave.
-template <class CD>
-__device__ __forceinline__ void stream_collide_tile(const typename CD::T *__restrict__ src, typename CD::T *__restrict__ dst,
-                                                    const CaseDev *__restrict__ cases, BodyDev *__restrict__ body, Tile tl)
-{
-    const CaseDev &cd = cases[tl.c];
-    const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
-    const int cell = tl.first + (int)threadIdx.x;
-    if (body[tl.c].err != 0 || cell >= (int)cd.cells) return;
-    const int z0 = body[tl.c].z0;
-    const int x = cell % nx;
-    const int t2 = cell / nx;
-    const int y = t2 % ny;
-    const int z = t2 / ny;
-    float g[Q];
-    pull<CD>(src + cd.pop_off, cd.plane, nx, ny, nz, z0, cd.bc_lo, cd.bc_hi, x, y, z, g);
-    const Macro M = macro(raw_moments(g));
-    const float u2 = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
-    const bool bad = !(fabsf(M.r1) < 1.0f) || !(u2 < 0.25f);
-    const unsigned long long m = __ballot(bad);
-    if (m != 0ull && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)m) - 1) atomicOr(&body[tl.c].err, 4);
-    const float tau = tau_at(cd.tau0, nz, cd.sponge, z);
-    const float om = 1.0f - 1.0f / tau;
-    float A[Q], out[Q];
-    post_collision_coeffs(M, M.u, om, A);
-    hermite_to_populations(A, out);
-    int zc = z + z0;
-    if (zc >= nz) zc -= nz;
-    store_all<CD>(dst + cd.pop_off, cd.plane, (zc * ny + y) * nx + x, out);
-}
-
-// SCHED 0: tile = workgroup; 1: XCD-grouped tiles (workgroups go
-// round-robin over the 8 XCDs, so workgroup b handles tile
-// (b mod 8) * (grid / 8) + b / 8 and neighbouring rows share one L2);
-// 2: persistent workgroups striding over the table; 3: persistent work
-// queue.  The queue is split in 8 contiguous segments with one counter each
-// (a single device-wide counter serializes every grab across the XCDs);
-// workgroup b starts on segment b mod 8, takes kQueueChunk tiles per grab and
-// moves on to the other segments when its own is exhausted.  Counters only
-// grow, so every workgroup leaves the loop.  One instantiation per schedule
-// keeps the register allocation of the plain schedules free of the loops.
-constexpr int kQueueChunk = 4;
-
-template <class CD, int SCHED>
-__global__ void __launch_bounds__(256) k_stream_collide(const typename CD::T *__restrict__ src,
-                                                        typename CD::T *__restrict__ dst,
-                                                        const CaseDev *__restrict__ cases, BodyDev *__restrict__ body,
-                                                        const Tile *__restrict__ tiles, int ntiles,
-                                                        int *__restrict__ counter)
-{
-    if constexpr (SCHED == 3) {
-        __shared__ int s_t;
-        const int per = (ntiles + 7) >> 3;
-        for (int k = 0; k < 8; k++) {
-            const int grp = (blockIdx.x + k) & 7;
-            const int lo = grp * per, hi = min(ntiles, lo + per);
-            for (;;) {
-                if (threadIdx.x == 0) s_t = lo + kQueueChunk * atomicAdd(&counter[grp], 1);
-                __syncthreads();
-                const int t0 = __builtin_amdgcn_readfirstlane(s_t);
-                __syncthreads();
-                if (t0 >= hi) break;
-                const int t1 = min(t0 + kQueueChunk, hi);
-                for (int t = t0; t < t1; t++) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
-            }
-        }
-    } else if constexpr (SCHED == 2) {
-        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
-    } else {
-        int t = blockIdx.x;
-        if constexpr (SCHED == 1) t = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-        if (t < ntiles) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
-    }
-}
-
-__global__ void k_reset_counter(int *counter)
-{
-    if (threadIdx.x < 8) counter[threadIdx.x] = 0;
-}
 
 // ---------------------------------------------------------------- body
 __device__ inline void cross3(const double a[3], const double b[3], double c[3])
@@ -423,21 +281,32 @@ __device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B,
     const double sg[3][3] = {{v[4], v[7], v[8]}, {v[7], v[5], v[9]}, {v[8], v[9], v[6]}};
     const double nk[3] = {p.N[3 * k], p.N[3 * k + 1], p.N[3 * k + 2]};
     const double dS = p.dS[k];
-    double s[3], rel[3], ts[3];
+    double s[3], rel[3], ts[3], h0[3], hp[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        h0[a] = p.U[3 * k + a] - v[1 + a];
+        hp[a] = p.hk[3 * k + a];   // the previous step's final h
+    }
+    // warm-start features: the plain start U - I[u*] (an invertible linear
+    // map of I[u*] and U that keeps their small difference out of
+    // cancellation) and the previous step's final h, both over the marker's
+    // scale |h0| + |h(t-1)|; U scaled by kFeatScale; the normal
+    const double sc = fmax(sqrt(h0[0] * h0[0] + h0[1] * h0[1] + h0[2] * h0[2]) +
+                               sqrt(hp[0] * hp[0] + hp[1] * hp[1] + hp[2] * hp[2]), 1e-14);
+    p.hs[k] = sc;
     float *ft = p.feat + (long long)kMlpIn * k;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         s[a] = sg[a][0] * nk[0] + sg[a][1] * nk[1] + sg[a][2] * nk[2];
         rel[a] = X[a] - B.r[a];
-        const double h0 = p.U[3 * k + a] - v[1 + a];
-        // warm-start features: I[u*], U, n and the previous step's final h
-        ft[a] = (float)(v[1 + a] * kFeatScale);
+        ft[a] = (float)(h0[a] / sc);
         ft[3 + a] = (float)(p.U[3 * k + a] * kFeatScale);
         ft[6 + a] = (float)nk[a];
-        ft[9 + a] = (float)(p.hk[3 * k + a] * kFeatScale);
-        p.h0[3 * k + a] = h0;
-        p.hk[3 * k + a] = h0;
-        p.dh[3 * k + a] = h0;
+        ft[9 + a] = (float)(hp[a] / sc);
+        // h_k holds what has been spread so far; dh is the next increment
+        p.h0[3 * k + a] = h0[a];
+        p.hk[3 * k + a] = 0.0;
+        p.dh[3 * k + a] = h0[a];
     }
     cross3(rel, s, ts);
     double *o = p.part + (long long)kPart * k;
@@ -490,14 +359,16 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p)
     }
 }
 
-// l = 1 over a tile: LDS accumulation, then one HBM atomic per touched cell.
-__global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int only_fallback)
+// Spreading of the increments dh over a tile (H += S[dh], h_k += dh): LDS
+// accumulation, then one HBM atomic per touched cell.  With masked set, cases
+// whose sequence has ended are skipped.
+__global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int masked)
 {
     __shared__ unsigned long long acc[3][kBoxCells];
     const MarkerTile mt = p.mtiles[blockIdx.x];
     const CaseDev &cd = p.cases[mt.c];
     const BodyDev &B = p.body[mt.c];
-    if (B.err != 0 || (only_fallback && !B.fallback)) return;
+    if (B.err != 0 || (masked && !B.active)) return;
     const int L = cd.L, L3 = L * L * L;
     long long *H = p.H + cd.reg_off * 3;
     const TileBox tb = tile_box(p, mt, B, L);
@@ -520,9 +391,13 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int only_fallba
             q = nd.q;
         }
         const double wS = W * p.dS[k];
+        const double dh[3] = {p.dh[3 * k], p.dh[3 * k + 1], p.dh[3 * k + 2]};
+        if (lane == 0)
+#pragma unroll
+            for (int a = 0; a < 3; a++) p.hk[3 * k + a] += dh[a];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            const double v = p.dh[3 * k + a] * wS;
+            const double v = dh[a] * wS;
             long long fx = 0;
             if (fabs(v) < 1.0e6) fx = __double2ll_rn(v * kFixScale);
             else atomicOr(&p.body[mt.c].err, 2);
@@ -540,14 +415,15 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int only_fallba
     }
 }
 
-// l = 2..4 over a tile: u* + H staged in LDS (FP64), interpolation, update.
-__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int update, int only_fallback)
+// Interpolation of u* + H over a tile (staged in LDS, FP64), the residual
+// U_k - I[u* + H](X_k) and the next increment dh = that residual.
+__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int masked)
 {
     __shared__ double box[3][kBoxCells];
     const MarkerTile mt = p.mtiles[blockIdx.x];
     const CaseDev &cd = p.cases[mt.c];
     const BodyDev &B = p.body[mt.c];
-    if (B.err != 0 || (only_fallback && !B.fallback)) return;
+    if (B.err != 0 || (masked && !B.active)) return;
     const int L = cd.L, L3 = L * L * L;
     const float *R = p.reg + cd.reg_off * kRegFields;
     const long long *H = p.H + cd.reg_off * 3;
@@ -585,10 +461,7 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int upda
         for (int a = 0; a < 3; a++) {
             const double e = p.U[3 * k + a] - v[a];
             res = fmax(res, fabs(e));
-            if (update) {
-                p.hk[3 * k + a] += e;
-                p.dh[3 * k + a] = e;
-            }
+            p.dh[3 * k + a] = e;
         }
         p.res[k] = res;
     }
@@ -630,12 +503,15 @@ __global__ void __launch_bounds__(1024) k_reduce_ft(DevPtrs p)
 }
 
 // Max residual over the markers of a case: into resid and resid_hist[slot].
-__global__ void __launch_bounds__(1024) k_reduce_resid(DevPtrs p, int slot, int only_fallback)
+// With masked set only cases still active are reduced; with gate_cycle > 0
+// (a learned-start cycle) a case whose residual is at or below its gate is
+// accepted and leaves the sequence.
+__global__ void __launch_bounds__(1024) k_reduce_resid(DevPtrs p, int slot, int masked, int gate_cycle)
 {
     __shared__ double sh[1024];
     const int c = blockIdx.x;
     const CaseDev &cd = p.cases[c];
-    if (cd.M == 0 || p.body[c].err != 0 || (only_fallback && !p.body[c].fallback)) return;
+    if (cd.M == 0 || p.body[c].err != 0 || (masked && !p.body[c].active)) return;
     double m = 0.0;
     for (int k = threadIdx.x; k < cd.M; k += blockDim.x) m = fmax(m, p.res[cd.marker_off + k]);
     sh[threadIdx.x] = m;
@@ -645,34 +521,49 @@ __global__ void __launch_bounds__(1024) k_reduce_resid(DevPtrs p, int slot, int 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        p.body[c].resid = sh[0];
-        if (slot >= 0 && slot < 16) p.body[c].resid_hist[slot] = sh[0];
+        BodyDev &B = p.body[c];
+        B.resid = sh[0];
+        if (slot >= 0 && slot < 16) B.resid_hist[slot] = sh[0];
+        if (gate_cycle > 0 && sh[0] <= B.gate) {
+            B.active = 0;
+            B.accepts += 1;
+            B.warm_cyc_sum += gate_cycle;
+        }
     }
 }
 
-// Gate of the learned start: a case whose residual after the learned-start
-// cycles exceeds its gate falls back to the plain start.
+// Start of a learned-start sequence: every live case runs cycles.
+__global__ void k_gate_begin(DevPtrs p, int n_cases)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cases) return;
+    BodyDev &B = p.body[c];
+    B.active = 1;
+    B.fallback = 0;
+}
+
+// End of the learned-start cycles: a case not accepted within them falls
+// back to the plain start and stays active for the plain cycles.
 __global__ void k_gate(DevPtrs p, int n_cases)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cases) return;
     BodyDev &B = p.body[c];
     if (p.cases[c].M == 0 || B.err != 0) return;
-    B.fallback = !(B.resid <= B.gate);
+    B.fallback = B.active;
     if (B.fallback) B.rejects += 1;
-    else B.accepts += 1;
 }
 
 // Warm start without a network: the previous step's final h_k (kept in the
-// features, scaled).
+// features over the marker's scale).
 __global__ void k_warm_previous(DevPtrs p, int Mtot)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= Mtot || p.body[p.mcase[k]].err != 0) return;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const double h = (double)p.feat[(long long)kMlpIn * k + 9 + a] / kFeatScale;
-        p.hk[3 * k + a] = h;
+        const double h = (double)p.feat[(long long)kMlpIn * k + 9 + a] * p.hs[k];
+        p.hk[3 * k + a] = 0.0;
         p.dh[3 * k + a] = h;
     }
 }
@@ -686,7 +577,7 @@ __global__ void k_fallback_markers(DevPtrs p, int Mtot)
     if (B.err != 0 || !B.fallback) return;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        p.hk[3 * k + a] = p.h0[3 * k + a];
+        p.hk[3 * k + a] = 0.0;
         p.dh[3 * k + a] = p.h0[3 * k + a];
     }
 }
@@ -707,15 +598,15 @@ __global__ void k_fallback_zero(DevPtrs p)
     H[2 * L3 + q] = 0;
 }
 
-// Training targets: what the cycles added to the plain start, scaled like
-// the features: (h_k - (U_k - I[u*](X_k))) * scale.
+// Training targets: the final h_k minus the previous step's h, over the
+// marker's feature scale: h_k / s_k - feature 9..11.
 __global__ void k_targets(DevPtrs p, int Mtot, float *out)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= Mtot) return;
+    const float *ft = p.feat + (long long)kMlpIn * k;
 #pragma unroll
-    for (int a = 0; a < 3; a++)
-        out[3 * k + a] = (float)((p.hk[3 * k + a] - p.h0[3 * k + a]) * kFeatScale);
+    for (int a = 0; a < 3; a++) out[3 * k + a] = (float)(p.hk[3 * k + a] / p.hs[k] - (double)ft[9 + a]);
 }
 
 // Forced collision of Sec. 2.2: the lattice kernel wrote
@@ -796,66 +687,7 @@ __global__ void k_window_reset(typename CD::T *__restrict__ cur, DevPtrs p)
     });
 }
 
-// ------------------------------------------------------------ copy kernel
-// Plain 16-byte-per-lane streaming copy, grid-strided.
-__global__ void __launch_bounds__(256) k_copy(int4 *__restrict__ dst, const int4 *__restrict__ src, long long n)
-{
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
-hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s)
-{
-    const long long n = bytes / 16;
-    long long grid = (n + 255) / 256;
-    if (grid > 65536) grid = 65536;
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(256), 0, s, (int4 *)dst, (const int4 *)src, n);
-    return hipGetLastError();
-}
-
 // --------------------------------------------------------------- launchers
-template <class CD>
-static hipError_t stream_collide_impl(const void *src, void *dst, const DevPtrs &p, int ntiles, int block,
-                                      int schedule, int persist_wgs, hipStream_t s)
-{
-    using T = typename CD::T;
-    int grid = ntiles;
-    if (schedule == 1) grid = (ntiles + 7) / 8 * 8;
-    if (schedule >= 2) grid = persist_wgs > 0 ? persist_wgs : 2048;
-    const T *a = (const T *)src;
-    T *b = (T *)dst;
-    switch (schedule) {
-    case 1:
-        hipLaunchKernelGGL((k_stream_collide<CD, 1>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
-                           ntiles, p.counter);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_stream_collide<CD, 2>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
-                           ntiles, p.counter);
-        break;
-    case 3:
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, p.counter);
-        hipLaunchKernelGGL((k_stream_collide<CD, 3>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
-                           ntiles, p.counter);
-        break;
-    default:
-        hipLaunchKernelGGL((k_stream_collide<CD, 0>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
-                           ntiles, p.counter);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_stream_collide(int storage, const void *src, void *dst, const DevPtrs &p, int ntiles,
-                                 int block, int schedule, int persist_wgs, hipStream_t s)
-{
-    switch (storage) {
-    case ST_F16: return stream_collide_impl<CodecF16>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
-    case ST_BF16: return stream_collide_impl<CodecBF16>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
-    default: return stream_collide_impl<CodecF32>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
-    }
-}
-
 hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s)
 {
     hipLaunchKernelGGL(k_body_advance, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
@@ -876,25 +708,34 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
     hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p);
     hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), dim3(1024), 0, s, p);
-    // one sequence of multi-direct forcing cycles (Sec. 2.2, l = 1..4): spread,
-    // then interpolate and update, except after the last spread
-    auto sequence = [&](int ncyc, int slot0, int only_fallback) {
+    // one sequence of multi-direct forcing cycles (Sec. 2.2, l = 1..4): spread
+    // the increment, then interpolate and form the next increment; the
+    // residual after the last spread is the sequence's residual
+    auto sequence = [&](int ncyc, int slot0, int masked) {
         for (int cyc = 1; cyc <= ncyc; cyc++) {
-            hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, only_fallback);
-            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, cyc < ncyc ? 1 : 0, only_fallback);
+            hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, masked);
+            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, masked);
             if (diag || cyc == ncyc)
-                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, slot0 + cyc - 1, only_fallback);
+                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, slot0 + cyc - 1, masked, 0);
         }
     };
     if (warm_mode != 0) {
+        // learned (or previous-h) start: cycles until the case's residual is
+        // at or below its gate, at most warm_cycles; the rest restart plain
         if (warm_mode == 2) {
             hipError_t e = launch_mlp_warm_start(th16, p, Mtot, s);   // the network lives in mlp.hip
             if (e != hipSuccess) return e;
         } else {
             hipLaunchKernelGGL(k_warm_previous, mark_grid, blk, 0, s, p, Mtot);
         }
-        sequence(warm_cycles, 0, 0);
-        hipLaunchKernelGGL(k_gate, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
+        const dim3 case_grid((n_cases + 63) / 64), case_blk(64);
+        hipLaunchKernelGGL(k_gate_begin, case_grid, case_blk, 0, s, p, n_cases);
+        for (int cyc = 1; cyc <= warm_cycles; cyc++) {
+            hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, 1);
+            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, 1);
+            hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, cyc - 1, 1, cyc);
+        }
+        hipLaunchKernelGGL(k_gate, case_grid, case_blk, 0, s, p, n_cases);
         hipLaunchKernelGGL(k_fallback_markers, mark_grid, blk, 0, s, p, Mtot);
         hipLaunchKernelGGL(k_fallback_zero, reg_grid, blk, 0, s, p);
         sequence(cycles, 8, 1);

@@ -275,6 +275,13 @@ __device__ inline void hermite_to_populations(const float A[Q], float out[Q])
 
 // Relaxation time at physical height z: tau0 below the sponge, rising
 // linearly to 1 on the top row inside it (Sec. 2.5).
+// Periodic wrap of an index into [0, n).
+__device__ inline int wrapi(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
 __device__ inline float tau_at(float tau0, int nz, int sponge, int z)
 {
     if (sponge < 2) return tau0;

@@ -76,10 +76,11 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const _Float16 *__restrict_
     for (int j = 0; j < kMlpOut; j++) Y[(long long)s * kMlpOut + j] = y[j];
 }
 
-// Warm start inside the IBM coupling: the network predicts the correction the
-// multi-direct forcing cycles add to the plain start, h_k = U_k - I[u*](X_k)
-// + MLP(features_k) / scale (U and I[u*] are features 3..5 and 0..2), for
-// every marker of an unmasked case; the first spread then spreads it.
+// Warm start inside the IBM coupling: the network predicts, over the
+// marker's feature scale s_k, the change of h from the previous step's final
+// value (features 9..11 = h(t-1) / s_k): h = s_k (feature 9..11 +
+// MLP(features_k)), for every marker of an unmasked case; it becomes the
+// first increment to spread.
 __global__ void __launch_bounds__(256) k_mlp_warm_start(const _Float16 *__restrict__ th16, DevPtrs p, int Mtot)
 {
     __shared__ float w[kMlpParams];
@@ -92,8 +93,8 @@ __global__ void __launch_bounds__(256) k_mlp_warm_start(const _Float16 *__restri
     mlp_forward_one(w, x, y, nullptr, nullptr, nullptr, nullptr, 0);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const double h = (double)(x[3 + a] - x[a] + y[a]) / kFeatScale;
-        p.hk[3 * k + a] = h;
+        const double h = ((double)x[9 + a] + (double)y[a]) * p.hs[k];
+        p.hk[3 * k + a] = 0.0;
         p.dh[3 * k + a] = h;
     }
 }

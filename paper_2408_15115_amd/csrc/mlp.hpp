@@ -15,8 +15,9 @@ constexpr int kOffB3 = kOffW3 + kMlpOut * kMlpH;
 constexpr int kMlpParams = kOffB3 + kMlpOut;   // 5187
 constexpr int kMlpSlice = 256;                 // samples per weight-gradient partial sum
 
-// Velocity-like features and outputs are scaled by 1 / 0.02, the lattice
-// terminal velocity of the cases, so they are O(1).
+// The marker velocity feature is scaled by 1 / 0.02, the largest lattice
+// terminal velocity of the cases, so it is O(1); the force-like features
+// and the output are taken over a per-marker scale instead.
 constexpr double kFeatScale = 50.0;
 
 // Per-sample training scratch, [field][sample] layout (n samples).

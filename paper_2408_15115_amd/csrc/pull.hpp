@@ -1,0 +1,54 @@
+// pull.hpp -- pull streaming with the boundary rules of the domain
+// (arXiv 2408.15115, Sec. 2.1 and Sec. 2.5), shared by the lattice kernel and
+// the particle-region gather.
+#pragma once
+#include "internal.hpp"
+#include "lattice.hpp"
+
+namespace turret {
+
+// ------------------------------------------------------------------ pull
+// The 27 populations arriving at cell (x, y, z): g_i = C_i(x - xi_i) from the
+// previous post-collision buffer.  x, y periodic; at the z walls the missing
+// population comes from specular reflection (free-slip: C_{mirror_z(i)} of the
+// lateral neighbour in the same row) or bounce-back (no-slip: C_{opposite(i)}
+// of the cell itself); periodic z wraps.  Physical row z sits in ring slot
+// (z + z0) mod nz.
+template <class CD>
+__device__ inline void pull(const typename CD::T *__restrict__ src, long long plane, int nx, int ny, int nz,
+                            int z0, int bc_lo, int bc_hi, int x, int y, int z, float g[Q])
+{
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    int zc = z + z0;
+    if (zc >= nz) zc -= nz;
+    const int zlo = zc == 0 ? nz - 1 : zc - 1;
+    const int zhi = zc == nz - 1 ? 0 : zc + 1;
+    const bool wlo = (z == 0) && bc_lo != BC_PERIODIC;
+    const bool whi = (z == nz - 1) && bc_hi != BC_PERIODIC;
+    const int rowc = zc * ny, rowlo = zlo * ny, rowhi = zhi * ny;
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        int sx = cx(i) == 1 ? xm : (cx(i) == -1 ? xp : x);
+        int sy = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
+        int srow = cz(i) == 1 ? rowlo : (cz(i) == -1 ? rowhi : rowc);
+        int dir = i;
+        if constexpr (cz(i) != 0) {
+            const bool wall = cz(i) == 1 ? wlo : whi;
+            const int bc = cz(i) == 1 ? bc_lo : bc_hi;
+            if (wall) {
+                srow = rowc;
+                if (bc == BC_FREESLIP) {
+                    dir = mirror_z(i);
+                } else {
+                    dir = opposite(i);
+                    sx = x;
+                    sy = y;
+                }
+            }
+        }
+        g[i] = CD::template dec<i>(src[(long long)dir * plane + (long long)((srow + sy) * nx + sx)]);
+    });
+}
+
+}  // namespace turret

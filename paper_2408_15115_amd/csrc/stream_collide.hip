@@ -1,0 +1,166 @@
+// stream_collide.hip -- the fused pull-streaming + recursive-regularized
+// collision kernel of the lattice Boltzmann step (arXiv 2408.15115, Sec. 2.1
+// and App. A), one thread per cell over SoA storage, its launch schedules,
+// and the plain streaming copy that calibrates HBM bandwidth and counters.
+#include "internal.hpp"
+#include "lattice.hpp"
+#include "pull.hpp"
+
+namespace turret {
+
+// Every population is written once per step and not read again before the
+// next step: the stores carry the non-temporal hint (measured faster; the
+// same hint on the loads is not).
+template <class CD>
+__device__ __forceinline__ void store_all(typename CD::T *__restrict__ dst, long long plane, int off, const float out[Q])
+{
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        __builtin_nontemporal_store(CD::template enc<i>(out[i]), &dst[(long long)i * plane + off]);
+    });
+}
+
+// ------------------------------------------------------------ stream-collide
+// One tile = blockDim.x consecutive cells of one case.  A case whose error
+// bits are set is masked (frozen) so the rest of a batch goes on.  The guard
+// flags non-finite density or |u| > 0.5 (bit 4) with one atomic per wave.
+template <class CD>
+__device__ __forceinline__ void stream_collide_tile(const typename CD::T *__restrict__ src, typename CD::T *__restrict__ dst,
+                                                    const CaseDev *__restrict__ cases, BodyDev *__restrict__ body, Tile tl)
+{
+    const CaseDev &cd = cases[tl.c];
+    const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
+    const int cell = tl.first + (int)threadIdx.x;
+    if (body[tl.c].err != 0 || cell >= (int)cd.cells) return;
+    const int z0 = body[tl.c].z0;
+    const int x = cell % nx;
+    const int t2 = cell / nx;
+    const int y = t2 % ny;
+    const int z = t2 / ny;
+    float g[Q];
+    pull<CD>(src + cd.pop_off, cd.plane, nx, ny, nz, z0, cd.bc_lo, cd.bc_hi, x, y, z, g);
+    const Macro M = macro(raw_moments(g));
+    const float u2 = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
+    const bool bad = !(fabsf(M.r1) < 1.0f) || !(u2 < 0.25f);
+    const unsigned long long m = __ballot(bad);
+    if (m != 0ull && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)m) - 1) atomicOr(&body[tl.c].err, 4);
+    const float tau = tau_at(cd.tau0, nz, cd.sponge, z);
+    const float om = 1.0f - 1.0f / tau;
+    float A[Q], out[Q];
+    post_collision_coeffs(M, M.u, om, A);
+    hermite_to_populations(A, out);
+    int zc = z + z0;
+    if (zc >= nz) zc -= nz;
+    store_all<CD>(dst + cd.pop_off, cd.plane, (zc * ny + y) * nx + x, out);
+}
+
+// SCHED 0: tile = workgroup; 1: XCD-grouped tiles (workgroups go
+// round-robin over the 8 XCDs, so workgroup b handles tile
+// (b mod 8) * (grid / 8) + b / 8 and neighbouring rows share one L2);
+// 2: persistent workgroups striding over the table; 3: persistent work
+// queue.  The queue is split in 8 contiguous segments with one counter each
+// (a single device-wide counter serializes every grab across the XCDs);
+// workgroup b starts on segment b mod 8, takes kQueueChunk tiles per grab and
+// moves on to the other segments when its own is exhausted.  Counters only
+// grow, so every workgroup leaves the loop.  One instantiation per schedule
+// keeps the register allocation of the plain schedules free of the loops.
+constexpr int kQueueChunk = 4;
+
+template <class CD, int SCHED>
+__global__ void __launch_bounds__(256) k_stream_collide(const typename CD::T *__restrict__ src,
+                                                        typename CD::T *__restrict__ dst,
+                                                        const CaseDev *__restrict__ cases, BodyDev *__restrict__ body,
+                                                        const Tile *__restrict__ tiles, int ntiles,
+                                                        int *__restrict__ counter)
+{
+    if constexpr (SCHED == 3) {
+        __shared__ int s_t;
+        const int per = (ntiles + 7) >> 3;
+        for (int k = 0; k < 8; k++) {
+            const int grp = (blockIdx.x + k) & 7;
+            const int lo = grp * per, hi = min(ntiles, lo + per);
+            for (;;) {
+                if (threadIdx.x == 0) s_t = lo + kQueueChunk * atomicAdd(&counter[grp], 1);
+                __syncthreads();
+                const int t0 = __builtin_amdgcn_readfirstlane(s_t);
+                __syncthreads();
+                if (t0 >= hi) break;
+                const int t1 = min(t0 + kQueueChunk, hi);
+                for (int t = t0; t < t1; t++) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
+            }
+        }
+    } else if constexpr (SCHED == 2) {
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
+    } else {
+        int t = blockIdx.x;
+        if constexpr (SCHED == 1) t = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+        if (t < ntiles) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
+    }
+}
+
+__global__ void k_reset_counter(int *counter)
+{
+    if (threadIdx.x < 8) counter[threadIdx.x] = 0;
+}
+
+// ------------------------------------------------------------ copy kernel
+// Plain 16-byte-per-lane streaming copy, grid-strided.
+__global__ void __launch_bounds__(256) k_copy(int4 *__restrict__ dst, const int4 *__restrict__ src, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s)
+{
+    const long long n = bytes / 16;
+    long long grid = (n + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(256), 0, s, (int4 *)dst, (const int4 *)src, n);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- launchers
+template <class CD>
+static hipError_t stream_collide_impl(const void *src, void *dst, const DevPtrs &p, int ntiles, int block,
+                                      int schedule, int persist_wgs, hipStream_t s)
+{
+    using T = typename CD::T;
+    int grid = ntiles;
+    if (schedule == 1) grid = (ntiles + 7) / 8 * 8;
+    if (schedule >= 2) grid = persist_wgs > 0 ? persist_wgs : 2048;
+    const T *a = (const T *)src;
+    T *b = (T *)dst;
+    switch (schedule) {
+    case 1:
+        hipLaunchKernelGGL((k_stream_collide<CD, 1>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
+                           ntiles, p.counter);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_stream_collide<CD, 2>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
+                           ntiles, p.counter);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, p.counter);
+        hipLaunchKernelGGL((k_stream_collide<CD, 3>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
+                           ntiles, p.counter);
+        break;
+    default:
+        hipLaunchKernelGGL((k_stream_collide<CD, 0>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
+                           ntiles, p.counter);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_collide(int storage, const void *src, void *dst, const DevPtrs &p, int ntiles,
+                                 int block, int schedule, int persist_wgs, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F16: return stream_collide_impl<CodecF16>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
+    case ST_BF16: return stream_collide_impl<CodecBF16>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
+    default: return stream_collide_impl<CodecF32>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
+    }
+}
+
+}  // namespace turret

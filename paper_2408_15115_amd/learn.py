@@ -42,7 +42,8 @@ def fit(net, X, Y, iters=2500, batch=8192, lr=1e-3, lr_final=3e-4, seed=0):
     """Train `net` on (X, Y); returns the last mini-batch loss (standardized
     units).  The network ends up mapping raw X to raw Y."""
     import torch
-    mx, sx = X.mean(0), X.std(0) + 1e-6
+    # the std floor keeps the folded first-layer weights inside FP16 range
+    mx, sx = X.mean(0), np.maximum(X.std(0), 1e-4)
     my, sy = Y.mean(0), Y.std(0) + 1e-9
     Xd = torch.tensor(((X - mx) / sx).astype(np.float32), device="cuda")
     Yd = torch.tensor(((Y - my) / sy).astype(np.float32), device="cuda")
@@ -55,8 +56,10 @@ def fit(net, X, Y, iters=2500, batch=8192, lr=1e-3, lr_final=3e-4, seed=0):
                        loss=loss)
     theta = net.params().astype(np.float64)
     (W1, b1), mid, (W3, b3) = _split(theta)
-    W1n = W1 / sx[None, :]
-    b1n = b1 - W1 @ (mx / sx)
+    # the device rounds weights to FP16: fold the input mean with the
+    # rounded first-layer weights so that only (x - mean) sees their rounding
+    W1n = (W1 / sx[None, :]).astype(np.float16).astype(np.float64)
+    b1n = b1 - W1n @ mx
     W3n = W3 * sy[:, None]
     b3n = b3 * sy + my
     folded = np.concatenate([W1n.ravel(), b1n, mid[0].ravel(), mid[1], W3n.ravel(), b3n]).astype(np.float32)

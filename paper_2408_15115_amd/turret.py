@@ -272,10 +272,11 @@ class Solver:
         return f, t
 
     def ibm_stats(self, case=0):
-        o = np.zeros(20)
+        o = np.zeros(24)
         self._chk("lbm_ibm_stats", lbm_ibm_stats(self._ctx, case, _dptr(o)))
         return {"resid": o[0], "resid_hist": o[1:9].copy(), "resid_hist_fallback": o[9:17].copy(),
-                "accepts": int(o[17]), "rejects": int(o[18]), "fallback": int(o[19])}
+                "accepts": int(o[17]), "rejects": int(o[18]), "fallback": int(o[19]),
+                "warm_cycles_accepted": int(o[20])}
 
     def save(self, path):
         self._chk("lbm_save", lbm_save(self._ctx, str(path).encode()))

@@ -77,5 +77,5 @@ def test_batch_is_seeded_and_in_range():
     for (ca, ba), (cb, bb) in zip(a, b):
         assert ca == cb and np.array_equal(ba["x_body"], bb["x_body"])
         assert 64 <= ca["nx"] <= 192 and ca["nz"] <= 384
-        assert 0.5 < ca["tau"] < 3.5
+        assert 0.5 < ca["tau"] <= 1.0 + 1e-12
         assert ca["sponge"] == round(0.08 * ca["nz"])
