@@ -16,6 +16,8 @@
 // stencil node (l & 3, (l >> 2) & 3, l >> 4) of the 4 x 4 x 4 weight support;
 // a workgroup takes one tile of nearby markers and stages their common box of
 // region cells in LDS.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "lattice.hpp"
 #include "pull.hpp"
@@ -675,16 +677,17 @@ __global__ void k_window_reset(typename CD::T *__restrict__ cur, DevPtrs p)
     const BodyDev &B = p.body[c];
     if (!B.shift_now) return;
     const int slab = cd.nx * cd.ny;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= cd.dz * slab) return;
-    const int zrow = idx / slab, rem = idx - zrow * slab;
-    int zc = zrow + B.z0;
-    if (zc >= cd.nz) zc -= cd.nz;
-    typename CD::T *dst = cur + cd.pop_off + (long long)zc * slab + rem;
-    Unroll<0, Q>::run([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        dst[(long long)i * cd.plane] = CD::template enc<i>(0.0f);
-    });
+    // grid-strided: the launch stays small on the many steps without a shift
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < cd.dz * slab; idx += gridDim.x * blockDim.x) {
+        const int zrow = idx / slab, rem = idx - zrow * slab;
+        int zc = zrow + B.z0;
+        if (zc >= cd.nz) zc -= cd.nz;
+        typename CD::T *dst = cur + cd.pop_off + (long long)zc * slab + rem;
+        Unroll<0, Q>::run([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            dst[(long long)i * cd.plane] = CD::template enc<i>(0.0f);
+        });
+    }
 }
 
 // --------------------------------------------------------------- launchers
@@ -774,9 +777,11 @@ template <class CD>
 static hipError_t window_impl(void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s)
 {
     hipLaunchKernelGGL(k_window_trigger, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
-    if (max_slab > 0)
-        hipLaunchKernelGGL(k_window_reset<CD>, dim3((max_slab + 255) / 256, n_cases), dim3(256), 0, s,
-                           (typename CD::T *)cur, p);
+    if (max_slab > 0) {
+        // about 2048 workgroups in all, at least 8 per case
+        const int per_case = std::max(8, std::min((max_slab + 255) / 256, 2048 / n_cases));
+        hipLaunchKernelGGL(k_window_reset<CD>, dim3(per_case, n_cases), dim3(256), 0, s, (typename CD::T *)cur, p);
+    }
     return hipGetLastError();
 }
 
