@@ -150,7 +150,8 @@ def batch_run(T, W, torch, steps, storage):
 
 
 def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, train_iters=2000, max_cycles=3):
-    """The learned form on the batched cases.  The network is trained by the
+    """The learned form on the batched cases (drag = F_z averaged over the
+    second half of the run, v_z at its end).  The network is trained by the
     library's kernels on samples of a plain run of the 64-case batch (seeds
     2408..2471) and evaluated on a held-out batch of 64 other seeds
     (2472..2535): the residual after k = 1..4 cycles from the plain start,
@@ -178,7 +179,7 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
     def run(S, steps, collect=False, hist=False):
         st = S.stream
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        X, Y, H = [], [], []
+        X, Y, H, Fz = [], [], [], []
         for k in range(steps):
             S.body_advance()
             S.lbm_step()
@@ -191,6 +192,8 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
                 sel = torch.arange(0, f.shape[0], 2, device="cuda")
                 X.append(f[sel].cpu().numpy())
                 Y.append(t[sel].cpu().numpy())
+            if k >= steps // 2:
+                Fz.append([S.body_state(c, check=False)["F"][2] for c in range(nc)])
             if k >= skip and hist:
                 sts = [S.ibm_stats(c) for c in range(nc)]
                 H.append([np.concatenate([x["resid_hist"], x["resid_hist_fallback"]]) for x in sts])
@@ -199,7 +202,7 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
         stats = [S.ibm_stats(c) for c in range(nc)]
         bs = [S.body_state(c, check=False) for c in range(nc)]
         return {"ms": sum(ms) / len(ms), "X": X, "Y": Y, "H": np.array(H), "stats": stats,
-                "Fz": np.array([b["F"][2] for b in bs]), "vz": np.array([b["v"][2] for b in bs]),
+                "Fz": np.array(Fz).mean(0), "vz": np.array([b["v"][2] for b in bs]),
                 "errs": np.array([b["err"] for b in bs])}
 
     # training data: plain run of the training batch

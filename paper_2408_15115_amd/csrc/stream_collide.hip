@@ -104,19 +104,19 @@ __global__ void k_reset_counter(int *counter)
 }
 
 // ------------------------------------------------------------ copy kernel
-// Plain 16-byte-per-lane streaming copy, grid-strided.
+// Plain copy, one 16-byte element per lane and one element per thread (a
+// flat grid reaches a higher HBM rate than a grid-strided loop).
 __global__ void __launch_bounds__(256) k_copy(int4 *__restrict__ dst, const int4 *__restrict__ src, long long n)
 {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
 hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s)
 {
     const long long n = bytes / 16;
-    long long grid = (n + 255) / 256;
-    if (grid > 65536) grid = 65536;
-    if (grid < 1) grid = 1;
+    const long long grid = (n + 255) / 256;
+    if (grid < 1 || grid > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(256), 0, s, (int4 *)dst, (const int4 *)src, n);
     return hipGetLastError();
 }
