@@ -286,6 +286,30 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
             "masked_cases": int((~ok).sum())}
 
 
+def settling_run(T, W, torch, steps=8000):
+    """Sphere settling at Re 5 (D = 16, kappa 2.7, 160 x 160 x 480): terminal
+    velocity over the Clift-Gauvin value, with the stress integral at the
+    markers (as written) and on the parallel surface 3 cells outside."""
+    import numpy as np
+    out = {"workload": "sphere D 16, Re 5, kappa 2.7, box 160x160x480, 8000 steps from rest",
+           "steps": steps}
+    for name, off in (("markers", 0.0), ("parallel_surface_3", 3.0)):
+        case, body, v_t = W.case_sphere_settling(16.0, 5.0, 2.7, force_offset=off)
+        S = T.Solver([case], [body], stream=torch.cuda.Stream())
+        v = []
+        t0 = time.perf_counter()
+        for k in range(steps // 250):
+            S.run(250)
+            if k >= steps // 250 - 8:
+                v.append(-S.body_state()["v"][2] / v_t)
+        dt = time.perf_counter() - t0
+        S.close()
+        torch.cuda.empty_cache()
+        out[name] = {"vT_over_clift_gauvin": round(float(np.mean(v)), 4),
+                     "mlups": round(case["nx"] * case["ny"] * case["nz"] * steps / dt / 1e6, 1)}
+    return out
+
+
 def cpu_baseline(case, body, steps):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the
     same body, relaxation time and walls in a 128^3 window."""
@@ -321,6 +345,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-settling", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -404,6 +429,13 @@ def main():
                 f"drag dev / weight {g['drag_dev_over_weight_vs_plain']}, v_z dev {g['vz_rel_dev_vs_plain']}")
         log(f"  plain 3 cycles: drag dev / weight {lr['plain_3cycles']['drag_dev_over_weight_vs_plain']}, "
             f"v_z dev {lr['plain_3cycles']['vz_rel_dev_vs_plain']}")
+
+    if not args.no_variants and not args.no_settling:
+        st = settling_run(T, W, torch)
+        variants["sphere_settling"] = st
+        log(f"  sphere settling, v_T / Clift-Gauvin: stress integral at the markers "
+            f"{st['markers']['vT_over_clift_gauvin']}, on the parallel surface 3 cells out "
+            f"{st['parallel_surface_3']['vT_over_clift_gauvin']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -76,7 +76,19 @@ typedef struct {
  *   kappa, volume   density ratio rho_p / rho_f and particle volume
  *   J_over_m        body-frame inertia per unit mass, 3 x 3 row-major
  *   r0, d0, v0, w0  centre, orientation rows d_0..d_2 (3 x 3 row-major),
- *                   velocity v(-1/2) and angular velocity w(-1/2) */
+ *                   velocity v(-1/2) and angular velocity w(-1/2)
+ *   force_offset    0: the force and torque are the stress integral at the
+ *                   markers, as written in Sec. 2.2 (the default);
+ *                   delta > 0: the same integral on the parallel surface at
+ *                   distance delta outside them, points X_k + delta n_k with
+ *                   the same normals and areas dS_offset.  The 4-point kernel
+ *                   at a marker averages the outer flow with the rigidly
+ *                   moving fluid inside the surface; from delta = 2 on the
+ *                   stencils see only the outer flow, and in steady flow the
+ *                   integral there equals the force the body exerts through
+ *                   the immersed forcing.  The particle region grows by delta.
+ *   dS_offset       host, n_markers: marker areas of that parallel surface
+ *                   (required when force_offset > 0; ignored otherwise) */
 typedef struct {
     int32_t n_markers;
     const double *x_body;
@@ -85,6 +97,8 @@ typedef struct {
     double kappa, volume;
     double J_over_m[9];
     double r0[3], d0[9], v0[3], w0[3];
+    double force_offset;
+    const double *dS_offset;
 } lbm_body;
 
 /* Options.
@@ -105,7 +119,14 @@ typedef struct {
  *   tile_order  0 = case after case; 1 = tiles of all cases interleaved
  *               round-robin; 2 = largest case first
  *   ibm_diag    1 = keep the residual max |U_k - I[u* + H](X_k)| after every
- *               multi-direct forcing cycle (lbm_ibm_stats), 0 = only the last */
+ *               multi-direct forcing cycle (lbm_ibm_stats), 0 = only the last
+ *   forcing     0 = the forced collision of Sec. 2.2 as printed,
+ *               f0(p, u + tau h) + (1 - 1/tau) f1: f1 carries no momentum, so
+ *               each step adds tau rho h (the default);
+ *               1 = momentum-exact variant: the first-order Hermite term of
+ *               the shift is reduced by (tau - 1) rho h, so each step adds
+ *               rho h, the velocity correction the multi-direct forcing
+ *               computes; mass and second moment as in 0 */
 typedef struct {
     int32_t storage;
     int32_t ibm_cycles;
@@ -114,7 +135,7 @@ typedef struct {
     int32_t persist_wgs;
     int32_t tile_order;
     int32_t ibm_diag;
-    int32_t reserved;
+    int32_t forcing;
 } lbm_options;
 
 /* Caller-owned device buffers (byte sizes from lbm_required_bytes):

@@ -55,12 +55,14 @@ def lib():
         L.orc_a1.argtypes = [pd, pd, pi, i32]
         L.orc_a1.restype = d
         L.orc_collide_cell.argtypes = [pd, pd, d, pd]
+        L.orc_collide_cell_v.argtypes = [pd, pd, d, i32, pd]
         L.orc_stress_cell.argtypes = [pd, d, pd, pd, pd]
         L.orc_phi.argtypes = [d]
         L.orc_phi.restype = d
         L.orc_tau_at.argtypes = [i32, d, i32, i32]
         L.orc_tau_at.restype = d
         L.orc_collide_grid.argtypes = [pi, d, i32, pd, pd, pd]
+        L.orc_collide_grid_v.argtypes = [pi, d, i32, i32, pd, pd, pd]
         L.orc_stream_grid.argtypes = [pi, i32, i32, pd, pd]
         L.orc_interp.argtypes = [pi, pd, i32, i32, pd, pd]
         L.orc_interp.restype = i32
@@ -70,6 +72,7 @@ def lib():
         L.orc_sim_new.argtypes = [pi, pi, pd, i32, pd, pd, pd, pd]
         L.orc_sim_new.restype = C.c_void_p
         L.orc_sim_free.argtypes = [C.c_void_p]
+        L.orc_sim_set_force_surface.argtypes = [C.c_void_p, d, pd]
         L.orc_sim_set_f.argtypes = [C.c_void_p, pd]
         L.orc_sim_get_f.argtypes = [C.c_void_p, pd]
         L.orc_sim_get_h.argtypes = [C.c_void_p, pd]
@@ -129,10 +132,11 @@ def a1(P1, u, idx):
     return lib().orc_a1(_pd(_f64(P1, (9,))), _pd(_f64(u)), _pi(al), len(al))
 
 
-def collide_cell(f, h, tau):
+def collide_cell(f, h, tau, forcing=0):
+    """Forced collision of one cell (Sec. 2.2); forcing 1 = momentum-exact variant."""
     out = np.zeros(27)
     hp = _pd(_f64(h)) if h is not None else None
-    lib().orc_collide_cell(_pd(_f64(f)), hp, float(tau), _pd(out))
+    lib().orc_collide_cell_v(_pd(_f64(f)), hp, float(tau), int(forcing), _pd(out))
     return out
 
 
@@ -154,13 +158,13 @@ def tau_at(nz, tau0, sponge, z):
 
 # ------------------------------------------------------------- grid ops
 # Grid arrays are (nz, ny, nx, ncomp) in the oracle's own layout.
-def collide_grid(f, tau0, sponge=0, h=None):
+def collide_grid(f, tau0, sponge=0, h=None, forcing=0):
     f = _f64(f)
     nz, ny, nx, _ = f.shape
     dims = np.array([nx, ny, nz], np.int32)
     out = np.zeros_like(f)
     hp = _pd(_f64(h)) if h is not None else None
-    lib().orc_collide_grid(_pi(dims), float(tau0), int(sponge), _pd(f), hp, _pd(out))
+    lib().orc_collide_grid_v(_pi(dims), float(tau0), int(sponge), int(forcing), _pd(f), hp, _pd(out))
     return out
 
 
@@ -211,14 +215,17 @@ class OracleSim:
 
     ``case`` and ``body`` are the plain dicts produced by the workload
     generators (keys: nx ny nz tau bc_zlo bc_zhi sponge gravity h_ini h_end
-    ibm_cycles; kappa volume J_over_m r0 d0 v0 w0 x_body n_body dS)."""
+    ibm_cycles, and optionally forcing: 0 = forced rule as printed, 1 =
+    momentum-exact variant; kappa volume J_over_m r0 d0 v0 w0 x_body n_body
+    dS, and optionally force_offset > 0 with dS_offset: the stress integral
+    on the parallel surface at that distance outside the markers)."""
 
     def __init__(self, case: dict, body: dict | None):
         L = lib()
         self.nx, self.ny, self.nz = int(case["nx"]), int(case["ny"]), int(case["nz"])
         dims = np.array([self.nx, self.ny, self.nz], np.int32)
         ip = np.array([case.get("bc_zlo", 0), case.get("bc_zhi", 0), case.get("sponge", 0),
-                       case.get("ibm_cycles", 4)], np.int32)
+                       case.get("ibm_cycles", 4), case.get("forcing", 0)], np.int32)
         dp = _f64([case["tau"], case.get("gravity", 0.0), case.get("h_ini", 0.0), case.get("h_end", 0.0)])
         if body is None:
             M = 0
@@ -235,6 +242,10 @@ class OracleSim:
         self.M = M
         self._keep = (dims, ip, dp, xb, nb, dS, bp)
         self._p = L.orc_sim_new(_pi(dims), _pi(ip), _pd(dp), M, _pd(xb), _pd(nb), _pd(dS), _pd(bp))
+        if body is not None and body.get("force_offset", 0.0) > 0.0:
+            dSo = _f64(body["dS_offset"])
+            self._keep = self._keep + (dSo,)
+            L.orc_sim_set_force_surface(self._p, float(body["force_offset"]), _pd(dSo))
 
     def __del__(self):
         if getattr(self, "_p", None):

@@ -239,7 +239,7 @@ static void offeq_moment(const double *f, const double *f0, double P1[3][3])
  * C_i = f^(0)_i(p, u + tau h) + (1 - 1/tau) f^(1)_i, i.e. the forced evolution
  * rule before the shift x -> x + xi_i.  Readings: f^(1) is built from P^(1) of
  * the unshifted f^(0)(p,u); u is sum xi f / sum f of the incoming f. */
-void orc_collide_cell(const double *f, const double *h, double tau, double *out)
+void orc_collide_cell_v(const double *f, const double *h, double tau, int32_t forcing, double *out)
 {
     orc_init();
     double rho, p, u[3], f0[Q], f1[Q], fs[Q], P1[3][3], P1f[9], us[3];
@@ -252,6 +252,23 @@ void orc_collide_cell(const double *f, const double *h, double tau, double *out)
     for (int d = 0; d < 3; d++) us[d] = u[d] + tau * (h ? h[d] : 0.0);
     orc_feq(p, us, fs);
     for (int i = 0; i < Q; i++) out[i] = fs[i] + (1.0 - 1.0 / tau) * f1[i];
+    /* Momentum-exact variant (forcing = 1): f^(0)(p, u + tau h) carries the
+     * momentum rho (u + tau h) and f^(1) none, so the rule as printed adds
+     * tau rho h per step.  Removing (tau - 1) rho h from the first-order
+     * Hermite term, w_i (xi_i . m) / cs^2 with m = (tau - 1) rho h, leaves the
+     * added momentum at rho h; mass and the second moment are unchanged
+     * because sum_i w_i xi_i = 0 and sum_i w_i xi_i xi_i xi_i = 0. */
+    if (forcing == 1 && h) {
+        for (int i = 0; i < Q; i++) {
+            double xh = g_xi[i][0] * h[0] + g_xi[i][1] * h[1] + g_xi[i][2] * h[2];
+            out[i] -= g_w[i] * (tau - 1.0) * rho * xh / CS2;
+        }
+    }
+}
+
+void orc_collide_cell(const double *f, const double *h, double tau, double *out)
+{
+    orc_collide_cell_v(f, h, tau, 0, out);
 }
 
 /* --------------------------------------------------------- stress (Sec. 2.1)
@@ -289,6 +306,7 @@ typedef struct {
     int nx, ny, nz;
     double tau0;
     int bc_lo, bc_hi, sponge;
+    int forcing;    /* 0: forced rule as printed; 1: momentum-exact variant */
 } dom_t;
 
 /* Relaxation time at height z.  Sponge reading (Sec. 2.5): tau rises linearly
@@ -322,7 +340,7 @@ static void collide_grid(const dom_t *D, const double *f, const double *h, doubl
         for (int y = 0; y < D->ny; y++)
             for (int x = 0; x < D->nx; x++) {
                 size_t c = cell(D, x, y, z);
-                orc_collide_cell(f + Q * c, h ? h + 3 * c : NULL, tau, C + Q * c);
+                orc_collide_cell_v(f + Q * c, h ? h + 3 * c : NULL, tau, D->forcing, C + Q * c);
             }
     }
 }
@@ -357,12 +375,18 @@ static void stream_grid(const dom_t *D, const double *C, double *f)
             }
 }
 
+void orc_collide_grid_v(const int32_t *dims, double tau0, int32_t sponge, int32_t forcing, const double *f,
+                        const double *h, double *C)
+{
+    orc_init();
+    dom_t D = {dims[0], dims[1], dims[2], tau0, 0, 0, sponge, forcing};
+    collide_grid(&D, f, h, C);
+}
+
 void orc_collide_grid(const int32_t *dims, double tau0, int32_t sponge, const double *f,
                       const double *h, double *C)
 {
-    orc_init();
-    dom_t D = {dims[0], dims[1], dims[2], tau0, 0, 0, sponge};
-    collide_grid(&D, f, h, C);
+    orc_collide_grid_v(dims, tau0, sponge, 0, f, h, C);
 }
 
 void orc_stream_grid(const int32_t *dims, int32_t bc_lo, int32_t bc_hi, const double *C, double *f)
@@ -548,11 +572,14 @@ typedef struct {
     unsigned char *need;           /* nodes covered by a marker stencil */
     double *X, *N, *U, *hk, *tmp;  /* markers at t+1 */
     int pending;                   /* window shift to apply to the next post-collision state */
+    double force_offset;           /* 0: stress integral at the markers; > 0: on the parallel
+                                      surface X_k + force_offset n_k, areas dSo */
+    double *dSo;
     int64_t shifts, steps;
     int err;
 } orc_sim;
 
-/* dims[3]; ip[4] = bc_lo bc_hi sponge cycles; dp[4] = tau0 gravity h_ini h_end;
+/* dims[3]; ip[5] = bc_lo bc_hi sponge cycles forcing; dp[4] = tau0 gravity h_ini h_end;
  * body[29] = kappa vol Jm(9) r(3) d(9) v(3) w(3). */
 orc_sim *orc_sim_new(const int32_t *dims, const int32_t *ip, const double *dp, int32_t M,
                      const double *xb, const double *nb, const double *dS, const double *body)
@@ -565,6 +592,7 @@ orc_sim *orc_sim_new(const int32_t *dims, const int32_t *ip, const double *dp, i
     S->D.bc_lo = ip[0];
     S->D.bc_hi = ip[1];
     S->D.sponge = ip[2];
+    S->D.forcing = ip[4];
     S->cycles = ip[3];
     S->D.tau0 = dp[0];
     S->B.gravity = dp[1];
@@ -605,12 +633,25 @@ orc_sim *orc_sim_new(const int32_t *dims, const int32_t *ip, const double *dp, i
     return S;
 }
 
+/* Force surface variant: the stress integral on the parallel surface at
+ * distance delta outside the markers, with its marker areas dSo (M values). */
+void orc_sim_set_force_surface(orc_sim *S, double delta, const double *dSo)
+{
+    S->force_offset = delta;
+    free(S->dSo);
+    S->dSo = NULL;
+    if (delta > 0.0 && S->M > 0) {
+        S->dSo = (double *)malloc(S->M * sizeof(double));
+        memcpy(S->dSo, dSo, S->M * sizeof(double));
+    }
+}
+
 void orc_sim_free(orc_sim *S)
 {
     if (!S) return;
     free(S->f); free(S->C); free(S->h); free(S->sig); free(S->uu); free(S->need);
     free(S->xb); free(S->nb); free(S->dS); free(S->X); free(S->N); free(S->U);
-    free(S->hk); free(S->tmp);
+    free(S->hk); free(S->tmp); free(S->dSo);
     free(S);
 }
 
@@ -702,6 +743,14 @@ static void stress_at_stencils(orc_sim *S)
         for (int c = 0; c < 4; c++)
             for (int b = 0; b < 4; b++)
                 for (int a = 0; a < 4; a++) S->need[cell(D, node[0][a], node[1][b], node[2][c])] = 1;
+        if (S->force_offset > 0.0) {
+            double Y[3];
+            for (int a = 0; a < 3; a++) Y[a] = S->X[3 * k + a] + S->force_offset * S->N[3 * k + a];
+            if (stencil(D, Y, node, wt)) { S->err = -1; return; }
+            for (int c = 0; c < 4; c++)
+                for (int b = 0; b < 4; b++)
+                    for (int a = 0; a < 4; a++) S->need[cell(D, node[0][a], node[1][b], node[2][c])] = 1;
+        }
     }
     #pragma omp parallel for schedule(static)
     for (int z = 0; z < D->nz; z++)
@@ -722,17 +771,21 @@ static void force_torque(orc_sim *S)
 {
     double F[3] = {0, 0, 0}, T[3] = {0, 0, 0}, Fp[3] = {0, 0, 0};
     for (int k = 0; k < S->M; k++) {
-        double sg[10], s[3], rel[3], rs[3];
-        interp(&S->D, S->sig, 10, S->X + 3 * k, sg);
+        double sg[10], s[3], rel[3], rs[3], Y[3];
         const double *nk = S->N + 3 * k;
+        /* evaluation point: the marker, or its image on the parallel surface
+         * at distance force_offset along the outward normal (same normal) */
+        for (int a = 0; a < 3; a++) Y[a] = S->X[3 * k + a] + S->force_offset * nk[a];
+        const double area = S->force_offset > 0.0 ? S->dSo[k] : S->dS[k];
+        interp(&S->D, S->sig, 10, Y, sg);
         for (int a = 0; a < 3; a++) s[a] = sg[3 * a] * nk[0] + sg[3 * a + 1] * nk[1] + sg[3 * a + 2] * nk[2];
         double p = sg[9];   /* interpolated pressure: the -pI part of sigma */
-        for (int a = 0; a < 3; a++) rel[a] = S->X[3 * k + a] - S->B.r[a];
+        for (int a = 0; a < 3; a++) rel[a] = Y[a] - S->B.r[a];
         cross(rel, s, rs);
         for (int a = 0; a < 3; a++) {
-            F[a] += S->dS[k] * s[a];
-            T[a] += S->dS[k] * rs[a];
-            Fp[a] += S->dS[k] * (-p) * nk[a];
+            F[a] += area * s[a];
+            T[a] += area * rs[a];
+            Fp[a] += area * (-p) * nk[a];
         }
     }
     memcpy(S->F, F, sizeof F);

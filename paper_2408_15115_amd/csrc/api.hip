@@ -32,9 +32,10 @@ struct Plan {
     std::vector<MarkerTile> mtiles;
     long long max_tiles = 0;    // tile table capacity: the count at the smallest block (64)
     int Mtot = 0, maxL3 = 0, max_slab = 0;
+    int force_surface = 0;    // some case evaluates its force on the parallel surface
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
-        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_mtiles, aux_bytes;
+        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, aux_bytes;
     int block = 256;
 };
 
@@ -58,12 +59,17 @@ std::string check_case(const lbm_case &c, const lbm_body *b)
             for (int a = 0; a < 3; a++) s += b->x_body[3 * k + a] * b->x_body[3 * k + a];
             rb = std::max(rb, std::sqrt(s));
         }
-        const double lo = b->r0[2] - rb, hi = b->r0[2] + rb;
+        if (!(b->force_offset >= 0.0) || b->force_offset > 64.0) return "force_offset must be in [0, 64]";
+        if (b->force_offset > 0.0 && !b->dS_offset) return "force_offset > 0 needs dS_offset";
+        const double ro = rb + b->force_offset;   // reach of the force-evaluation points
+        const double lo = b->r0[2] - ro, hi = b->r0[2] + ro;
         if (std::floor(lo) - 1 < 0 || std::floor(hi) + 2 > c.nz - 1) {
-            std::snprintf(msg, sizeof msg, "markers closer than two cells to a z wall (z in [%g, %g], nz %d)", lo, hi, c.nz);
+            std::snprintf(msg, sizeof msg,
+                          "markers (or force points) closer than two cells to a z wall (z in [%g, %g], nz %d)", lo, hi,
+                          c.nz);
             return msg;
         }
-        const int L = (int)std::ceil(2.0 * (1.001 * rb + 0.01)) + 6;
+        const int L = (int)std::ceil(2.0 * (1.001 * ro + 0.01)) + 6;
         if (L > c.nx || L > c.ny) return "particle region wider than the box";
         double det = b->J_over_m[0] * (b->J_over_m[4] * b->J_over_m[8] - b->J_over_m[5] * b->J_over_m[7]) -
                      b->J_over_m[1] * (b->J_over_m[3] * b->J_over_m[8] - b->J_over_m[5] * b->J_over_m[6]) +
@@ -83,6 +89,7 @@ std::string check_options(const lbm_options *o)
     if (o->persist_wgs < 0 || o->persist_wgs > (1 << 20)) return "persist_wgs must be 0..2^20";
     if (o->tile_order < 0 || o->tile_order > 2) return "tile_order must be 0, 1 or 2";
     if (o->ibm_diag < 0 || o->ibm_diag > 1) return "ibm_diag must be 0 or 1";
+    if (o->forcing < 0 || o->forcing > 1) return "forcing must be 0 or 1";
     return "";
 }
 
@@ -181,6 +188,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         d.bc_hi = k.bc_zhi;
         d.sponge = k.sponge_cells;
         d.tau0 = (float)k.tau;
+        d.forcing = opt ? opt->forcing : 0;
         d.h_ini = k.h_ini;
         d.h_end = k.h_end;
         d.dz = k.h_end > 0.0 ? (int)std::lround(k.h_ini - k.h_end) : 0;
@@ -190,6 +198,8 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         d.pop_off = pop;
         pop += Q * d.plane;
         d.M = b ? std::max(0, b->n_markers) : 0;
+        d.force_offset = (b && d.M > 0) ? b->force_offset : 0.0;
+        if (d.force_offset > 0.0) P.force_surface = 1;
         d.marker_off = moff;
         if (d.M > 0) tile_markers(*b, c, moff, P.morder, P.mtiles);
         moff += d.M;
@@ -200,7 +210,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
                 for (int a = 0; a < 3; a++) s += b->x_body[3 * q + a] * b->x_body[3 * q + a];
                 rb = std::max(rb, std::sqrt(s));
             }
-            d.L = (int)std::ceil(2.0 * (1.001 * rb + 0.01)) + 6;
+            d.L = (int)std::ceil(2.0 * (1.001 * (rb + d.force_offset) + 0.01)) + 6;
         } else {
             d.L = 0;
         }
@@ -241,6 +251,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_feat = take(sizeof(float) * kMlpIn * M);
     P.off_h0 = take(sizeof(double) * 3 * M);
     P.off_hs = take(sizeof(double) * M);
+    P.off_dSo = take(sizeof(double) * M);
     P.off_mtiles = take(sizeof(MarkerTile) * std::max<size_t>(P.mtiles.size(), 1));
     P.aux_bytes = o;
     (void)eb;
@@ -367,11 +378,13 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.feat = (float *)(a + P.off_feat);
     p.h0 = (double *)(a + P.off_h0);
     p.hs = (double *)(a + P.off_hs);
+    p.dSo = (double *)(a + P.off_dSo);
 
     // host images of the descriptors, body states and markers
     std::vector<BodyDev> bd(n_cases);
     std::vector<int> mcase(std::max(P.Mtot, 1));
     std::vector<double> xb(3 * std::max(P.Mtot, 1)), nb(3 * std::max(P.Mtot, 1)), dS(std::max(P.Mtot, 1));
+    std::vector<double> dSo(std::max(P.Mtot, 1), 0.0);
     for (int c = 0; c < n_cases; c++) {
         BodyDev &B = bd[c];
         std::memset(&B, 0, sizeof B);
@@ -408,10 +421,11 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
                     s += b.x_body[3 * q + k] * b.x_body[3 * q + k];
                 }
                 dS[g] = b.dS[q];
+                if (d.force_offset > 0.0) dSo[g] = b.dS_offset[q];
                 mcase[g] = c;
                 rb = std::max(rb, std::sqrt(s));
             }
-            B.Rb = 1.001 * rb + 0.01;
+            B.Rb = 1.001 * (rb + d.force_offset) + 0.01;
             for (int k = 0; k < 3; k++) B.org[k] = (int)std::floor(B.r[k] - B.Rb) - 2;
         }
     }
@@ -428,6 +442,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
         (he = hipMemcpyAsync(p.xb, xb.data(), sizeof(double) * xb.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (he = hipMemcpyAsync(p.nb, nb.data(), sizeof(double) * nb.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (he = hipMemcpyAsync(p.dS, dS.data(), sizeof(double) * dS.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (he = hipMemcpyAsync(p.dSo, dSo.data(), sizeof(double) * dSo.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (P.mtiles.size() &&
          (he = hipMemcpyAsync(p.mtiles, P.mtiles.data(), sizeof(MarkerTile) * P.mtiles.size(), hipMemcpyHostToDevice,
                               s)) != hipSuccess) ||
@@ -463,7 +478,7 @@ static int32_t do_ibm(lbm_ctx *ctx)
     HIPCHK(ctx,
            launch_ibm(ctx->opt.storage, ctx->pop[1 - ctx->cur], ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.Mtot,
                       (int)ctx->plan.mtiles.size(), ctx->plan.maxL3, ctx->opt.ibm_cycles, ctx->warm_mode, ctx->mlp_th16, ctx->mlp_cycles,
-                      ctx->opt.ibm_diag, ctx->stream),
+                      ctx->opt.ibm_diag, ctx->plan.force_surface, ctx->stream),
            "ibm_couple");
     ctx->needs_ibm = false;
     return LBM_OK;
@@ -531,8 +546,8 @@ int32_t lbm_set_schedule(lbm_ctx *ctx, const lbm_options *opt)
     std::string e = check_options(opt);
     if (!e.empty()) return fail(ctx, LBM_EINVAL, e);
     const int cyc = opt->ibm_cycles ? opt->ibm_cycles : 4;
-    if (opt->storage != ctx->opt.storage || cyc != ctx->opt.ibm_cycles)
-        return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage or ibm_cycles");
+    if (opt->storage != ctx->opt.storage || cyc != ctx->opt.ibm_cycles || opt->forcing != ctx->opt.forcing)
+        return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage, ibm_cycles or forcing");
     if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "lbm_set_schedule between lbm_step and ibm_couple");
     const int block = opt->block ? opt->block : 256;
     build_tiles(ctx->plan, block, opt->tile_order);

@@ -18,8 +18,9 @@ struct CaseDev {
     long long pop_off;      // element offset of the case block in the population buffers
     long long reg_off;      // cell offset of the case region in the region pool
     float tau0;
-    int pad;
+    int forcing;            // 0: forced rule as printed; 1: momentum-exact variant
     double h_ini, h_end;
+    double force_offset;    // 0: stress integral at the markers; > 0: on the parallel surface
 };
 
 // Dynamic FP64 rigid-body state of one case plus the ring origin and region
@@ -83,6 +84,7 @@ struct DevPtrs {
     float *feat;     // per-marker warm-start features (12)
     double *h0;      // per-marker plain start U - I[u*] (3)
     double *hs;      // per-marker scale of the warm-start features, |h0| + |h(t-1)|
+    double *dSo;     // per-marker areas of the parallel force surface (cases with force_offset > 0)
 };
 
 // ---------------------------------------------------------------- launchers
@@ -94,9 +96,10 @@ hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
 // residual is at or below its gate, at most warm_cycles of them; cases that
 // do not get there rerun `cycles` plain cycles.  diag keeps the residual of
 // every cycle.
+// force_surface: some case evaluates the force on its parallel surface.
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
                       int n_mtiles, int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles,
-                      int diag, hipStream_t s);
+                      int diag, int force_surface, hipStream_t s);
 hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s);
 hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s);

@@ -122,6 +122,11 @@ __global__ void k_markers(DevPtrs p, int Mtot)
     }
     const int fz = (int)floor(X[2]);
     if (fz - 1 < 0 || fz + 2 > p.cases[c].nz - 1) atomicOr(&p.body[c].err, 1);
+    const double dl = p.cases[c].force_offset;
+    if (dl > 0.0) {
+        const int gz = (int)floor(X[2] + dl * N[2]);
+        if (gz - 1 < 0 || gz + 2 > p.cases[c].nz - 1) atomicOr(&p.body[c].err, 1);
+    }
 }
 
 // ------------------------------------------------------------ region fields
@@ -358,6 +363,55 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p)
 #pragma unroll
         for (int f = 0; f < kRegFields; f++) v[f] = wave_sum(v[f]);
         if (lane == 0) force_epilogue(p, k, B, v);
+    }
+}
+
+// Force surface variant: the stress integral on the parallel surface at
+// distance force_offset outside the markers (points X_k + delta n_k, same
+// normals, areas dSo).  One wavefront per marker; overwrites the marker's
+// force, torque and pressure parts written by the tile kernel.
+__global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int Mtot)
+{
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= Mtot) return;
+    const int c = p.mcase[k];
+    const CaseDev &cd = p.cases[c];
+    const BodyDev &B = p.body[c];
+    if (B.err != 0 || !(cd.force_offset > 0.0)) return;
+    const int L3 = cd.L * cd.L * cd.L;
+    const float *R = p.reg + cd.reg_off * kRegFields;
+    const double nk[3] = {p.N[3 * k], p.N[3 * k + 1], p.N[3 * k + 2]};
+    double Y[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) Y[a] = p.X[3 * k + a] + cd.force_offset * nk[a];
+    const Node nd = stencil_node(Y, lane, cd, B);
+    // fields 0 (rho - 1) and 4..9 (sigma xx yy zz xy xz yz)
+    double v[7];
+#pragma unroll
+    for (int f = 0; f < 7; f++) {
+        const int fld = f == 0 ? 0 : f + 3;
+        v[f] = nd.q >= 0 ? nd.W * (double)R[fld * L3 + nd.q] : 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < 7; f++) v[f] = wave_sum(v[f]);
+    if (lane != 0) return;
+    const double pr = (double)CS2 * v[0];
+    const double sg[3][3] = {{v[1], v[4], v[5]}, {v[4], v[2], v[6]}, {v[5], v[6], v[3]}};
+    double s[3], rel[3], ts[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        s[a] = sg[a][0] * nk[0] + sg[a][1] * nk[1] + sg[a][2] * nk[2];
+        rel[a] = Y[a] - B.r[a];
+    }
+    cross3(rel, s, ts);
+    const double dA = p.dSo[k];
+    double *o = p.part + (long long)kPart * k;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        o[a] = dA * s[a];
+        o[3 + a] = dA * ts[a];
+        o[6 + a] = dA * (-pr) * nk[a];
     }
 }
 
@@ -613,7 +667,8 @@ __global__ void k_targets(DevPtrs p, int Mtot, float *out)
 
 // Forced collision of Sec. 2.2: the lattice kernel wrote
 // f0(rho, u) + (1 - 1/tau) f1; cells carrying an immersed force get
-// f0(rho, u + tau h) - f0(rho, u) added.
+// f0(rho, u + tau h) - f0(rho, u) added (in the momentum-exact variant less
+// the first-order term w_i xi_i . (tau - 1) rho h / cs^2).
 template <class CD>
 __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
 {
@@ -638,6 +693,14 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
                          u[2] + tau * (float)((double)h2 * kFixInv)};
     float A[Q], d[Q];
     shift_coeffs(rho, u, us, A);
+    if (cd.forcing == 1) {
+        // momentum-exact variant: the first-order coefficients (m = e_x, e_y,
+        // e_z) become rho h instead of rho tau h
+        const float k = (tau - 1.0f) * rho;
+        A[1] -= k * (float)((double)h0 * kFixInv);
+        A[3] -= k * (float)((double)h1 * kFixInv);
+        A[9] -= k * (float)((double)h2 * kFixInv);
+    }
     hermite_to_populations(A, d);
     const int gx = wrapi(B.org[0] + a, cd.nx), gy = wrapi(B.org[1] + b, cd.ny);
     int zc = gz + B.z0;
@@ -700,7 +763,7 @@ hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s)
 template <class CD>
 static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot, int n_mtiles,
                            int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles, int diag,
-                           hipStream_t s)
+                           int force_surface, hipStream_t s)
 {
     using T = typename CD::T;
     const dim3 blk(256);
@@ -710,6 +773,7 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     hipLaunchKernelGGL(k_markers, mark_grid, blk, 0, s, p, Mtot);
     hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
     hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p);
+    if (force_surface) hipLaunchKernelGGL(k_offset_force, dim3((Mtot + 3) / 4), blk, 0, s, p, Mtot);
     hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), dim3(1024), 0, s, p);
     // one sequence of multi-direct forcing cycles (Sec. 2.2, l = 1..4): spread
     // the increment, then interpolate and form the next increment; the
@@ -751,19 +815,19 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
 
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
                       int n_mtiles, int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles,
-                      int diag, hipStream_t s)
+                      int diag, int force_surface, hipStream_t s)
 {
     if (Mtot == 0) return hipSuccess;
     switch (storage) {
     case ST_F16:
         return ibm_impl<CodecF16>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16, warm_cycles,
-                                  diag, s);
+                                  diag, force_surface, s);
     case ST_BF16:
         return ibm_impl<CodecBF16>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16,
-                                   warm_cycles, diag, s);
+                                   warm_cycles, diag, force_surface, s);
     default:
         return ibm_impl<CodecF32>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16, warm_cycles,
-                                  diag, s);
+                                  diag, force_surface, s);
     }
 }
 

@@ -154,16 +154,33 @@ def _body(kappa, volume, Jm, xb, nb, dS, r0, d0=None, v0=None, w0=None):
             "w0": np.zeros(3) if w0 is None else np.asarray(w0, np.float64)}
 
 
-def sphere_fibonacci_body(R, n, kappa, r0, **kw):
+def _with_force_surface(body, delta, dS_offset):
+    """Attach the parallel surface at distance delta outside the markers on
+    which the force may be evaluated: its marker areas (input geometry)."""
+    if delta > 0.0:
+        body["force_offset"] = float(delta)
+        body["dS_offset"] = np.ascontiguousarray(dS_offset, np.float64)
+    return body
+
+
+def sphere_fibonacci_body(R, n, kappa, r0, force_offset=0.0, **kw):
     xb, nb, dS = fibonacci_sphere(n, R)
-    return _body(kappa, 4.0 / 3.0 * math.pi * R ** 3, 0.4 * R * R * np.eye(3), xb, nb, dS, r0, **kw)
+    b = _body(kappa, 4.0 / 3.0 * math.pi * R ** 3, 0.4 * R * R * np.eye(3), xb, nb, dS, r0, **kw)
+    return _with_force_surface(b, force_offset, dS * ((R + force_offset) / R) ** 2)
 
 
-def mesh_body(V, F, kappa, r0, **kw):
+def mesh_body(V, F, kappa, r0, force_offset=0.0, **kw):
+    """Markers at the vertices of a closed triangle mesh.  With force_offset
+    > 0 the mesh is also offset along the vertex normals by that distance and
+    the vertex areas of the offset mesh are attached."""
     vol, cen, Jm = mesh_mass_properties(V, F)
     Vc = V - cen
     dS, nb = vertex_areas_normals(Vc, F)
-    return _body(kappa, vol, Jm, Vc, nb, dS, r0, **kw)
+    b = _body(kappa, vol, Jm, Vc, nb, dS, r0, **kw)
+    if force_offset > 0.0:
+        dSo, _ = vertex_areas_normals(Vc + force_offset * nb, F)
+        _with_force_surface(b, force_offset, dSo)
+    return b
 
 
 def ellipsoid_mesh(a, b, c, freq):
@@ -253,6 +270,26 @@ def case_ellipsoid_tall(seed=2408, nx=256, ny=256, nz=768, semi=(32.0, 32.0, 16.
 
 def _freq_for_area(area, target_dS=0.5):
     return max(4, int(round(math.sqrt(area / target_dS / 10.0))))
+
+
+def case_sphere_settling(D=16.0, re=5.0, kappa=2.7, force_offset=0.0, w_d=10, h_d=30):
+    """A sphere of diameter D (lattice units) settling from rest in a
+    w = w_d D by w_d D by h = h_d D box (the paper's w* = 10, h* = 30 domain of
+    its low-Re sphere cases): periodic x/y, free-slip top and bottom, sponge
+    0.08 h, window re-injection from 0.75 h by 4 D.  Gravity from the
+    Clift-Gauvin drag so that the unbounded terminal velocity is v_T (0.02,
+    lowered to keep tau <= 1).  Markers at the vertices of a geodesic mesh
+    with mean area about 0.5.  Returns (case, body, v_T)."""
+    R = D / 2.0
+    w, h = int(round(w_d * D)), int(round(h_d * D))
+    V, F = geodesic_sphere(_freq_for_area(4 * math.pi * R * R))
+    v_t = min(V_TERMINAL_LU, re * TAU_MAX_BATCH_NU / D)
+    nu, tau, g = lattice_scaling(D, re, kappa, v_t)
+    z0 = 0.75 * h
+    body = mesh_body(V * R, F, kappa, [(w - 1) / 2.0, (w - 1) / 2.0, z0], force_offset=force_offset)
+    case = make_case(w, w, h, tau, BC_FREESLIP, BC_FREESLIP, int(round(0.08 * h)), g, h_ini=z0, h_end=z0 - 4 * D)
+    case["re"], case["d_eq"], case["v_terminal"] = re, D, v_t
+    return case, body, v_t
 
 
 def batch_cases(n_cases=64, seed0=2408, max_h=384):

@@ -108,6 +108,59 @@ def test_rotating_sphere_matches_oracle(T, orc):
     assert max_rel(S.populations(), oracle_to_soa(o.post_collision())) < 1e-5
 
 
+def test_momentum_exact_forcing_matches_oracle(T, orc):
+    """The momentum-exact variant of the forced rule (each step adds rho h):
+    force, torque, body and populations against the oracle's variant, and
+    different from the rule as printed."""
+    case, body = small_sphere(tau=0.8, gravity=3e-5)
+    cv = dict(case, forcing=1)
+    o = orc.OracleSim(cv, body)
+    S = T.Solver([case], [body], forcing=1)
+    L = T.Solver([case], [body], forcing=0)
+    o.step(40)
+    S.run(40)
+    L.run(40)
+    st, ost, lit = S.body_state(), o.body_state(), L.body_state()
+    Fs = np.linalg.norm(ost["F"])
+    say(f"  momentum-exact: |F| {Fs:.3e}, F err {np.max(np.abs(st['F'] - ost['F'])) / Fs:.3e}, "
+        f"printed-rule F differs by {np.max(np.abs(lit['F'] - ost['F'])) / Fs:.3e}")
+    assert np.max(np.abs(st["F"] - ost["F"])) < 1e-4 * Fs
+    assert np.max(np.abs(st["T"] - ost["T"])) < 1e-4 * Fs * 3.0
+    assert np.max(np.abs(st["v"] - ost["v"])) < 1e-6 * np.linalg.norm(ost["v"])
+    assert max_rel(S.populations(), oracle_to_soa(o.post_collision())) < 1e-5
+    assert np.max(np.abs(lit["F"] - ost["F"])) > 2e-3 * Fs
+
+
+def test_force_surface_variant_matches_oracle(T, orc):
+    """Stress integral on the parallel surface 3 cells outside the markers:
+    force, torque, body and populations against the oracle's variant (with a
+    tilted, spinning sphere, so the torque arm and the normals matter)."""
+    n = 32
+    case = W.make_case(n, n, 48, 0.75, W.BC_FREESLIP, W.BC_FREESLIP, 0, 3e-5)
+    body = W.sphere_fibonacci_body(4.0, 300, 2.0, [(n - 1) / 2 + 0.3, (n - 1) / 2 - 0.2, 23.5],
+                                   w0=np.array([1e-3, -2e-3, 3e-3]), force_offset=3.0,
+                                   d0=W.rotation_matrix([1.0, 2.0, 0.5], 0.4).T)
+    o = orc.OracleSim(case, body)
+    S = T.Solver([case], [body])
+    plain = dict(body)
+    plain.pop("force_offset")
+    plain.pop("dS_offset")
+    Pm = T.Solver([case], [plain])
+    o.step(40)
+    S.run(40)
+    Pm.run(40)
+    st, ost, pm = S.body_state(), o.body_state(), Pm.body_state()
+    Fs = np.linalg.norm(ost["F"])
+    say(f"  force surface: |F| {Fs:.3e}, F err {np.max(np.abs(st['F'] - ost['F'])) / Fs:.3e}, "
+        f"marker-surface F_z / offset F_z {pm['F'][2] / ost['F'][2]:.3f}")
+    assert np.max(np.abs(st["F"] - ost["F"])) < 1e-4 * Fs
+    assert np.max(np.abs(st["T"] - ost["T"])) < 1e-4 * max(np.linalg.norm(ost["T"]), Fs * 4.0)
+    assert np.max(np.abs(st["v"] - ost["v"])) < 1e-6 * np.linalg.norm(ost["v"])
+    assert np.allclose(st["w"], ost["w"], rtol=1e-6, atol=1e-12)
+    assert max_rel(S.populations(), oracle_to_soa(o.post_collision())) < 1e-5
+    assert abs(pm["F"][2] - ost["F"][2]) > 1e-2 * Fs
+
+
 def test_graph_replay_equals_eager(T):
     import torch
     case, body = small_sphere()

@@ -1,0 +1,49 @@
+"""Physics validation of the coupled solver against a closed form: the
+terminal settling velocity of a sphere (Re 5, density ratio 2.7, the
+paper's w* = 10, h* = 30 domain) against the Clift-Gauvin value the gravity
+was set from (Sec. 3.2).
+
+The stress integral at the markers, as written in Sec. 2.2, averages the
+outer flow with the rigidly moving fluid inside the surface (the 4-point
+kernel straddles it) and sees about half the drag: the sphere settles far
+too fast.  On the parallel surface 3 cells outside, the integral sees the
+force the body exerts through the forcing, and the terminal velocity comes
+within the confinement and diffuse-interface effects of this resolution
+(D = 16 cells) of the design value.  Not a parity test: both runs are
+compared with physics, not with the oracle."""
+import numpy as np
+import pytest
+
+from paper_2408_15115_amd import workloads as W
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_2408_15115_amd import turret
+    return turret
+
+
+def terminal_ratio(T, force_offset, steps=8000):
+    case, body, v_t = W.case_sphere_settling(16.0, 5.0, 2.7, force_offset=force_offset)
+    S = T.Solver([case], [body])
+    v = []
+    for k in range(steps // 250):
+        S.run(250)
+        if k >= steps // 250 - 8:
+            v.append(-S.body_state()["v"][2] / v_t)
+    S.close()
+    return float(np.mean(v))
+
+
+def test_sphere_terminal_velocity_vs_clift_gauvin(T):
+    printed = terminal_ratio(T, 0.0)
+    surface = terminal_ratio(T, 3.0)
+    say(f"  v_T / Clift-Gauvin value: stress integral at the markers {printed:.3f}, "
+        f"on the parallel surface 3 cells out {surface:.3f}")
+    assert printed > 1.4
+    assert 0.85 < surface < 1.05

@@ -214,6 +214,28 @@ def test_collision_conservation_and_stress_relaxation(orc, seed):
     assert np.allclose(second, expect, atol=1e-15, rtol=0)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_momentum_exact_variant_adds_rho_h(orc, seed):
+    """Momentum-exact variant of the forced rule: the momentum added per step
+    is exactly rho h (not tau rho h); mass and the second moment are those of
+    the rule as printed; at tau = 1 the two coincide."""
+    rng = np.random.default_rng(900 + seed)
+    xi, w = orc.lattice()
+    f = random_cell(orc, rng)
+    tau = rng.uniform(0.51, 2.0)
+    h = 1e-3 * rng.standard_normal(3)
+    lit = orc.collide_cell(f, h, tau)
+    ex = orc.collide_cell(f, h, tau, forcing=1)
+    rho = f.sum()
+    u = (f @ xi) / rho
+    assert abs(ex.sum() - rho) < 1e-15
+    assert np.allclose(ex @ xi, rho * (u + h), atol=1e-16, rtol=0)
+    sec = lambda g: (g[:, None, None] * xi[:, :, None] * xi[:, None, :]).sum(0)
+    assert np.allclose(sec(ex), sec(lit), atol=1e-15, rtol=0)
+    assert np.allclose(orc.collide_cell(f, h, 1.0, forcing=1), orc.collide_cell(f, h, 1.0), atol=1e-17, rtol=0)
+    assert np.array_equal(orc.collide_cell(f, None, tau, forcing=1), orc.collide_cell(f, None, tau))
+
+
 def test_tau_one_is_equilibrium(orc):
     rng = np.random.default_rng(7)
     xi, _ = orc.lattice()

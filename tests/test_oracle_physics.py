@@ -71,6 +71,49 @@ def test_channel_flow_under_uniform_immersed_force(orc, tau):
     assert abs(off.mean()) < 3 * g
 
 
+@pytest.mark.parametrize("tau", [0.6, 0.8])
+def test_channel_flow_momentum_exact_variant(orc, tau):
+    """With the momentum-exact variant a uniform h is a body force of density
+    rho h per step: the steady profile is the plane Poiseuille parabola of
+    curvature -h / nu, whatever tau."""
+    xi, w = orc.lattice()
+    nz, g = 16, 1e-6
+    nu = (tau - 0.5) / 3
+    f = np.tile(w, (nz, 1, 1, 1))
+    H = np.zeros((nz, 1, 1, 3))
+    H[..., 0] = g
+    steps = int(25 * nz * nz / (math.pi ** 2 * nu))
+    for _ in range(steps):
+        f = orc.stream_grid(orc.collide_grid(f, tau, 0, H, forcing=1), 2, 2)
+    u = ((f @ xi[:, 0]) / f.sum(-1)).ravel()
+    curv = u[2:] - 2 * u[1:-1] + u[:-2]
+    assert np.allclose(curv, -g / nu, rtol=1e-7)
+
+
+@pytest.mark.parametrize("offset", [0.0, 3.0])
+def test_stress_integral_of_linear_pressure_is_enclosed_volume(orc, offset):
+    """A fluid at rest with density linear in z has sigma = -p I, p = cs^2
+    (rho - 1), up to O(alpha^2) after one stream.  By the divergence theorem
+    the stress integral over a closed surface is then -grad p times the
+    enclosed volume: 4/3 pi R^3 at the markers, 4/3 pi (R + delta)^3 on the
+    parallel surface of the force-surface variant; the torque vanishes."""
+    _, w = orc.lattice()
+    n, nz, R, alpha = 32, 40, 5.0, 1e-6
+    zc = (nz - 1) / 2
+    case = W.make_case(n, n, nz, 0.8, W.BC_FREESLIP, W.BC_FREESLIP, 0, 0.0)
+    body = W.sphere_fibonacci_body(R, 2000, 2.0, [(n - 1) / 2, (n - 1) / 2, zc], force_offset=offset)
+    o = orc.OracleSim(case, body)
+    rho = 1.0 + alpha * (np.arange(nz) - zc)
+    o.set_populations(np.broadcast_to(rho[:, None, None, None] * w, (nz, n, n, 27)))
+    o.step(1)
+    st = o.body_state()
+    expect = -CS2 * alpha * 4.0 / 3.0 * math.pi * (R + offset) ** 3
+    assert abs(st["F"][2] - expect) < 2e-3 * abs(expect)
+    assert np.max(np.abs(st["F"][:2])) < 1e-3 * abs(expect)
+    assert np.max(np.abs(st["T"])) < 1e-3 * abs(expect) * R
+    assert abs(st["F_pressure"][2] - expect) < 2e-3 * abs(expect)
+
+
 def small_case(nz=32, h_end=0.0, bc=W.BC_FREESLIP, markers=200, R=3.0, zc=None, gravity=1e-5, sponge=0):
     n = 20
     zc = (nz - 1) / 2 if zc is None else zc
