@@ -167,12 +167,23 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
     from paper_2408_15115_amd import autotune, learn
     seed_train, seed_eval, nc = 2408, 2408 + 64, 64
 
-    def solver(seed0, diag, cycles=4):
+    def solver(seed0, diag, cycles=4, serial=1):
+        # serial coupling: the events around ibm_couple then time the coupling itself
         batch = W.batch_cases(nc, seed0=seed0)
         cases = [c for c, _ in batch]
         sched = autotune.tune(cases, storage=storage)["best"]
         return T.Solver(cases, [b for _, b in batch], storage=storage, stream=torch.cuda.Stream(), ibm_diag=diag,
-                        ibm_cycles=cycles, **sched)
+                        ibm_cycles=cycles, serial_ibm=serial, **sched)
+
+    def step_ms(S, steps=60):
+        """Whole coupled step with the coupling beside the lattice kernel."""
+        S.run(5)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(S.stream)
+        S.run(steps)
+        e1.record(S.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
 
     def close(S):
         S.close()
@@ -246,6 +257,16 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
     S = solver(seed_eval, 0, cycles=3)
     plain3 = run(S, eval_steps)
     close(S)
+    # whole steps with the coupling beside the lattice kernel (the default)
+    overlapped = {}
+    for name, mode, m in (("plain", None, None), ("learned_gated", T.LBM_WARM_MLP, net)):
+        S = solver(seed_eval, 0, serial=0)
+        if mode is not None:
+            S.set_warm_start(mode, m, max_cycles)
+            for c in range(nc):
+                S.set_ibm_gate(c, float(gates[c]))
+        overlapped[name] = round(step_ms(S), 4)
+        close(S)
     ok = ok0 & (gated["mlp"]["errs"] == 0) & (gated["previous_h"]["errs"] == 0) & (plain3["errs"] == 0)
     live = np.where(ok)[0]
 
@@ -280,6 +301,7 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
             "ibm_ms_per_step_plain_4cycles": round(plain["ms"], 4),
             "learned_gated": gated_report(gated["mlp"]),
             "previous_h_gated": gated_report(gated["previous_h"]),
+            "step_ms_coupling_beside_lattice": overlapped,
             "plain_3cycles": {"ibm_ms_per_step": round(plain3["ms"], 4),
                               "drag_dev_over_weight_vs_plain": dev(plain3, "Fz"),
                               "vz_rel_dev_vs_plain": dev(plain3, "vz")},
@@ -427,6 +449,7 @@ def main():
             log(f"  {k}: IBM {lr['ibm_ms_per_step_plain_4cycles']:.3f} -> {g['ibm_ms_per_step']:.3f} ms/step, "
                 f"acceptance {g['acceptance']:.2f}, mean cycles {g['mean_cycles_accepted']}, "
                 f"drag dev / weight {g['drag_dev_over_weight_vs_plain']}, v_z dev {g['vz_rel_dev_vs_plain']}")
+        log(f"  whole step with the coupling beside the lattice kernel: {lr['step_ms_coupling_beside_lattice']} ms")
         log(f"  plain 3 cycles: drag dev / weight {lr['plain_3cycles']['drag_dev_over_weight_vs_plain']}, "
             f"v_z dev {lr['plain_3cycles']['vz_rel_dev_vs_plain']}")
 

@@ -126,7 +126,10 @@ typedef struct {
  *               1 = momentum-exact variant: the first-order Hermite term of
  *               the shift is reduced by (tau - 1) rho h, so each step adds
  *               rho h, the velocity correction the multi-direct forcing
- *               computes; mass and second moment as in 0 */
+ *               computes; mass and second moment as in 0
+ *   serial_ibm  0 = ibm_couple runs the coupling on a second stream beside
+ *               the step's lattice kernel (the default); 1 = on the context
+ *               stream after it (to time the coupling alone) */
 typedef struct {
     int32_t storage;
     int32_t ibm_cycles;
@@ -136,6 +139,7 @@ typedef struct {
     int32_t tile_order;
     int32_t ibm_diag;
     int32_t forcing;
+    int32_t serial_ibm;
 } lbm_options;
 
 /* Caller-owned device buffers (byte sizes from lbm_required_bytes):
@@ -170,7 +174,15 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
  *     body_advance -> lbm_step -> ibm_couple -> window_shift
  * Without particles only lbm_step is needed.  ibm_couple without a preceding
  * lbm_step, or lbm_step twice without ibm_couple while particles exist,
- * return LBM_ESTATE. */
+ * return LBM_ESTATE.
+ * The coupling of a step reads the body state and the populations the
+ * lattice kernel reads, never its output, so ibm_couple runs everything up to
+ * h(t+1) on a second stream the library owns, concurrently with that step's
+ * lattice kernel (an event recorded on the context stream just before the
+ * lattice kernel starts it); the forced correction and every later call wait
+ * for it on the context stream.  Work on the context stream therefore stays
+ * ordered as the calls are made, and graph capture on it takes the second
+ * stream along. */
 
 /* Table 1 event (2), Sec. 2.3: advance every body with F(t), T(t):
  * a = g + F/(kappa V); v += a; r += v; w += M^-1 (J/m)^-1 M T/(kappa V);

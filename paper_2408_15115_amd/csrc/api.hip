@@ -90,6 +90,7 @@ std::string check_options(const lbm_options *o)
     if (o->tile_order < 0 || o->tile_order > 2) return "tile_order must be 0, 1 or 2";
     if (o->ibm_diag < 0 || o->ibm_diag > 1) return "ibm_diag must be 0 or 1";
     if (o->forcing < 0 || o->forcing > 1) return "forcing must be 0 or 1";
+    if (o->serial_ibm < 0 || o->serial_ibm > 1) return "serial_ibm must be 0 or 1";
     return "";
 }
 
@@ -278,7 +279,20 @@ struct lbm_ctx {
     int warm_mode = LBM_WARM_NONE;        // start of the multi-direct forcing
     const _Float16 *mlp_th16 = nullptr;   // warm-start network (FP16 weights)
     int mlp_cycles = 0;
+    // The coupling of a step reads only the body state and the buffer the
+    // lattice kernel reads, so it runs on `side` beside the lattice kernel:
+    // `fork` is recorded on `stream` just before the lattice kernel, `join`
+    // on `side` after the forcing cycles; the forced correction and
+    // everything after it wait for `join` on `stream`.
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     std::string err;
+    ~lbm_ctx()
+    {
+        if (join) (void)hipEventDestroy(join);
+        if (fork) (void)hipEventDestroy(fork);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 
 struct lbm_mlp {
@@ -448,6 +462,13 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
                               s)) != hipSuccess) ||
         (he = hipStreamSynchronize(s)) != hipSuccess)
         return bail(LBM_EHIP, std::string("init: ") + hipGetErrorString(he));
+    // side stream of the coupling (default priority, no implicit
+    // synchronization with the null stream) and its two events
+    if (ctx->has_body &&
+        ((he = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking)) != hipSuccess ||
+         (he = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming)) != hipSuccess ||
+         (he = hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming)) != hipSuccess))
+        return bail(LBM_EHIP, std::string("init: side stream: ") + hipGetErrorString(he));
     *out = ctx;
     return LBM_OK;
 }
@@ -463,6 +484,7 @@ static int32_t do_body_advance(lbm_ctx *ctx)
 static int32_t do_lbm_step(lbm_ctx *ctx)
 {
     const int src = ctx->cur, dst = 1 - ctx->cur;
+    if (ctx->has_body) HIPCHK(ctx, hipEventRecord(ctx->fork, ctx->stream), "record fork event");
     HIPCHK(ctx,
            launch_stream_collide(ctx->opt.storage, ctx->pop[src], ctx->pop[dst], ctx->p, (int)ctx->plan.tiles.size(),
                                  ctx->opt.block, ctx->opt.schedule, ctx->opt.persist_wgs, ctx->stream),
@@ -475,11 +497,21 @@ static int32_t do_lbm_step(lbm_ctx *ctx)
 static int32_t do_ibm(lbm_ctx *ctx)
 {
     if (!ctx->has_body) return LBM_OK;
+    const bool serial = ctx->opt.serial_ibm != 0;
+    hipStream_t cs = serial ? ctx->stream : ctx->side;
+    if (!serial) HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->fork, 0), "side stream waits for the fork event");
     HIPCHK(ctx,
            launch_ibm(ctx->opt.storage, ctx->pop[1 - ctx->cur], ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.Mtot,
                       (int)ctx->plan.mtiles.size(), ctx->plan.maxL3, ctx->opt.ibm_cycles, ctx->warm_mode, ctx->mlp_th16, ctx->mlp_cycles,
-                      ctx->opt.ibm_diag, ctx->plan.force_surface, ctx->stream),
+                      ctx->opt.ibm_diag, ctx->plan.force_surface, cs),
            "ibm_couple");
+    if (!serial) {
+        HIPCHK(ctx, hipEventRecord(ctx->join, ctx->side), "record join event");
+        HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->join, 0), "stream waits for the coupling");
+    }
+    HIPCHK(ctx, launch_correct(ctx->opt.storage, ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.Mtot, ctx->plan.maxL3,
+                               ctx->stream),
+           "forced correction");
     ctx->needs_ibm = false;
     return LBM_OK;
 }
@@ -548,6 +580,8 @@ int32_t lbm_set_schedule(lbm_ctx *ctx, const lbm_options *opt)
     const int cyc = opt->ibm_cycles ? opt->ibm_cycles : 4;
     if (opt->storage != ctx->opt.storage || cyc != ctx->opt.ibm_cycles || opt->forcing != ctx->opt.forcing)
         return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage, ibm_cycles or forcing");
+    if (opt->serial_ibm != ctx->opt.serial_ibm) drop_graph(ctx);
+    ctx->opt.serial_ibm = opt->serial_ibm;
     if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "lbm_set_schedule between lbm_step and ibm_couple");
     const int block = opt->block ? opt->block : 256;
     build_tiles(ctx->plan, block, opt->tile_order);
@@ -994,6 +1028,7 @@ int32_t lbm_destroy(lbm_ctx *ctx)
 {
     if (!ctx) return LBM_OK;
     drop_graph(ctx);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     delete ctx;
     return LBM_OK;
 }

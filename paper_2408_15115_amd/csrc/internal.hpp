@@ -97,9 +97,13 @@ hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
 // do not get there rerun `cycles` plain cycles.  diag keeps the residual of
 // every cycle.
 // force_surface: some case evaluates the force on its parallel surface.
+// launch_ibm runs the coupling up to h(t+1) (it reads `prev`, the buffer the
+// lattice kernel reads, not the lattice kernel's output, so it may run
+// beside it); launch_correct then adds the forcing to `cur`.
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
                       int n_mtiles, int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles,
                       int diag, int force_surface, hipStream_t s);
+hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3, hipStream_t s);
 hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s);
 hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s);

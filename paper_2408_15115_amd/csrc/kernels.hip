@@ -809,8 +809,26 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     } else {
         sequence(cycles, 0, 0);
     }
-    hipLaunchKernelGGL(k_correct<CD>, reg_grid, blk, 0, s, (T *)cur, p);
+    (void)cur;
     return hipGetLastError();
+}
+
+template <class CD>
+static hipError_t correct_impl(void *cur, const DevPtrs &p, int n_cases, int maxL3, hipStream_t s)
+{
+    const dim3 reg_grid((maxL3 + 255) / 256, n_cases);
+    hipLaunchKernelGGL(k_correct<CD>, reg_grid, dim3(256), 0, s, (typename CD::T *)cur, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3, hipStream_t s)
+{
+    if (Mtot == 0) return hipSuccess;
+    switch (storage) {
+    case ST_F16: return correct_impl<CodecF16>(cur, p, n_cases, maxL3, s);
+    case ST_BF16: return correct_impl<CodecBF16>(cur, p, n_cases, maxL3, s);
+    default: return correct_impl<CodecF32>(cur, p, n_cases, maxL3, s);
+    }
 }
 
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,

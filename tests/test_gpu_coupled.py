@@ -161,6 +161,21 @@ def test_force_surface_variant_matches_oracle(T, orc):
     assert abs(pm["F"][2] - ost["F"][2]) > 1e-2 * Fs
 
 
+def test_concurrent_coupling_equals_serial(T):
+    """The coupling beside the lattice kernel (second stream) and after it on
+    the context stream give identical results: only the schedule differs."""
+    case, body = small_sphere(h_end=19.5 - 1e-6, h_ini=25.5, sponge=5)
+    A = T.Solver([case], [body], serial_ibm=0)
+    B = T.Solver([case], [body], serial_ibm=1)
+    A.run(30)
+    B.run(30)
+    a, b = A.body_state(), B.body_state()
+    assert a["shifts"] >= 1
+    for k in ("F", "T", "r", "v", "w", "d"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(A.populations(), B.populations())
+
+
 def test_graph_replay_equals_eager(T):
     import torch
     case, body = small_sphere()
