@@ -391,8 +391,32 @@ def main():
     if copy_gbps:
         log(f"streaming copy: {copy_gbps:.0f} GB/s")
 
+    def coupling_mode(storage, steps=100):
+        """serial_ibm value with the shorter coupled step: the coupling beside
+        the lattice kernel (0) or after it (1)."""
+        best = None
+        for serial in (0, 1):
+            S = T.Solver([case], [body], storage=storage, stream=torch.cuda.Stream(), serial_ibm=serial)
+            S.run(10)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(S.stream)
+            S.run(steps)
+            e1.record(S.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            S.close()
+            del S
+            torch.cuda.empty_cache()
+            if best is None or ms < best[1]:
+                best = (serial, ms)
+        return best[0]
+
+    modes = {}
+
     def run_storage(storage, steps, warmup, graph):
-        S = T.Solver([case], [body], storage=storage, stream=torch.cuda.Stream())
+        if storage not in modes:
+            modes[storage] = coupling_mode(storage)
+        S = T.Solver([case], [body], storage=storage, stream=torch.cuda.Stream(), serial_ibm=modes[storage])
         total_ms, k1_ms = timed_steps(S, torch, steps, warmup)
         k1 = timed_steps.last_k1
         n = min(100, len(k1))
@@ -482,7 +506,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "falling-frame box 256x256x768, tilted oblate ellipsoid 32/32/16 with 12252 "
                                "markers, kappa 2.7, Re 100, sponge 61, free-slip z, 4 IBM cycles",
-                   "cells": cells, "markers": M, "storage": args.storage, "launch": "eager, one stream",
+                   "cells": cells, "markers": M, "storage": args.storage, "launch": "eager",
+                   "coupling": "after the lattice kernel" if modes.get(args.storage) else "beside the lattice kernel",
                    "graph_ms_per_step": (round(main_run["graph_ms_per_step"], 5)
                                          if main_run["graph_ms_per_step"] else None)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
