@@ -46,12 +46,15 @@ enum {
 };
 
 enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 };                   /* population storage */
-enum { LBM_BC_PERIODIC = 0, LBM_BC_FREESLIP = 1, LBM_BC_NOSLIP = 2 }; /* z walls */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_FREESLIP = 1, LBM_BC_NOSLIP = 2, LBM_BC_PRESSURE = 3 }; /* z walls */
 
 /* One settling case (Sec. 2.5 and Table 2).
  *   nx, ny, nz      lattice cells, each >= 8; x, y periodic
  *   bc_zlo, bc_zhi  LBM_BC_*: walls halfway below z = 0 and above z = nz-1;
- *                   free-slip = specular reflection, no-slip = bounce-back
+ *                   free-slip = specular reflection, no-slip = bounce-back,
+ *                   pressure = constant density 1 (Sec. 3 domain top): the
+ *                   entering populations by anti-bounce-back,
+ *                   f_i = -C_opp(i) + 2 w_i, velocity terms of O(u^2) dropped
  *   sponge_cells    0, or >= 2: tau rises linearly from tau to 1 over the top
  *                   sponge_cells rows (Sec. 2.5)
  *   tau             relaxation time > 0.5 (nu = (tau - 1/2)/3, Sec. 2.1)

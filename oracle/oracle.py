@@ -19,7 +19,7 @@ SRC_PATH = os.path.join(_HERE, "orc.c")
 # A test of the pins themselves may point this at a build with a planted mistake.
 _OVERRIDE = os.environ.get("ORACLE_LIB_OVERRIDE")
 
-BC_PERIODIC, BC_FREESLIP, BC_NOSLIP = 0, 1, 2
+BC_PERIODIC, BC_FREESLIP, BC_NOSLIP, BC_PRESSURE = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:

@@ -300,7 +300,7 @@ double orc_phi(double r)
 
 /* ------------------------------------------------------------- domain */
 
-enum { BC_PERIODIC = 0, BC_FREESLIP = 1, BC_NOSLIP = 2 };
+enum { BC_PERIODIC = 0, BC_FREESLIP = 1, BC_NOSLIP = 2, BC_PRESSURE = 3 };
 
 typedef struct {
     int nx, ny, nz;
@@ -347,8 +347,10 @@ static void collide_grid(const dom_t *D, const double *f, const double *h, doubl
 
 /* Streaming f_i(x) = C_i(x - xi_i) (Sec. 2.1 evolution rule, pull form).
  * Lateral walls periodic (Sec. 2.5).  z walls at z = -1/2 and nz - 1/2:
- * periodic, free-slip (specular reflection, xi_z flipped) or no-slip
- * (bounce-back, whole xi reversed). */
+ * periodic, free-slip (specular reflection, xi_z flipped), no-slip
+ * (bounce-back, whole xi reversed) or constant pressure (the Sec. 3 domain
+ * top, density rho0 = 1 at the halfway plane; reading: anti-bounce-back
+ * f_i = -C_opp(i) + 2 w_i rho0, the O(u^2) wall-velocity terms dropped). */
 static void stream_grid(const dom_t *D, const double *C, double *f)
 {
     #pragma omp parallel for schedule(static)
@@ -368,6 +370,8 @@ static void stream_grid(const dom_t *D, const double *C, double *f)
                     } else if (bc == BC_FREESLIP) {
                         int im = 9 * (-g_xi[i][2] + 1) + 3 * (g_xi[i][1] + 1) + (g_xi[i][0] + 1);
                         f[Q * c + i] = C[Q * cell(D, sx, sy, z) + im];
+                    } else if (bc == BC_PRESSURE) {
+                        f[Q * c + i] = -C[Q * c + (Q - 1 - i)] + 2.0 * g_w[i] * RHO0;
                     } else {
                         f[Q * c + i] = C[Q * c + (Q - 1 - i)];
                     }

@@ -47,7 +47,7 @@ std::string check_case(const lbm_case &c, const lbm_body *b)
     if (!(c.tau > 0.5)) return "tau must be > 0.5";
     if (c.sponge_cells < 0 || c.sponge_cells == 1 || c.sponge_cells > c.nz) return "sponge_cells must be 0 or 2..nz";
     for (int bc : {c.bc_zlo, c.bc_zhi})
-        if (bc < LBM_BC_PERIODIC || bc > LBM_BC_NOSLIP) return "unknown z boundary code";
+        if (bc < LBM_BC_PERIODIC || bc > LBM_BC_PRESSURE) return "unknown z boundary code";
     if ((c.bc_zlo == LBM_BC_PERIODIC) != (c.bc_zhi == LBM_BC_PERIODIC)) return "periodic z needs both walls periodic";
     if (c.h_end > 0.0 && std::lround(c.h_ini - c.h_end) >= c.nz) return "window shift exceeds the box height";
     if (b && b->n_markers > 0) {

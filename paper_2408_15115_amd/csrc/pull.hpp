@@ -11,9 +11,10 @@ namespace turret {
 // The 27 populations arriving at cell (x, y, z): g_i = C_i(x - xi_i) from the
 // previous post-collision buffer.  x, y periodic; at the z walls the missing
 // population comes from specular reflection (free-slip: C_{mirror_z(i)} of the
-// lateral neighbour in the same row) or bounce-back (no-slip: C_{opposite(i)}
-// of the cell itself); periodic z wraps.  Physical row z sits in ring slot
-// (z + z0) mod nz.
+// lateral neighbour in the same row), bounce-back (no-slip: C_{opposite(i)}
+// of the cell itself) or anti-bounce-back at density 1 (constant pressure:
+// f_i = -C_{opposite(i)} + 2 w_i, i.e. g_i = -g^C_{opposite(i)} in deviation
+// form); periodic z wraps.  Physical row z sits in ring slot (z + z0) mod nz.
 template <class CD>
 __device__ inline void pull(const typename CD::T *__restrict__ src, long long plane, int nx, int ny, int nz,
                             int z0, int bc_lo, int bc_hi, int x, int y, int z, float g[Q])
@@ -33,6 +34,7 @@ __device__ inline void pull(const typename CD::T *__restrict__ src, long long pl
         int sy = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
         int srow = cz(i) == 1 ? rowlo : (cz(i) == -1 ? rowhi : rowc);
         int dir = i;
+        bool neg = false;
         if constexpr (cz(i) != 0) {
             const bool wall = cz(i) == 1 ? wlo : whi;
             const int bc = cz(i) == 1 ? bc_lo : bc_hi;
@@ -44,10 +46,12 @@ __device__ inline void pull(const typename CD::T *__restrict__ src, long long pl
                     dir = opposite(i);
                     sx = x;
                     sy = y;
+                    neg = bc == BC_PRESSURE;
                 }
             }
         }
-        g[i] = CD::template dec<i>(src[(long long)dir * plane + (long long)((srow + sy) * nx + sx)]);
+        const float v = CD::template dec<i>(src[(long long)dir * plane + (long long)((srow + sy) * nx + sx)]);
+        g[i] = neg ? -v : v;
     });
 }
 

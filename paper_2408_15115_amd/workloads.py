@@ -27,7 +27,7 @@ import math
 
 import numpy as np
 
-BC_PERIODIC, BC_FREESLIP, BC_NOSLIP = 0, 1, 2
+BC_PERIODIC, BC_FREESLIP, BC_NOSLIP, BC_PRESSURE = 0, 1, 2, 3
 V_TERMINAL_LU = 0.02
 
 # D3Q27 weights w_i = prod_d w1(xi_d), w1(0) = 2/3, w1(+-1) = 1/6; direction
@@ -272,11 +272,12 @@ def _freq_for_area(area, target_dS=0.5):
     return max(4, int(round(math.sqrt(area / target_dS / 10.0))))
 
 
-def case_sphere_settling(D=16.0, re=5.0, kappa=2.7, force_offset=0.0, w_d=10, h_d=30):
+def case_sphere_settling(D=16.0, re=5.0, kappa=2.7, force_offset=0.0, w_d=10, h_d=30, domain="free-slip"):
     """A sphere of diameter D (lattice units) settling from rest in a
     w = w_d D by w_d D by h = h_d D box (the paper's w* = 10, h* = 30 domain of
-    its low-Re sphere cases): periodic x/y, free-slip top and bottom, sponge
-    0.08 h, window re-injection from 0.75 h by 4 D.  Gravity from the
+    its low-Re sphere cases): periodic x/y, free-slip top and bottom (or, with
+    domain="paper", the Sec. 3 layout: no-slip bottom, constant-pressure top),
+    sponge 0.08 h, window re-injection from 0.75 h by 4 D.  Gravity from the
     Clift-Gauvin drag so that the unbounded terminal velocity is v_T (0.02,
     lowered to keep tau <= 1).  Markers at the vertices of a geodesic mesh
     with mean area about 0.5.  Returns (case, body, v_T)."""
@@ -287,7 +288,8 @@ def case_sphere_settling(D=16.0, re=5.0, kappa=2.7, force_offset=0.0, w_d=10, h_
     nu, tau, g = lattice_scaling(D, re, kappa, v_t)
     z0 = 0.75 * h
     body = mesh_body(V * R, F, kappa, [(w - 1) / 2.0, (w - 1) / 2.0, z0], force_offset=force_offset)
-    case = make_case(w, w, h, tau, BC_FREESLIP, BC_FREESLIP, int(round(0.08 * h)), g, h_ini=z0, h_end=z0 - 4 * D)
+    lo, hi = (BC_NOSLIP, BC_PRESSURE) if domain == "paper" else (BC_FREESLIP, BC_FREESLIP)
+    case = make_case(w, w, h, tau, lo, hi, int(round(0.08 * h)), g, h_ini=z0, h_end=z0 - 4 * D)
     case["re"], case["d_eq"], case["v_terminal"] = re, D, v_t
     return case, body, v_t
 

@@ -29,11 +29,15 @@ CASES = [
     (12, 10, 14, 0.55, W.BC_NOSLIP, 0),
     (64, 8, 9, 1.3, W.BC_FREESLIP, 4),
     (33, 17, 19, 0.51, W.BC_NOSLIP, 6),
+    # the paper's domain: no-slip bottom, constant-pressure top, sponge
+    (20, 12, 16, 0.7, (W.BC_NOSLIP, W.BC_PRESSURE), 5),
+    (12, 9, 13, 0.9, (W.BC_PRESSURE, W.BC_FREESLIP), 0),
 ]
 
 
 def run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed, storage="f32", amp=0.05):
-    case = W.make_case(nx, ny, nz, tau, bc, bc, sponge)
+    lo, hi = bc if isinstance(bc, tuple) else (bc, bc)
+    case = W.make_case(nx, ny, nz, tau, lo, hi, sponge)
     f0 = W.random_populations(seed, nx, ny, nz, amp=amp)
     say(f"lattice parity nx={nx} ny={ny} nz={nz} tau={tau} bc={bc} sponge={sponge} steps={steps} {storage}")
     S = T.Solver([case], storage=storage)
@@ -43,11 +47,11 @@ def run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed, storage="f32", am
     gpu = S.populations()
     # the library keeps post-collision states: its input is C_0, so the
     # oracle streams it first, then alternates collide/stream
-    f = orc.stream_grid(f0, bc, bc)
+    f = orc.stream_grid(f0, lo, hi)
     for s in range(steps):
         C = orc.collide_grid(f, tau, sponge)
         if s + 1 < steps:
-            f = orc.stream_grid(C, bc, bc)
+            f = orc.stream_grid(C, lo, hi)
     S.close()
     return gpu, oracle_to_soa(C)
 
@@ -58,14 +62,15 @@ def test_one_step_matches_oracle(T, orc, nx, ny, nz, tau, bc, sponge):
     assert max_rel(gpu, ref) < TOL_F32
 
 
-@pytest.mark.parametrize("nx,ny,nz,tau,bc,sponge", CASES[1:4])
+@pytest.mark.parametrize("nx,ny,nz,tau,bc,sponge", CASES[1:4] + CASES[5:6])
 def test_many_steps_match_oracle(T, orc, nx, ny, nz, tau, bc, sponge):
     gpu, ref = run_pair(T, orc, nx, ny, nz, tau, bc, sponge, 25, seed=nx + ny, amp=0.02)
     assert max_rel(gpu, ref) < TOL_F32
 
 
-def test_rest_state_stays_exactly_at_rest(T):
-    case = W.make_case(16, 16, 16, 0.6, W.BC_FREESLIP, W.BC_FREESLIP, 5)
+@pytest.mark.parametrize("lo,hi", [(W.BC_FREESLIP, W.BC_FREESLIP), (W.BC_NOSLIP, W.BC_PRESSURE)])
+def test_rest_state_stays_exactly_at_rest(T, lo, hi):
+    case = W.make_case(16, 16, 16, 0.6, lo, hi, 5)
     S = T.Solver([case])
     S.run(10)
     f = S.populations()

@@ -114,6 +114,43 @@ def test_stress_integral_of_linear_pressure_is_enclosed_volume(orc, offset):
     assert abs(st["F_pressure"][2] - expect) < 2e-3 * abs(expect)
 
 
+@pytest.mark.parametrize("forcing", [0, 1])
+def test_pressure_top_hydrostatic_column(orc, forcing):
+    """Constant-pressure top (density 1 on the halfway plane above the top
+    row) over a no-slip bottom, uniform downward h: the steady column is
+    hydrostatic, rho - 1 = 3 a (nz - 1/2 - z) with a = tau g for the forced
+    rule as printed (each step adds tau rho h) and a = g for the
+    momentum-exact variant."""
+    xi, w = orc.lattice()
+    nz, tau, g = 12, 0.8, 1e-5
+    f = np.tile(w, (nz, 1, 1, 1))
+    H = np.zeros((nz, 1, 1, 3))
+    H[..., 2] = -g
+    for _ in range(6000):
+        f = orc.stream_grid(orc.collide_grid(f, tau, 0, H, forcing=forcing), orc.BC_NOSLIP, orc.BC_PRESSURE)
+    rho = f.sum(-1).ravel()
+    a = tau * g if forcing == 0 else g
+    expect = 3 * a * (nz - 0.5 - np.arange(nz))
+    assert np.max(np.abs((rho - 1) - expect)) < 1e-3 * expect.max()
+
+
+def test_pressure_top_drains_to_unit_density(orc):
+    """A closed column at rest with density 1.01 and a constant-pressure top
+    loses its excess mass through the top: the density relaxes to 1
+    everywhere (with walls on both ends the mass would stay)."""
+    xi, w = orc.lattice()
+    nz, tau = 12, 0.8
+    f = np.tile(1.01 * w, (nz, 1, 1, 1))
+    m0 = f.sum() - nz
+    for _ in range(8000):
+        f = orc.stream_grid(orc.collide_grid(f, tau, 0), orc.BC_NOSLIP, orc.BC_PRESSURE)
+    assert np.max(np.abs(f.sum(-1) - 1.0)) < 1e-4 * m0 / nz
+    g = np.tile(1.01 * w, (nz, 1, 1, 1))
+    for _ in range(200):
+        g = orc.stream_grid(orc.collide_grid(g, tau, 0), orc.BC_NOSLIP, orc.BC_NOSLIP)
+    assert abs(g.sum() - nz - m0) < 1e-12
+
+
 def small_case(nz=32, h_end=0.0, bc=W.BC_FREESLIP, markers=200, R=3.0, zc=None, gravity=1e-5, sponge=0):
     n = 20
     zc = (nz - 1) / 2 if zc is None else zc
