@@ -132,7 +132,11 @@ typedef struct {
  *               computes; mass and second moment as in 0
  *   serial_ibm  0 = ibm_couple runs the coupling on a second stream beside
  *               the step's lattice kernel (the default); 1 = on the context
- *               stream after it (to time the coupling alone) */
+ *               stream after it (to time the coupling alone)
+ *   collision   0 = the recursive-regularized collision of Sec. 2.1 / App. A
+ *               (the default); 1 = BGK for comparison: the same rule with the
+ *               raw off-equilibrium f - f0(p, u) in place of f1 (all its
+ *               moments relax by 1 - 1/tau); runs with schedule 0 */
 typedef struct {
     int32_t storage;
     int32_t ibm_cycles;
@@ -143,6 +147,7 @@ typedef struct {
     int32_t ibm_diag;
     int32_t forcing;
     int32_t serial_ibm;
+    int32_t collision;
 } lbm_options;
 
 /* Caller-owned device buffers (byte sizes from lbm_required_bytes):

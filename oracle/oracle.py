@@ -56,6 +56,7 @@ def lib():
         L.orc_a1.restype = d
         L.orc_collide_cell.argtypes = [pd, pd, d, pd]
         L.orc_collide_cell_v.argtypes = [pd, pd, d, i32, pd]
+        L.orc_collide_cell_m.argtypes = [pd, pd, d, i32, i32, pd]
         L.orc_stress_cell.argtypes = [pd, d, pd, pd, pd]
         L.orc_phi.argtypes = [d]
         L.orc_phi.restype = d
@@ -63,6 +64,7 @@ def lib():
         L.orc_tau_at.restype = d
         L.orc_collide_grid.argtypes = [pi, d, i32, pd, pd, pd]
         L.orc_collide_grid_v.argtypes = [pi, d, i32, i32, pd, pd, pd]
+        L.orc_collide_grid_m.argtypes = [pi, d, i32, i32, i32, pd, pd, pd]
         L.orc_stream_grid.argtypes = [pi, i32, i32, pd, pd]
         L.orc_interp.argtypes = [pi, pd, i32, i32, pd, pd]
         L.orc_interp.restype = i32
@@ -132,11 +134,12 @@ def a1(P1, u, idx):
     return lib().orc_a1(_pd(_f64(P1, (9,))), _pd(_f64(u)), _pi(al), len(al))
 
 
-def collide_cell(f, h, tau, forcing=0):
-    """Forced collision of one cell (Sec. 2.2); forcing 1 = momentum-exact variant."""
+def collide_cell(f, h, tau, forcing=0, collision=0):
+    """Forced collision of one cell (Sec. 2.2); forcing 1 = momentum-exact
+    variant; collision 1 = BGK (raw off-equilibrium) for comparison."""
     out = np.zeros(27)
     hp = _pd(_f64(h)) if h is not None else None
-    lib().orc_collide_cell_v(_pd(_f64(f)), hp, float(tau), int(forcing), _pd(out))
+    lib().orc_collide_cell_m(_pd(_f64(f)), hp, float(tau), int(forcing), int(collision), _pd(out))
     return out
 
 
@@ -158,13 +161,14 @@ def tau_at(nz, tau0, sponge, z):
 
 # ------------------------------------------------------------- grid ops
 # Grid arrays are (nz, ny, nx, ncomp) in the oracle's own layout.
-def collide_grid(f, tau0, sponge=0, h=None, forcing=0):
+def collide_grid(f, tau0, sponge=0, h=None, forcing=0, collision=0):
     f = _f64(f)
     nz, ny, nx, _ = f.shape
     dims = np.array([nx, ny, nz], np.int32)
     out = np.zeros_like(f)
     hp = _pd(_f64(h)) if h is not None else None
-    lib().orc_collide_grid_v(_pi(dims), float(tau0), int(sponge), int(forcing), _pd(f), hp, _pd(out))
+    lib().orc_collide_grid_m(_pi(dims), float(tau0), int(sponge), int(forcing), int(collision), _pd(f), hp,
+                             _pd(out))
     return out
 
 
@@ -225,7 +229,7 @@ class OracleSim:
         self.nx, self.ny, self.nz = int(case["nx"]), int(case["ny"]), int(case["nz"])
         dims = np.array([self.nx, self.ny, self.nz], np.int32)
         ip = np.array([case.get("bc_zlo", 0), case.get("bc_zhi", 0), case.get("sponge", 0),
-                       case.get("ibm_cycles", 4), case.get("forcing", 0)], np.int32)
+                       case.get("ibm_cycles", 4), case.get("forcing", 0), case.get("collision", 0)], np.int32)
         dp = _f64([case["tau"], case.get("gravity", 0.0), case.get("h_ini", 0.0), case.get("h_end", 0.0)])
         if body is None:
             M = 0

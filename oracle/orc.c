@@ -239,16 +239,24 @@ static void offeq_moment(const double *f, const double *f0, double P1[3][3])
  * C_i = f^(0)_i(p, u + tau h) + (1 - 1/tau) f^(1)_i, i.e. the forced evolution
  * rule before the shift x -> x + xi_i.  Readings: f^(1) is built from P^(1) of
  * the unshifted f^(0)(p,u); u is sum xi f / sum f of the incoming f. */
-void orc_collide_cell_v(const double *f, const double *h, double tau, int32_t forcing, double *out)
+/* collision = 0: the recursive-regularized rule above; collision = 1: BGK
+ * for comparison, the same rule with the raw off-equilibrium f - f^(0)(p,u)
+ * in place of the regularized f^(1). */
+void orc_collide_cell_m(const double *f, const double *h, double tau, int32_t forcing, int32_t collision,
+                        double *out)
 {
     orc_init();
     double rho, p, u[3], f0[Q], f1[Q], fs[Q], P1[3][3], P1f[9], us[3];
     moments(f, &rho, &p, u);
     orc_feq(p, u, f0);
-    offeq_moment(f, f0, P1);
-    for (int a = 0; a < 3; a++)
-        for (int b = 0; b < 3; b++) P1f[3 * a + b] = P1[a][b];
-    orc_fneq(P1f, u, f1);
+    if (collision == 1) {
+        for (int i = 0; i < Q; i++) f1[i] = f[i] - f0[i];
+    } else {
+        offeq_moment(f, f0, P1);
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) P1f[3 * a + b] = P1[a][b];
+        orc_fneq(P1f, u, f1);
+    }
     for (int d = 0; d < 3; d++) us[d] = u[d] + tau * (h ? h[d] : 0.0);
     orc_feq(p, us, fs);
     for (int i = 0; i < Q; i++) out[i] = fs[i] + (1.0 - 1.0 / tau) * f1[i];
@@ -264,6 +272,11 @@ void orc_collide_cell_v(const double *f, const double *h, double tau, int32_t fo
             out[i] -= g_w[i] * (tau - 1.0) * rho * xh / CS2;
         }
     }
+}
+
+void orc_collide_cell_v(const double *f, const double *h, double tau, int32_t forcing, double *out)
+{
+    orc_collide_cell_m(f, h, tau, forcing, 0, out);
 }
 
 void orc_collide_cell(const double *f, const double *h, double tau, double *out)
@@ -307,6 +320,7 @@ typedef struct {
     double tau0;
     int bc_lo, bc_hi, sponge;
     int forcing;    /* 0: forced rule as printed; 1: momentum-exact variant */
+    int collision;  /* 0: recursive regularized (the paper's); 1: BGK */
 } dom_t;
 
 /* Relaxation time at height z.  Sponge reading (Sec. 2.5): tau rises linearly
@@ -340,7 +354,7 @@ static void collide_grid(const dom_t *D, const double *f, const double *h, doubl
         for (int y = 0; y < D->ny; y++)
             for (int x = 0; x < D->nx; x++) {
                 size_t c = cell(D, x, y, z);
-                orc_collide_cell_v(f + Q * c, h ? h + 3 * c : NULL, tau, D->forcing, C + Q * c);
+                orc_collide_cell_m(f + Q * c, h ? h + 3 * c : NULL, tau, D->forcing, D->collision, C + Q * c);
             }
     }
 }
@@ -379,12 +393,18 @@ static void stream_grid(const dom_t *D, const double *C, double *f)
             }
 }
 
+void orc_collide_grid_m(const int32_t *dims, double tau0, int32_t sponge, int32_t forcing, int32_t collision,
+                        const double *f, const double *h, double *C)
+{
+    orc_init();
+    dom_t D = {dims[0], dims[1], dims[2], tau0, 0, 0, sponge, forcing, collision};
+    collide_grid(&D, f, h, C);
+}
+
 void orc_collide_grid_v(const int32_t *dims, double tau0, int32_t sponge, int32_t forcing, const double *f,
                         const double *h, double *C)
 {
-    orc_init();
-    dom_t D = {dims[0], dims[1], dims[2], tau0, 0, 0, sponge, forcing};
-    collide_grid(&D, f, h, C);
+    orc_collide_grid_m(dims, tau0, sponge, forcing, 0, f, h, C);
 }
 
 void orc_collide_grid(const int32_t *dims, double tau0, int32_t sponge, const double *f,
@@ -583,7 +603,7 @@ typedef struct {
     int err;
 } orc_sim;
 
-/* dims[3]; ip[5] = bc_lo bc_hi sponge cycles forcing; dp[4] = tau0 gravity h_ini h_end;
+/* dims[3]; ip[6] = bc_lo bc_hi sponge cycles forcing collision; dp[4] = tau0 gravity h_ini h_end;
  * body[29] = kappa vol Jm(9) r(3) d(9) v(3) w(3). */
 orc_sim *orc_sim_new(const int32_t *dims, const int32_t *ip, const double *dp, int32_t M,
                      const double *xb, const double *nb, const double *dS, const double *body)
@@ -597,6 +617,7 @@ orc_sim *orc_sim_new(const int32_t *dims, const int32_t *ip, const double *dp, i
     S->D.bc_hi = ip[1];
     S->D.sponge = ip[2];
     S->D.forcing = ip[4];
+    S->D.collision = ip[5];
     S->cycles = ip[3];
     S->D.tau0 = dp[0];
     S->B.gravity = dp[1];

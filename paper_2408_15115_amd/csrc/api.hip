@@ -91,6 +91,7 @@ std::string check_options(const lbm_options *o)
     if (o->ibm_diag < 0 || o->ibm_diag > 1) return "ibm_diag must be 0 or 1";
     if (o->forcing < 0 || o->forcing > 1) return "forcing must be 0 or 1";
     if (o->serial_ibm < 0 || o->serial_ibm > 1) return "serial_ibm must be 0 or 1";
+    if (o->collision < 0 || o->collision > 1) return "collision must be 0 or 1";
     return "";
 }
 
@@ -487,7 +488,8 @@ static int32_t do_lbm_step(lbm_ctx *ctx)
     if (ctx->has_body) HIPCHK(ctx, hipEventRecord(ctx->fork, ctx->stream), "record fork event");
     HIPCHK(ctx,
            launch_stream_collide(ctx->opt.storage, ctx->pop[src], ctx->pop[dst], ctx->p, (int)ctx->plan.tiles.size(),
-                                 ctx->opt.block, ctx->opt.schedule, ctx->opt.persist_wgs, ctx->stream),
+                                 ctx->opt.block, ctx->opt.schedule, ctx->opt.persist_wgs, ctx->opt.collision,
+                                 ctx->stream),
            "lbm_step");
     ctx->cur = dst;
     ctx->needs_ibm = ctx->has_body;
@@ -580,8 +582,9 @@ int32_t lbm_set_schedule(lbm_ctx *ctx, const lbm_options *opt)
     const int cyc = opt->ibm_cycles ? opt->ibm_cycles : 4;
     if (opt->storage != ctx->opt.storage || cyc != ctx->opt.ibm_cycles || opt->forcing != ctx->opt.forcing)
         return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage, ibm_cycles or forcing");
-    if (opt->serial_ibm != ctx->opt.serial_ibm) drop_graph(ctx);
+    if (opt->serial_ibm != ctx->opt.serial_ibm || opt->collision != ctx->opt.collision) drop_graph(ctx);
     ctx->opt.serial_ibm = opt->serial_ibm;
+    ctx->opt.collision = opt->collision;
     if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "lbm_set_schedule between lbm_step and ibm_couple");
     const int block = opt->block ? opt->block : 256;
     build_tiles(ctx->plan, block, opt->tile_order);

@@ -24,7 +24,9 @@ __device__ __forceinline__ void store_all(typename CD::T *__restrict__ dst, long
 // One tile = blockDim.x consecutive cells of one case.  A case whose error
 // bits are set is masked (frozen) so the rest of a batch goes on.  The guard
 // flags non-finite density or |u| > 0.5 (bit 4) with one atomic per wave.
-template <class CD>
+// COLL 0: recursive-regularized collision (App. A); COLL 1: BGK for
+// comparison, f0 + (1 - 1/tau)(f - f0) with the raw off-equilibrium.
+template <class CD, int COLL>
 __device__ __forceinline__ void stream_collide_tile(const typename CD::T *__restrict__ src, typename CD::T *__restrict__ dst,
                                                     const CaseDev *__restrict__ cases, BodyDev *__restrict__ body, Tile tl)
 {
@@ -47,8 +49,15 @@ __device__ __forceinline__ void stream_collide_tile(const typename CD::T *__rest
     const float tau = tau_at(cd.tau0, nz, cd.sponge, z);
     const float om = 1.0f - 1.0f / tau;
     float A[Q], out[Q];
-    post_collision_coeffs(M, M.u, om, A);
-    hermite_to_populations(A, out);
+    if constexpr (COLL == 1) {
+        post_collision_coeffs(M, M.u, 0.0f, A);   // equilibrium coefficients only
+        hermite_to_populations(A, out);
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i] += om * (g[i] - out[i]);
+    } else {
+        post_collision_coeffs(M, M.u, om, A);
+        hermite_to_populations(A, out);
+    }
     int zc = z + z0;
     if (zc >= nz) zc -= nz;
     store_all<CD>(dst + cd.pop_off, cd.plane, (zc * ny + y) * nx + x, out);
@@ -66,7 +75,7 @@ __device__ __forceinline__ void stream_collide_tile(const typename CD::T *__rest
 // keeps the register allocation of the plain schedules free of the loops.
 constexpr int kQueueChunk = 4;
 
-template <class CD, int SCHED>
+template <class CD, int SCHED, int COLL = 0>
 __global__ void __launch_bounds__(256) k_stream_collide(const typename CD::T *__restrict__ src,
                                                         typename CD::T *__restrict__ dst,
                                                         const CaseDev *__restrict__ cases, BodyDev *__restrict__ body,
@@ -86,15 +95,15 @@ __global__ void __launch_bounds__(256) k_stream_collide(const typename CD::T *__
                 __syncthreads();
                 if (t0 >= hi) break;
                 const int t1 = min(t0 + kQueueChunk, hi);
-                for (int t = t0; t < t1; t++) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
+                for (int t = t0; t < t1; t++) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t]);
             }
         }
     } else if constexpr (SCHED == 2) {
-        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t]);
     } else {
         int t = blockIdx.x;
         if constexpr (SCHED == 1) t = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-        if (t < ntiles) stream_collide_tile<CD>(src, dst, cases, body, tiles[t]);
+        if (t < ntiles) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t]);
     }
 }
 
@@ -124,9 +133,14 @@ hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t 
 // --------------------------------------------------------------- launchers
 template <class CD>
 static hipError_t stream_collide_impl(const void *src, void *dst, const DevPtrs &p, int ntiles, int block,
-                                      int schedule, int persist_wgs, hipStream_t s)
+                                      int schedule, int persist_wgs, int collision, hipStream_t s)
 {
     using T = typename CD::T;
+    if (collision == 1) {   // the comparison collision runs with the plain schedule only
+        hipLaunchKernelGGL((k_stream_collide<CD, 0, 1>), dim3(ntiles), dim3(block), 0, s, (const T *)src, (T *)dst,
+                           p.cases, p.body, p.tiles, ntiles, p.counter);
+        return hipGetLastError();
+    }
     int grid = ntiles;
     if (schedule == 1) grid = (ntiles + 7) / 8 * 8;
     if (schedule >= 2) grid = persist_wgs > 0 ? persist_wgs : 2048;
@@ -154,12 +168,15 @@ static hipError_t stream_collide_impl(const void *src, void *dst, const DevPtrs 
 }
 
 hipError_t launch_stream_collide(int storage, const void *src, void *dst, const DevPtrs &p, int ntiles,
-                                 int block, int schedule, int persist_wgs, hipStream_t s)
+                                 int block, int schedule, int persist_wgs, int collision, hipStream_t s)
 {
     switch (storage) {
-    case ST_F16: return stream_collide_impl<CodecF16>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
-    case ST_BF16: return stream_collide_impl<CodecBF16>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
-    default: return stream_collide_impl<CodecF32>(src, dst, p, ntiles, block, schedule, persist_wgs, s);
+    case ST_F16:
+        return stream_collide_impl<CodecF16>(src, dst, p, ntiles, block, schedule, persist_wgs, collision, s);
+    case ST_BF16:
+        return stream_collide_impl<CodecBF16>(src, dst, p, ntiles, block, schedule, persist_wgs, collision, s);
+    default:
+        return stream_collide_impl<CodecF32>(src, dst, p, ntiles, block, schedule, persist_wgs, collision, s);
     }
 }
 

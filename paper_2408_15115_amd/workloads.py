@@ -358,6 +358,22 @@ def smooth_noise(rng, shape, n_modes=4, kmax=2):
     return out / n_modes
 
 
+def taylor_green_populations(n, U0):
+    """Initial state of the 3-D Taylor-Green vortex on an n^3 periodic box:
+    density 1, u = U0 (sin a cos b cos c, -cos a sin b cos c, 0) with
+    (a, b, c) = 2 pi (x, y, z) / n, populations from the second-order
+    Maxwellian expansion w_i (1 + 3 xi.u + 9/2 (xi.u)^2 - 3/2 u^2).  Layout
+    (nz, ny, nx, 27)."""
+    t = 2 * math.pi * np.arange(n) / n
+    c, b, a = np.meshgrid(t, t, t, indexing="ij")
+    u = np.stack([U0 * np.sin(a) * np.cos(b) * np.cos(c), -U0 * np.cos(a) * np.sin(b) * np.cos(c),
+                  np.zeros_like(a)], axis=-1)
+    xi = np.array([[i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1] for i in range(27)], np.float64)
+    xu = u @ xi.T
+    uu = (u * u).sum(-1, keepdims=True)
+    return D3Q27_W * (1.0 + 3.0 * xu + 4.5 * xu * xu - 1.5 * uu)
+
+
 def random_populations(seed, nx, ny, nz, amp=0.02):
     """Near-rest population field f_i = w_i (1 + amp * eta_i(x)) with smooth
     random eta_i.  Layout (nz, ny, nx, 27)."""

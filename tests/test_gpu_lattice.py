@@ -35,12 +35,13 @@ CASES = [
 ]
 
 
-def run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed, storage="f32", amp=0.05):
+def run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed, storage="f32", amp=0.05, collision=0):
     lo, hi = bc if isinstance(bc, tuple) else (bc, bc)
     case = W.make_case(nx, ny, nz, tau, lo, hi, sponge)
     f0 = W.random_populations(seed, nx, ny, nz, amp=amp)
-    say(f"lattice parity nx={nx} ny={ny} nz={nz} tau={tau} bc={bc} sponge={sponge} steps={steps} {storage}")
-    S = T.Solver([case], storage=storage)
+    say(f"lattice parity nx={nx} ny={ny} nz={nz} tau={tau} bc={bc} sponge={sponge} steps={steps} {storage} "
+        f"collision={collision}")
+    S = T.Solver([case], storage=storage, collision=collision)
     S.set_populations(oracle_to_soa(f0))
     for _ in range(steps):
         S.lbm_step()
@@ -49,7 +50,7 @@ def run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed, storage="f32", am
     # oracle streams it first, then alternates collide/stream
     f = orc.stream_grid(f0, lo, hi)
     for s in range(steps):
-        C = orc.collide_grid(f, tau, sponge)
+        C = orc.collide_grid(f, tau, sponge, collision=collision)
         if s + 1 < steps:
             f = orc.stream_grid(C, lo, hi)
     S.close()
@@ -66,6 +67,15 @@ def test_one_step_matches_oracle(T, orc, nx, ny, nz, tau, bc, sponge):
 def test_many_steps_match_oracle(T, orc, nx, ny, nz, tau, bc, sponge):
     gpu, ref = run_pair(T, orc, nx, ny, nz, tau, bc, sponge, 25, seed=nx + ny, amp=0.02)
     assert max_rel(gpu, ref) < TOL_F32
+
+
+@pytest.mark.parametrize("nx,ny,nz,tau,bc,sponge,steps", [(16, 12, 11, 0.8, W.BC_FREESLIP, 0, 1),
+                                                          (20, 12, 16, 0.7, (W.BC_NOSLIP, W.BC_PRESSURE), 5, 20)])
+def test_bgk_comparison_collision_matches_oracle(T, orc, nx, ny, nz, tau, bc, sponge, steps):
+    gpu, ref = run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed=5 + nx, amp=0.02, collision=1)
+    assert max_rel(gpu, ref) < TOL_F32
+    rr, _ = run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed=5 + nx, amp=0.02)
+    assert max_rel(gpu, rr) > 1e-6
 
 
 @pytest.mark.parametrize("lo,hi", [(W.BC_FREESLIP, W.BC_FREESLIP), (W.BC_NOSLIP, W.BC_PRESSURE)])

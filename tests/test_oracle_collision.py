@@ -236,6 +236,39 @@ def test_momentum_exact_variant_adds_rho_h(orc, seed):
     assert np.array_equal(orc.collide_cell(f, None, tau, forcing=1), orc.collide_cell(f, None, tau))
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_bgk_comparison_collision(orc, seed):
+    """BGK (collision 1, for comparison): every moment of the off-equilibrium
+    part relaxes by the same factor 1 - 1/tau (third- and fourth-order ones
+    too, which the regularized rule filters); mass and momentum as in the
+    regularized rule; on a state whose off-equilibrium is the regularized
+    second-order one the two collisions agree."""
+    rng = np.random.default_rng(700 + seed)
+    xi, w = orc.lattice()
+    f = random_cell(orc, rng)
+    tau = rng.uniform(0.51, 1.8)
+    h = 1e-3 * rng.standard_normal(3)
+    rho = f.sum()
+    u = (f @ xi) / rho
+    bgk = orc.collide_cell(f, h, tau, collision=1)
+    rr = orc.collide_cell(f, h, tau)
+    assert abs(bgk.sum() - rho) < 1e-15
+    assert np.allclose(bgk @ xi, rho * (u + tau * h), atol=1e-16, rtol=0)
+    neq_in = f - orc.feq(CS2 * (rho - 1), u)
+    neq_bgk = bgk - orc.feq(CS2 * (rho - 1), u + tau * h)
+    neq_rr = rr - orc.feq(CS2 * (rho - 1), u + tau * h)
+    for mono in [(1, 1, 1), (2, 1, 0), (2, 2, 0), (2, 1, 1), (2, 2, 2)]:
+        psi = xi[:, 0] ** mono[0] * xi[:, 1] ** mono[1] * xi[:, 2] ** mono[2]
+        assert abs(psi @ neq_bgk - (1 - 1 / tau) * (psi @ neq_in)) < 1e-15
+    # the random state has higher-order off-equilibrium content that RR drops
+    psi = xi[:, 0] * xi[:, 1] * xi[:, 2]
+    assert abs(psi @ neq_rr - (1 - 1 / tau) * (psi @ neq_in)) > 1e-6
+    # pure regularized off-equilibrium: both rules coincide
+    P1 = (neq_in[:, None, None] * xi[:, :, None] * xi[:, None, :]).sum(0)
+    g = orc.feq(CS2 * (rho - 1), u) + orc.fneq(P1, u)
+    assert np.allclose(orc.collide_cell(g, h, tau, collision=1), orc.collide_cell(g, h, tau), atol=1e-15, rtol=0)
+
+
 def test_tau_one_is_equilibrium(orc):
     rng = np.random.default_rng(7)
     xi, _ = orc.lattice()
