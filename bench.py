@@ -332,6 +332,35 @@ def settling_run(T, W, torch, steps=8000):
     return out
 
 
+def stability_run(T, W, torch, n=64, U0=0.1, steps=2000):
+    """3-D Taylor-Green vortex (n^3, U0 = 0.1): the smallest relaxation time
+    that runs `steps` steps without tripping the lattice kernel's guard, for
+    the recursive-regularized collision and for BGK on the same lattice."""
+    import numpy as np
+    taus = [0.52, 0.51, 0.505, 0.502, 0.501, 0.5005, 0.5002, 0.5001]
+    f0 = np.moveaxis(W.taylor_green_populations(n, U0), -1, 0)
+    out = {"workload": f"Taylor-Green vortex {n}^3, U0 {U0}, {steps} steps", "taus_tried": taus}
+    for name, coll in (("regularized", 0), ("bgk", 1)):
+        low = None
+        for tau in taus:
+            S = T.Solver([W.make_case(n, n, n, tau, W.BC_PERIODIC, W.BC_PERIODIC, 0)], collision=coll,
+                         stream=torch.cuda.Stream())
+            S.set_populations(f0)
+            ok = True
+            for _ in range(steps // 250):
+                S.run(250)
+                if S.body_state(0, check=False)["err"]:
+                    ok = False
+                    break
+            S.close()
+            if not ok:
+                break
+            low = tau
+        out[name] = {"smallest_stable_tau": low,
+                     "reynolds": round(U0 * n / (2 * math.pi) / ((low - 0.5) / 3.0), 1) if low else None}
+    return out
+
+
 def cpu_baseline(case, body, steps):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the
     same body, relaxation time and walls in a 128^3 window."""
@@ -368,6 +397,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-settling", action="store_true")
+    ap.add_argument("--no-stability", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -483,6 +513,11 @@ def main():
         log(f"  sphere settling, v_T / Clift-Gauvin: stress integral at the markers "
             f"{st['markers']['vT_over_clift_gauvin']}, on the parallel surface 3 cells out "
             f"{st['parallel_surface_3']['vT_over_clift_gauvin']}")
+
+    if not args.no_variants and not args.no_stability:
+        sb = stability_run(T, W, torch)
+        variants["stability"] = sb
+        log(f"  Taylor-Green stability, smallest stable tau: regularized {sb['regularized']}, BGK {sb['bgk']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -137,9 +137,11 @@ def make_body(d: dict | None, keep: list) -> lbm_body:
     b.v0[:] = [float(v) for v in np.ravel(d["v0"])]
     b.w0[:] = [float(v) for v in np.ravel(d["w0"])]
     if d.get("force_offset", 0.0) > 0.0:
-        dSo = np.ascontiguousarray(d["dS_offset"], np.float64)
-        keep.append(dSo)
-        b.force_offset, b.dS_offset = float(d["force_offset"]), _dptr(dSo)
+        b.force_offset = float(d["force_offset"])
+        if d.get("dS_offset") is not None:   # else NULL: the library rejects the body
+            dSo = np.ascontiguousarray(d["dS_offset"], np.float64)
+            keep.append(dSo)
+            b.dS_offset = _dptr(dSo)
     return b
 
 

@@ -89,6 +89,35 @@ def test_init_rejects_null_buffers_without_gpu():
 def test_bad_options_rejected():
     from paper_2408_15115_amd import turret as T
     case, body = W.case_sphere48()
-    for kw in ({"storage": 7}, {"block": 96}, {"schedule": 5}, {"ibm_cycles": 40}):
+    for kw in ({"storage": 7}, {"block": 96}, {"schedule": 5}, {"ibm_cycles": 40}, {"forcing": 2},
+               {"serial_ibm": 3}, {"collision": 2}, {"ibm_diag": 2}, {"tile_order": 3}):
         with pytest.raises(T.TurretError):
             T.required_bytes([case], [body], **kw)
+
+
+def test_force_surface_checks():
+    """A body with force_offset > 0 needs the offset areas, keeps its offset
+    points two cells inside the z walls, and gets a larger region."""
+    from paper_2408_15115_amd import turret as T
+    case, body = W.case_sphere48()
+    _, _, aux0 = T.required_bytes([case], [body])
+    b = W.sphere_fibonacci_body(4.0, 400, 2.0, body["r0"], force_offset=3.0)
+    _, _, aux1 = T.required_bytes([case], [b])
+    assert aux1 > aux0
+    nod = dict(b)
+    nod.pop("dS_offset")
+    with pytest.raises(T.TurretError) as e:
+        T.required_bytes([case], [nod])
+    assert "dS_offset" in str(e.value)
+    low = W.sphere_fibonacci_body(4.0, 400, 2.0, [23.5, 23.5, 7.0], force_offset=3.0)
+    with pytest.raises(T.TurretError) as e:
+        T.required_bytes([case], [low])
+    assert "wall" in str(e.value)
+
+
+def test_pressure_wall_accepted_and_unknown_wall_rejected():
+    from paper_2408_15115_amd import turret as T
+    case, body = W.case_sphere48()
+    T.required_bytes([dict(case, bc_zlo=W.BC_NOSLIP, bc_zhi=W.BC_PRESSURE)], [body])
+    with pytest.raises(T.TurretError):
+        T.required_bytes([dict(case, bc_zhi=4)], [body])
