@@ -398,6 +398,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-settling", action="store_true")
     ap.add_argument("--no-stability", action="store_true")
+    ap.add_argument("--coupling", default="auto", choices=["auto", "serial", "beside"],
+                    help="where the coupling runs: chosen by timing both (auto), after the lattice kernel, or "
+                         "beside it on a second stream")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -445,7 +448,9 @@ def main():
 
     def run_storage(storage, steps, warmup, graph):
         if storage not in modes:
-            modes[storage] = coupling_mode(storage)
+            modes[storage] = {"serial": 1, "beside": 0}.get(args.coupling)
+            if modes[storage] is None:
+                modes[storage] = coupling_mode(storage)
         S = T.Solver([case], [body], storage=storage, stream=torch.cuda.Stream(), serial_ibm=modes[storage])
         total_ms, k1_ms = timed_steps(S, torch, steps, warmup)
         k1 = timed_steps.last_k1
