@@ -121,3 +121,19 @@ def test_pressure_wall_accepted_and_unknown_wall_rejected():
     T.required_bytes([dict(case, bc_zlo=W.BC_NOSLIP, bc_zhi=W.BC_PRESSURE)], [body])
     with pytest.raises(T.TurretError):
         T.required_bytes([dict(case, bc_zhi=4)], [body])
+
+
+def test_degenerate_and_maximum_sizes_on_host():
+    """No case at all, a box of 2^31 cells or more, and a particle-free case
+    next to a particle case."""
+    from paper_2408_15115_amd import turret as T
+    case, body = W.case_sphere48()
+    with pytest.raises(T.TurretError) as e:
+        T.required_bytes([], [])
+    assert "at least one case" in str(e.value)
+    with pytest.raises(T.TurretError) as e:
+        T.required_bytes([dict(case, nx=2048, ny=1024, nz=1024)], None)
+    assert "2^31" in str(e.value)
+    a = T.required_bytes([case, case], [body, None])
+    b = T.required_bytes([case], [body])
+    assert a[0] == 2 * b[0] and a[2] >= b[2]

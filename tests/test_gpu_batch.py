@@ -69,6 +69,25 @@ def test_batch_case_equals_case_alone(T, alone, sched):
     assert S.body_state(0)["shifts"] == 1
 
 
+def test_particle_free_case_in_a_batch(T, alone):
+    """A case without a particle beside particle cases: it evolves exactly as
+    it does alone, and the particle cases are untouched by it."""
+    cases, bodies = small_batch()
+    fluid = W.make_case(20, 18, 26, 0.65, W.BC_NOSLIP, W.BC_PRESSURE, 5)
+    f0 = np.moveaxis(W.random_populations(21, 20, 18, 26, amp=0.02), -1, 0)
+    S = T.Solver(cases + [fluid], bodies + [None])
+    S.set_populations(f0, 3)
+    S.run(12)
+    A = T.Solver([fluid])
+    A.set_populations(f0)
+    A.run(12)
+    assert np.array_equal(S.populations(3), A.populations())
+    for c in range(3):
+        assert np.array_equal(S.populations(c), alone[c][0]), c
+    S.close()
+    A.close()
+
+
 def test_batched_case_matches_oracle(T, orc):
     cases, bodies = small_batch()
     S = T.Solver(cases, bodies, schedule=3, persist_wgs=16, tile_order=2)
