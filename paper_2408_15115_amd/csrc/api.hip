@@ -35,7 +35,8 @@ struct Plan {
     int force_surface = 0;    // some case evaluates its force on the parallel surface
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
-        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, aux_bytes;
+        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox,
+        aux_bytes;
     int block = 256;
 };
 
@@ -255,6 +256,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_hs = take(sizeof(double) * M);
     P.off_dSo = take(sizeof(double) * M);
     P.off_mtiles = take(sizeof(MarkerTile) * std::max<size_t>(P.mtiles.size(), 1));
+    P.off_tbox = take(sizeof(TileBox) * std::max<size_t>(P.mtiles.size(), 1));
     P.aux_bytes = o;
     (void)eb;
     return "";
@@ -394,6 +396,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.h0 = (double *)(a + P.off_h0);
     p.hs = (double *)(a + P.off_hs);
     p.dSo = (double *)(a + P.off_dSo);
+    p.tbox = (TileBox *)(a + P.off_tbox);
 
     // host images of the descriptors, body states and markers
     std::vector<BodyDev> bd(n_cases);

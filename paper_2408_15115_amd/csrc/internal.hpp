@@ -56,6 +56,13 @@ struct Tile {
 struct MarkerTile {
     int c, first, count, pad;
 };
+// Box of region cells covering the stencils of a tile's markers.
+struct TileBox {
+    int lo[3];    // first stencil node of the box (physical cell coordinates, x/y unwrapped)
+    int o[3];     // the same as region coordinates
+    int e[3];     // box extent
+    int fits;     // 1 if the box fits kBoxMax^3 and lies inside the region
+};
 constexpr int kTileMarkers = 16;
 constexpr double kTileSpan = 3.0;
 constexpr int kBoxMax = 11;
@@ -85,6 +92,7 @@ struct DevPtrs {
     double *h0;      // per-marker plain start U - I[u*] (3)
     double *hs;      // per-marker scale of the warm-start features, |h0| + |h(t-1)|
     double *dSo;     // per-marker areas of the parallel force surface (cases with force_offset > 0)
+    TileBox *tbox;   // per-tile box, computed each step by the force kernel
 };
 
 // ---------------------------------------------------------------- launchers

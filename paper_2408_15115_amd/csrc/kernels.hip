@@ -226,32 +226,43 @@ __device__ inline double wave_sum(double v)
 // accumulates into an LDS copy of the box (int64 fixed point) and adds each
 // touched cell to HBM once.  A box larger than kBoxMax^3 (not expected for
 // the tile span) falls back to per-node HBM access.
-struct TileBox {
-    int lo[3];    // first stencil node of the box (physical cell coordinates, x/y unwrapped)
-    int o[3];     // the same as region coordinates
-    int e[3];     // box extent
-    bool fits;
-};
-
-__device__ inline TileBox tile_box(const DevPtrs &p, const MarkerTile &mt, const BodyDev &B, int L)
+// Tile handled by workgroup b: the dispatcher deals workgroups round-robin
+// over the 8 XCDs, so consecutive blocks are spread and each XCD is given a
+// contiguous (Morton-ordered, hence spatially compact) run of tiles whose
+// boxes overlap inside one L2.  The grid is padded to a multiple of 8.
+__device__ inline int tile_of_block(int b, int n)
 {
-    int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-    for (int j = 0; j < mt.count; j++) {
-        const int k = mt.first + j;
+    const int per = (n + 7) >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// Box of a tile (once per step, by the force kernel; the marker positions do
+// not change during the cycles): one thread per marker, LDS min / max.
+__device__ inline TileBox tile_box_block(const DevPtrs &p, const MarkerTile &mt, const BodyDev &B, int L)
+{
+    __shared__ int ext[6];
+    if (threadIdx.x < 3) {
+        ext[threadIdx.x] = 1 << 30;
+        ext[3 + threadIdx.x] = -(1 << 30);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < mt.count) {
+        const int k = mt.first + (int)threadIdx.x;
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             const int f = (int)floor(p.X[3 * k + d]);
-            mn[d] = min(mn[d], f);
-            mx[d] = max(mx[d], f);
+            atomicMin(&ext[d], f);
+            atomicMax(&ext[3 + d], f);
         }
     }
+    __syncthreads();
     TileBox b;
-    b.fits = true;
+    b.fits = 1;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        b.lo[d] = mn[d] - 1;
+        b.lo[d] = ext[d] - 1;
         b.o[d] = b.lo[d] - B.org[d];
-        b.e[d] = mx[d] - mn[d] + 4;
+        b.e[d] = ext[3 + d] - ext[d] + 4;
         b.fits = b.fits && b.e[d] <= kBoxMax && b.o[d] >= 0 && b.o[d] + b.e[d] <= L;
     }
     return b;
@@ -326,16 +337,19 @@ __device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B,
 }
 
 // l = 0 and the stress integral over a tile (wave w takes markers w, w+4, ...).
-__global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p)
+__global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mtiles)
 {
     __shared__ float box[kRegFields][kBoxCells];
-    const MarkerTile mt = p.mtiles[blockIdx.x];
+    const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
+    if (tix >= n_mtiles) return;
+    const MarkerTile mt = p.mtiles[tix];
     const CaseDev &cd = p.cases[mt.c];
     const BodyDev &B = p.body[mt.c];
     if (B.err != 0) return;
     const int L = cd.L, L3 = L * L * L;
     const float *R = p.reg + cd.reg_off * kRegFields;
-    const TileBox tb = tile_box(p, mt, B, L);
+    const TileBox tb = tile_box_block(p, mt, B, L);
+    if (threadIdx.x == 0) p.tbox[tix] = tb;
     const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
     if (tb.fits) {
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
@@ -418,16 +432,18 @@ __global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int Mtot)
 // Spreading of the increments dh over a tile (H += S[dh], h_k += dh): LDS
 // accumulation, then one HBM atomic per touched cell.  With masked set, cases
 // whose sequence has ended are skipped.
-__global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int masked)
+__global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, int masked)
 {
     __shared__ unsigned long long acc[3][kBoxCells];
-    const MarkerTile mt = p.mtiles[blockIdx.x];
+    const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
+    if (tix >= n_mtiles) return;
+    const MarkerTile mt = p.mtiles[tix];
     const CaseDev &cd = p.cases[mt.c];
     const BodyDev &B = p.body[mt.c];
     if (B.err != 0 || (masked && !B.active)) return;
     const int L = cd.L, L3 = L * L * L;
     long long *H = p.H + cd.reg_off * 3;
-    const TileBox tb = tile_box(p, mt, B, L);
+    const TileBox tb = p.tbox[tix];
     const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
     if (tb.fits)
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[0][i] = acc[1][i] = acc[2][i] = 0ull;
@@ -473,17 +489,19 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int masked)
 
 // Interpolation of u* + H over a tile (staged in LDS, FP64), the residual
 // U_k - I[u* + H](X_k) and the next increment dh = that residual.
-__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int masked)
+__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked)
 {
     __shared__ double box[3][kBoxCells];
-    const MarkerTile mt = p.mtiles[blockIdx.x];
+    const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
+    if (tix >= n_mtiles) return;
+    const MarkerTile mt = p.mtiles[tix];
     const CaseDev &cd = p.cases[mt.c];
     const BodyDev &B = p.body[mt.c];
     if (B.err != 0 || (masked && !B.active)) return;
     const int L = cd.L, L3 = L * L * L;
     const float *R = p.reg + cd.reg_off * kRegFields;
     const long long *H = p.H + cd.reg_off * 3;
-    const TileBox tb = tile_box(p, mt, B, L);
+    const TileBox tb = p.tbox[tix];
     const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
     if (tb.fits) {
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
@@ -768,11 +786,11 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     using T = typename CD::T;
     const dim3 blk(256);
     const dim3 reg_grid((maxL3 + 255) / 256, n_cases);
-    const dim3 tile_grid(n_mtiles);
+    const dim3 tile_grid((n_mtiles + 7) / 8 * 8);
     const dim3 mark_grid((Mtot + 255) / 256);
     hipLaunchKernelGGL(k_markers, mark_grid, blk, 0, s, p, Mtot);
     hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
-    hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p);
+    hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p, n_mtiles);
     if (force_surface) hipLaunchKernelGGL(k_offset_force, dim3((Mtot + 3) / 4), blk, 0, s, p, Mtot);
     hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), dim3(1024), 0, s, p);
     // one sequence of multi-direct forcing cycles (Sec. 2.2, l = 1..4): spread
@@ -780,8 +798,8 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     // residual after the last spread is the sequence's residual
     auto sequence = [&](int ncyc, int slot0, int masked) {
         for (int cyc = 1; cyc <= ncyc; cyc++) {
-            hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, masked);
-            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, masked);
+            hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, masked);
+            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, masked);
             if (diag || cyc == ncyc)
                 hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, slot0 + cyc - 1, masked, 0);
         }
@@ -798,8 +816,8 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
         const dim3 case_grid((n_cases + 63) / 64), case_blk(64);
         hipLaunchKernelGGL(k_gate_begin, case_grid, case_blk, 0, s, p, n_cases);
         for (int cyc = 1; cyc <= warm_cycles; cyc++) {
-            hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, 1);
-            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, 1);
+            hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, 1);
+            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, 1);
             hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, cyc - 1, 1, cyc);
         }
         hipLaunchKernelGGL(k_gate, case_grid, case_blk, 0, s, p, n_cases);
