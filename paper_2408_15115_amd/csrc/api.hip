@@ -36,7 +36,7 @@ struct Plan {
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
         off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox,
-        aux_bytes;
+        off_mark, aux_bytes;
     int block = 256;
 };
 
@@ -204,7 +204,9 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         d.force_offset = (b && d.M > 0) ? b->force_offset : 0.0;
         if (d.force_offset > 0.0) P.force_surface = 1;
         d.marker_off = moff;
+        d.tile_off = (int)P.mtiles.size();
         if (d.M > 0) tile_markers(*b, c, moff, P.morder, P.mtiles);
+        d.n_tiles = (int)P.mtiles.size() - d.tile_off;
         moff += d.M;
         if (d.M > 0) {
             double rb = 0;
@@ -247,16 +249,18 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_U = take(sizeof(double) * 3 * M);
     P.off_hk = take(sizeof(double) * 3 * M);
     P.off_dh = take(sizeof(double) * 3 * M);
-    P.off_part = take(sizeof(double) * kPart * M);
-    P.off_res = take(sizeof(double) * M);
+    const size_t NT = std::max<size_t>(P.mtiles.size(), 1);
+    P.off_part = take(sizeof(double) * kPart * NT);
+    P.off_res = take(sizeof(double) * NT);
     P.off_reg = take(sizeof(float) * kRegFields * std::max<long long>(reg, 1));
     P.off_H = take(sizeof(long long) * 3 * std::max<long long>(reg, 1));
+    P.off_mark = take((size_t)std::max<long long>(reg, 1));
     P.off_feat = take(sizeof(float) * kMlpIn * M);
     P.off_h0 = take(sizeof(double) * 3 * M);
     P.off_hs = take(sizeof(double) * M);
     P.off_dSo = take(sizeof(double) * M);
-    P.off_mtiles = take(sizeof(MarkerTile) * std::max<size_t>(P.mtiles.size(), 1));
-    P.off_tbox = take(sizeof(TileBox) * std::max<size_t>(P.mtiles.size(), 1));
+    P.off_mtiles = take(sizeof(MarkerTile) * NT);
+    P.off_tbox = take(sizeof(TileBox) * NT);
     P.aux_bytes = o;
     (void)eb;
     return "";
@@ -391,6 +395,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.res = (double *)(a + P.off_res);
     p.reg = (float *)(a + P.off_reg);
     p.H = (long long *)(a + P.off_H);
+    p.mark = (unsigned char *)(a + P.off_mark);
     p.mtiles = (MarkerTile *)(a + P.off_mtiles);
     p.feat = (float *)(a + P.off_feat);
     p.h0 = (double *)(a + P.off_h0);

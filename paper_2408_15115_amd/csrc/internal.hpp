@@ -12,6 +12,7 @@ struct CaseDev {
     int nx, ny, nz;
     int bc_lo, bc_hi, sponge;
     int M, marker_off;      // markers of this case: [marker_off, marker_off + M)
+    int tile_off, n_tiles;  // marker tiles of this case: [tile_off, tile_off + n_tiles)
     int L, dz;              // IBM region edge (cells) and window shift rows
     long long cells;        // nx * ny * nz
     long long plane;        // elements per direction plane (cells rounded up to 128)
@@ -51,7 +52,7 @@ struct Tile {
 // A marker tile: up to kTileMarkers markers of one case that lie close
 // together on the body (sorted along a Morton curve of their body-frame
 // positions, at most kTileSpan lattice units apart per axis), handled by one
-// workgroup whose stencils share a box of at most kBoxMax^3 cells staged in
+// workgroup whose stencils share a box of at most kBoxCells cells staged in
 // LDS.
 struct MarkerTile {
     int c, first, count, pad;
@@ -61,18 +62,21 @@ struct TileBox {
     int lo[3];    // first stencil node of the box (physical cell coordinates, x/y unwrapped)
     int o[3];     // the same as region coordinates
     int e[3];     // box extent
-    int fits;     // 1 if the box fits kBoxMax^3 and lies inside the region
+    int fits;     // 1 if the box has at most kBoxCells cells and lies inside the region
 };
 constexpr int kTileMarkers = 16;
 constexpr double kTileSpan = 3.0;
-constexpr int kBoxMax = 11;
-constexpr int kBoxCells = kBoxMax * kBoxMax * kBoxMax;
+// LDS box capacity: a tile spans at most kTileSpan per axis in the body frame,
+// so its box is at most 7^3 cells axis-aligned and stays below 8^3 in the
+// rotations measured (a 448-cell maximum over random orientations of the
+// 12k-marker ellipsoid); larger boxes take the per-node HBM path.
+constexpr int kBoxCells = 512;
 
 // Fixed-point scale of the deterministic immersed-force accumulator.
 constexpr double kFixScale = 1099511627776.0;   // 2^40
 constexpr double kFixInv = 1.0 / 1099511627776.0;
 
-// Per-marker partial sums written by the force kernel: F(3) T(3) Fp(3).
+// Per-tile partial sums written by the force kernels: F(3) T(3) Fp(3).
 constexpr int kPart = 9;
 // Region fields: rho - 1, u (3), sigma xx yy zz xy xz yz (6).
 constexpr int kRegFields = 10;
@@ -83,7 +87,10 @@ struct DevPtrs {
     Tile *tiles;
     int *mcase;
     double *xb, *nb, *dS;
-    double *X, *N, *U, *hk, *dh, *part, *res;
+    double *X, *N, *U, *hk, *dh;
+    double *part;    // per-tile force, torque and pressure-force sums (kPart each)
+    double *res;     // per-tile max residual of the last interpolation
+    unsigned char *mark;   // per region cell: 1 if inside a stencil this step
     float *reg;
     long long *H;
     int *counter;    // 8 work-queue counters of the persistent lattice schedule

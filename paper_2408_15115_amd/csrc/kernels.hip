@@ -97,11 +97,35 @@ __global__ void k_body_advance(DevPtrs p, int n_cases)
 }
 
 // X_k = r + sum_j xb_kj d_j, n_k = sum_j nb_kj d_j, U_k = v + w x (X_k - r).
-__global__ void k_markers(DevPtrs p, int Mtot)
+// Marks stencil node `lane` of the point X as used in this step (region
+// cells outside every stencil are neither gathered nor corrected).
+__device__ inline void mark_node(const DevPtrs &p, const CaseDev &cd, const BodyDev &B, const double X[3], int lane)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int off[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+    const int n[3] = {cd.nx, cd.ny, cd.nz};
+    const int L = cd.L;
+    int r[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        int rel = (int)floor(X[d]) - 1 + off[d] - B.org[d];
+        if (d < 2) rel = wrapi(rel, n[d]);
+        ok = ok && rel >= 0 && rel < L;
+        r[d] = rel;
+    }
+    if (ok) p.mark[cd.reg_off + r[0] + L * (r[1] + L * r[2])] = 1;
+}
+
+// One wavefront per marker: every lane forms the marker's position; lane 0
+// stores X, n, U and checks the z range; lane l marks stencil node l of the
+// marker (and of its force-surface point).
+__global__ void __launch_bounds__(256) k_markers(DevPtrs p, int Mtot)
+{
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (k >= Mtot) return;
     const int c = p.mcase[k];
+    const CaseDev &cd = p.cases[c];
     const BodyDev &B = p.body[c];
     if (B.err != 0) return;
     const double xb[3] = {p.xb[3 * k], p.xb[3 * k + 1], p.xb[3 * k + 2]};
@@ -113,19 +137,26 @@ __global__ void k_markers(DevPtrs p, int Mtot)
         N[a] = nb[0] * B.d[a] + nb[1] * B.d[3 + a] + nb[2] * B.d[6 + a];
         rel[a] = X[a] - B.r[a];
     }
-    cross3(B.w, rel, wr);
+    const double dl = cd.force_offset;
+    if (lane == 0) {
+        cross3(B.w, rel, wr);
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        p.X[3 * k + a] = X[a];
-        p.N[3 * k + a] = N[a];
-        p.U[3 * k + a] = B.v[a] + wr[a];
+        for (int a = 0; a < 3; a++) {
+            p.X[3 * k + a] = X[a];
+            p.N[3 * k + a] = N[a];
+            p.U[3 * k + a] = B.v[a] + wr[a];
+        }
+        const int fz = (int)floor(X[2]);
+        if (fz - 1 < 0 || fz + 2 > cd.nz - 1) atomicOr(&p.body[c].err, 1);
+        if (dl > 0.0) {
+            const int gz = (int)floor(X[2] + dl * N[2]);
+            if (gz - 1 < 0 || gz + 2 > cd.nz - 1) atomicOr(&p.body[c].err, 1);
+        }
     }
-    const int fz = (int)floor(X[2]);
-    if (fz - 1 < 0 || fz + 2 > p.cases[c].nz - 1) atomicOr(&p.body[c].err, 1);
-    const double dl = p.cases[c].force_offset;
+    mark_node(p, cd, B, X, lane);
     if (dl > 0.0) {
-        const int gz = (int)floor(X[2] + dl * N[2]);
-        if (gz - 1 < 0 || gz + 2 > p.cases[c].nz - 1) atomicOr(&p.body[c].err, 1);
+        const double Y[3] = {X[0] + dl * N[0], X[1] + dl * N[1], X[2] + dl * N[2]};
+        mark_node(p, cd, B, Y, lane);
     }
 }
 
@@ -133,7 +164,9 @@ __global__ void k_markers(DevPtrs p, int Mtot)
 // For every cell of the particle region: pull f(t+1) from the buffer the
 // lattice kernel read, then rho - 1, u* = sum xi f / sum f and the stress
 // sigma = -p I + (1/(2 tau) - 1) P1 with p = cs^2 (rho - 1) (Sec. 2.1).
-// Also clears the fixed-point immersed-force accumulator.
+// Also clears the fixed-point immersed-force accumulator.  Only cells marked
+// by k_markers (inside some stencil) are visited; the others are read by no
+// interpolation and carry no force.
 template <class CD>
 __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs p)
 {
@@ -143,7 +176,7 @@ __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs 
     if (cd.M == 0 || B.err != 0) return;
     const int L = cd.L, L3 = L * L * L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= L3) return;
+    if (q >= L3 || !p.mark[cd.reg_off + q]) return;
     float *R = p.reg + cd.reg_off * kRegFields;
     long long *H = p.H + cd.reg_off * 3;
     H[q] = 0;
@@ -224,7 +257,7 @@ __device__ inline double wave_sum(double v)
 // tile's stencils share a box of region cells.  Interpolations stage the
 // box's fields in LDS once and read every stencil node from there; spreading
 // accumulates into an LDS copy of the box (int64 fixed point) and adds each
-// touched cell to HBM once.  A box larger than kBoxMax^3 (not expected for
+// touched cell to HBM once.  A box larger than kBoxCells (not expected for
 // the tile span) falls back to per-node HBM access.
 // Tile handled by workgroup b: the dispatcher deals workgroups round-robin
 // over the 8 XCDs, so consecutive blocks are spread and each XCD is given a
@@ -263,8 +296,9 @@ __device__ inline TileBox tile_box_block(const DevPtrs &p, const MarkerTile &mt,
         b.lo[d] = ext[d] - 1;
         b.o[d] = b.lo[d] - B.org[d];
         b.e[d] = ext[3 + d] - ext[d] + 4;
-        b.fits = b.fits && b.e[d] <= kBoxMax && b.o[d] >= 0 && b.o[d] + b.e[d] <= L;
+        b.fits = b.fits && b.o[d] >= 0 && b.o[d] + b.e[d] <= L;
     }
+    b.fits = b.fits && b.e[0] * b.e[1] * b.e[2] <= kBoxCells;
     return b;
 }
 
@@ -291,8 +325,9 @@ __device__ inline int box_region_cell(int i, const TileBox &b, int L)
 }
 
 // Per-marker epilogue of the l = 0 interpolation: plain start, features and
-// the stress-integral parts (v = interpolated rho - 1, u*, sigma).
-__device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B, const double v[kRegFields])
+// the stress-integral parts into o[kPart] (v = interpolated rho - 1, u*, sigma).
+__device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B, const double v[kRegFields],
+                                      double *o)
 {
     const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
     const double pr = (double)CS2 * v[0];
@@ -327,7 +362,6 @@ __device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B,
         p.dh[3 * k + a] = h0[a];
     }
     cross3(rel, s, ts);
-    double *o = p.part + (long long)kPart * k;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         o[a] = dS * s[a];
@@ -336,10 +370,22 @@ __device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B,
     }
 }
 
+// Tile sums of the per-marker parts, in marker order (deterministic).
+__device__ inline void tile_part_sum(const DevPtrs &p, int tix, int count, const double (*tp)[kPart])
+{
+    __syncthreads();
+    if ((int)threadIdx.x < kPart) {
+        double acc = 0.0;
+        for (int j = 0; j < count; j++) acc += tp[j][threadIdx.x];
+        p.part[(long long)kPart * tix + threadIdx.x] = acc;
+    }
+}
+
 // l = 0 and the stress integral over a tile (wave w takes markers w, w+4, ...).
 __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mtiles)
 {
     __shared__ float box[kRegFields][kBoxCells];
+    __shared__ double tp[kTileMarkers][kPart];
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
@@ -376,25 +422,17 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
         }
 #pragma unroll
         for (int f = 0; f < kRegFields; f++) v[f] = wave_sum(v[f]);
-        if (lane == 0) force_epilogue(p, k, B, v);
+        if (lane == 0) force_epilogue(p, k, B, v, tp[j]);
     }
+    tile_part_sum(p, tix, mt.count, tp);
 }
 
-// Force surface variant: the stress integral on the parallel surface at
-// distance force_offset outside the markers (points X_k + delta n_k, same
-// normals, areas dSo).  One wavefront per marker; overwrites the marker's
-// force, torque and pressure parts written by the tile kernel.
-__global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int Mtot)
+// Stress-integral parts of marker k on the parallel surface at distance
+// force_offset outside it (point Y = X_k + delta n_k, same normal, area dSo):
+// one wavefront, parts into o[kPart] by lane 0.
+__device__ inline void offset_part(const DevPtrs &p, int k, const CaseDev &cd, const BodyDev &B, const float *R,
+                                   int L3, int lane, double *o)
 {
-    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (k >= Mtot) return;
-    const int c = p.mcase[k];
-    const CaseDev &cd = p.cases[c];
-    const BodyDev &B = p.body[c];
-    if (B.err != 0 || !(cd.force_offset > 0.0)) return;
-    const int L3 = cd.L * cd.L * cd.L;
-    const float *R = p.reg + cd.reg_off * kRegFields;
     const double nk[3] = {p.N[3 * k], p.N[3 * k + 1], p.N[3 * k + 2]};
     double Y[3];
 #pragma unroll
@@ -420,13 +458,36 @@ __global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int Mtot)
     }
     cross3(rel, s, ts);
     const double dA = p.dSo[k];
-    double *o = p.part + (long long)kPart * k;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         o[a] = dA * s[a];
         o[3 + a] = dA * ts[a];
         o[6 + a] = dA * (-pr) * nk[a];
     }
+}
+
+// Force surface variant: the stress integral on the parallel surface at
+// distance force_offset outside the markers (points X_k + delta n_k, same
+// normals, areas dSo).  One workgroup per marker tile, one wavefront per
+// marker; overwrites the tile's force, torque and pressure sums written by
+// the tile kernel.
+__global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int n_mtiles)
+{
+    __shared__ double tp[kTileMarkers][kPart];
+    const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
+    if (tix >= n_mtiles) return;
+    const MarkerTile mt = p.mtiles[tix];
+    const CaseDev &cd = p.cases[mt.c];
+    const BodyDev &B = p.body[mt.c];
+    if (B.err != 0 || !(cd.force_offset > 0.0)) return;
+    const int L3 = cd.L * cd.L * cd.L;
+    const float *R = p.reg + cd.reg_off * kRegFields;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
+        const int k = mt.first + j;
+        offset_part(p, k, cd, B, R, L3, lane, tp[j]);
+    }
+    tile_part_sum(p, tix, mt.count, tp);
 }
 
 // Spreading of the increments dh over a tile (H += S[dh], h_k += dh): LDS
@@ -488,10 +549,12 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, i
 }
 
 // Interpolation of u* + H over a tile (staged in LDS, FP64), the residual
-// U_k - I[u* + H](X_k) and the next increment dh = that residual.
+// U_k - I[u* + H](X_k), the next increment dh = that residual, and the
+// tile's largest residual component.
 __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked)
 {
     __shared__ double box[3][kBoxCells];
+    __shared__ double wmax[4];
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
@@ -512,6 +575,7 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double res = 0.0;
     for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
         const int k = mt.first + j;
         const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
@@ -530,53 +594,60 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
 #pragma unroll
         for (int a = 0; a < 3; a++) v[a] = wave_sum(v[a]);
         if (lane != 0) continue;
-        double res = 0.0;
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             const double e = p.U[3 * k + a] - v[a];
             res = fmax(res, fabs(e));
             p.dh[3 * k + a] = e;
         }
-        p.res[k] = res;
     }
+    if (lane == 0) wmax[wave] = res;
+    __syncthreads();
+    if (threadIdx.x == 0) p.res[tix] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
 }
 
-// Deterministic FP64 sums of the per-marker parts of one case.
+// Deterministic FP64 sums of the per-tile parts of one case: strided
+// per-thread sums, a fixed butterfly inside each wavefront, then the
+// wavefronts in order.
 __global__ void __launch_bounds__(1024) k_reduce_ft(DevPtrs p)
 {
-    __shared__ double sh[kPart][1024];
+    __shared__ double sh[16][kPart];
     const int c = blockIdx.x;
     const CaseDev &cd = p.cases[c];
     if (cd.M == 0 || p.body[c].err != 0) return;
     double acc[kPart];
 #pragma unroll
     for (int j = 0; j < kPart; j++) acc[j] = 0.0;
-    for (int k = threadIdx.x; k < cd.M; k += blockDim.x) {
-        const double *o = p.part + (long long)kPart * (cd.marker_off + k);
+    for (int t = threadIdx.x; t < cd.n_tiles; t += blockDim.x) {
+        const double *o = p.part + (long long)kPart * (cd.tile_off + t);
 #pragma unroll
         for (int j = 0; j < kPart; j++) acc[j] += o[j];
     }
 #pragma unroll
-    for (int j = 0; j < kPart; j++) sh[j][threadIdx.x] = acc[j];
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
+    for (int j = 0; j < kPart; j++) acc[j] = wave_sum(acc[j]);
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0)
 #pragma unroll
-            for (int j = 0; j < kPart; j++) sh[j][threadIdx.x] += sh[j][threadIdx.x + s];
-        __syncthreads();
+        for (int j = 0; j < kPart; j++) sh[wave][j] = acc[j];
+    __syncthreads();
+    if (threadIdx.x < kPart) {
+        double v = 0.0;
+        for (int w = 0; w < nw; w++) v += sh[w][threadIdx.x];
+        sh[0][threadIdx.x] = v;   // each thread reads and writes only its own column
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         BodyDev &B = p.body[c];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            B.F[a] = sh[a][0];
-            B.T[a] = sh[3 + a][0];
-            B.Fp[a] = sh[6 + a][0];
+            B.F[a] = sh[0][a];
+            B.T[a] = sh[0][3 + a];
+            B.Fp[a] = sh[0][6 + a];
         }
     }
 }
 
-// Max residual over the markers of a case: into resid and resid_hist[slot].
+// Max residual over the tiles of a case: into resid and resid_hist[slot].
 // With masked set only cases still active are reduced; with gate_cycle > 0
 // (a learned-start cycle) a case whose residual is at or below its gate is
 // accepted and leaves the sequence.
@@ -587,7 +658,7 @@ __global__ void __launch_bounds__(1024) k_reduce_resid(DevPtrs p, int slot, int 
     const CaseDev &cd = p.cases[c];
     if (cd.M == 0 || p.body[c].err != 0 || (masked && !p.body[c].active)) return;
     double m = 0.0;
-    for (int k = threadIdx.x; k < cd.M; k += blockDim.x) m = fmax(m, p.res[cd.marker_off + k]);
+    for (int t = threadIdx.x; t < cd.n_tiles; t += blockDim.x) m = fmax(m, p.res[cd.tile_off + t]);
     sh[threadIdx.x] = m;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -665,7 +736,7 @@ __global__ void k_fallback_zero(DevPtrs p)
     if (cd.M == 0 || B.err != 0 || !B.fallback) return;
     const int L3 = cd.L * cd.L * cd.L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= L3) return;
+    if (q >= L3 || !p.mark[cd.reg_off + q]) return;
     long long *H = p.H + cd.reg_off * 3;
     H[q] = 0;
     H[L3 + q] = 0;
@@ -686,7 +757,8 @@ __global__ void k_targets(DevPtrs p, int Mtot, float *out)
 // Forced collision of Sec. 2.2: the lattice kernel wrote
 // f0(rho, u) + (1 - 1/tau) f1; cells carrying an immersed force get
 // f0(rho, u + tau h) - f0(rho, u) added (in the momentum-exact variant less
-// the first-order term w_i xi_i . (tau - 1) rho h / cs^2).
+// the first-order term w_i xi_i . (tau - 1) rho h / cs^2).  Only cells
+// marked this step can carry a force; their marks are cleared here.
 template <class CD>
 __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
 {
@@ -697,6 +769,9 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
     const int L = cd.L, L3 = L * L * L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= L3) return;
+    unsigned char &mk = p.mark[cd.reg_off + q];
+    if (!mk) return;
+    mk = 0;
     const int a = q % L, b = (q / L) % L, cc = q / (L * L);
     const int gz = B.org[2] + cc;
     if (gz < 0 || gz >= cd.nz) return;
@@ -788,10 +863,10 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     const dim3 reg_grid((maxL3 + 255) / 256, n_cases);
     const dim3 tile_grid((n_mtiles + 7) / 8 * 8);
     const dim3 mark_grid((Mtot + 255) / 256);
-    hipLaunchKernelGGL(k_markers, mark_grid, blk, 0, s, p, Mtot);
+    hipLaunchKernelGGL(k_markers, dim3((Mtot + 3) / 4), blk, 0, s, p, Mtot);
     hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
     hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p, n_mtiles);
-    if (force_surface) hipLaunchKernelGGL(k_offset_force, dim3((Mtot + 3) / 4), blk, 0, s, p, Mtot);
+    if (force_surface) hipLaunchKernelGGL(k_offset_force, tile_grid, blk, 0, s, p, n_mtiles);
     hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), dim3(1024), 0, s, p);
     // one sequence of multi-direct forcing cycles (Sec. 2.2, l = 1..4): spread
     // the increment, then interpolate and form the next increment; the
