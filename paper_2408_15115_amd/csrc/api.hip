@@ -253,7 +253,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_part = take(sizeof(double) * kPart * NT);
     P.off_res = take(sizeof(double) * NT);
     P.off_reg = take(sizeof(float) * kRegFields * std::max<long long>(reg, 1));
-    P.off_H = take(sizeof(long long) * 3 * std::max<long long>(reg, 1));
+    P.off_H = take(sizeof(long long) * 3 * kHBufs * std::max<long long>(reg, 1));
     P.off_mark = take((size_t)std::max<long long>(reg, 1));
     P.off_feat = take(sizeof(float) * kMlpIn * M);
     P.off_h0 = take(sizeof(double) * 3 * M);
@@ -395,6 +395,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.res = (double *)(a + P.off_res);
     p.reg = (float *)(a + P.off_reg);
     p.H = (long long *)(a + P.off_H);
+    p.hstride = 3 * std::max<long long>(P.reg_cells, 1);
     p.mark = (unsigned char *)(a + P.off_mark);
     p.mtiles = (MarkerTile *)(a + P.off_mtiles);
     p.feat = (float *)(a + P.off_feat);

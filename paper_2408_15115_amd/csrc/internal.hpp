@@ -67,14 +67,21 @@ struct TileBox {
 constexpr int kTileMarkers = 16;
 constexpr double kTileSpan = 3.0;
 // LDS box capacity: a tile spans at most kTileSpan per axis in the body frame,
-// so its box is at most 7^3 cells axis-aligned and stays below 8^3 in the
-// rotations measured (a 448-cell maximum over random orientations of the
-// 12k-marker ellipsoid); larger boxes take the per-node HBM path.
-constexpr int kBoxCells = 512;
+// so its box is at most 7^3 cells axis-aligned and stays at or below 448
+// cells in the rotations measured (random orientations of the 12k-marker
+// ellipsoid); larger boxes take the per-node HBM path.  480 keeps the force
+// kernel (10 FP32 fields + 3 int64 accumulators per cell) under 32 KB of LDS,
+// five workgroups per CU.
+constexpr int kBoxCells = 480;
 
 // Fixed-point scale of the deterministic immersed-force accumulator.
 constexpr double kFixScale = 1099511627776.0;   // 2^40
 constexpr double kFixInv = 1.0 / 1099511627776.0;
+// Immersed-force accumulators: the spread of forcing cycle c goes to
+// accumulator c - 1, so that one kernel can interpolate cycle c (reading
+// accumulators 0 .. c-1) and spread cycle c + 1 without a race; their sum is
+// the immersed force H.  Paths with more cycles use accumulator 0 alone.
+constexpr int kHBufs = 4;
 
 // Per-tile partial sums written by the force kernels: F(3) T(3) Fp(3).
 constexpr int kPart = 9;
@@ -92,7 +99,8 @@ struct DevPtrs {
     double *res;     // per-tile max residual of the last interpolation
     unsigned char *mark;   // per region cell: 1 if inside a stencil this step
     float *reg;
-    long long *H;
+    long long *H;    // kHBufs fixed-point immersed-force accumulators, hstride elements apart
+    long long hstride;
     int *counter;    // 8 work-queue counters of the persistent lattice schedule
     MarkerTile *mtiles;
     float *feat;     // per-marker warm-start features (12)

@@ -6,9 +6,11 @@
 //   k_markers             Sec. 2.3: marker position, normal and rigid velocity
 //   k_region_gather       Sec. 2.1 stress and Sec. 2.2 u* on the particle region
 //   k_interp_force_tiles  Sec. 2.2: l = 0 interpolation and the stress integral
+//                         (+ the first spread)
 //   k_reduce_ft           FP64 force / torque sums (deterministic tree)
 //   k_spread_tiles        Sec. 2.2 spreading (deterministic fixed-point atomics)
 //   k_interp_update_tiles Sec. 2.2 interpolation of u* + H and the residual
+//                         (+ the next cycle's spread)
 //   k_correct             Sec. 2.2 forced rule: add f0(u + tau h) - f0(u)
 //   k_window_*            Sec. 2.5 re-injection as a ring-origin shift
 //
@@ -179,9 +181,12 @@ __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs 
     if (q >= L3 || !p.mark[cd.reg_off + q]) return;
     float *R = p.reg + cd.reg_off * kRegFields;
     long long *H = p.H + cd.reg_off * 3;
-    H[q] = 0;
-    H[L3 + q] = 0;
-    H[2 * L3 + q] = 0;
+#pragma unroll
+    for (int j = 0; j < kHBufs; j++) {
+        H[j * p.hstride + q] = 0;
+        H[j * p.hstride + L3 + q] = 0;
+        H[j * p.hstride + 2 * L3 + q] = 0;
+    }
     const int a = q % L, b = (q / L) % L, cc = q / (L * L);
     const int gz = B.org[2] + cc;
     if (gz < 0 || gz >= cd.nz) {
@@ -381,10 +386,44 @@ __device__ inline void tile_part_sum(const DevPtrs &p, int tix, int count, const
     }
 }
 
+// Spread of one marker's increment d (held by every lane) through the lane's
+// stencil node with weight W dS_k: fixed point, into the tile's LDS
+// accumulator (box cell i) or, when the box does not fit, straight into the
+// region accumulator Hc (region cell q, -1 outside).
+__device__ inline void spread_node(const DevPtrs &p, int c, const TileBox &tb, int i, int q, double wS,
+                                   const double d[3], unsigned long long (*acc)[kBoxCells], long long *Hc, int L3)
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double v = d[a] * wS;
+        long long fx = 0;
+        if (fabs(v) < 1.0e6) fx = __double2ll_rn(v * kFixScale);
+        else atomicOr(&p.body[c].err, 2);
+        if (tb.fits) atomicAdd(&acc[a][i], (unsigned long long)fx);
+        else if (q >= 0) atomicAdd((unsigned long long *)&Hc[a * L3 + q], (unsigned long long)fx);
+    }
+}
+
+// The tile's LDS accumulator into the region accumulator: one global atomic
+// per touched cell and component (after a barrier).
+__device__ inline void spread_flush(const TileBox &tb, int ncell, int L, int L3,
+                                    const unsigned long long (*acc)[kBoxCells], long long *Hc)
+{
+    for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+        const int q = box_region_cell(i, tb, L);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+            if (acc[a][i] != 0ull) atomicAdd((unsigned long long *)&Hc[a * L3 + q], acc[a][i]);
+    }
+}
+
 // l = 0 and the stress integral over a tile (wave w takes markers w, w+4, ...).
-__global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mtiles)
+// With spread set, also the first forcing cycle's spread of the plain start
+// h0 into accumulator 0 (h_k = h0).
+__global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mtiles, int spread)
 {
     __shared__ float box[kRegFields][kBoxCells];
+    __shared__ unsigned long long acc[3][kBoxCells];
     __shared__ double tp[kTileMarkers][kPart];
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
@@ -394,6 +433,7 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
     if (B.err != 0) return;
     const int L = cd.L, L3 = L * L * L;
     const float *R = p.reg + cd.reg_off * kRegFields;
+    long long *H0 = p.H + cd.reg_off * 3;
     const TileBox tb = tile_box_block(p, mt, B, L);
     if (threadIdx.x == 0) p.tbox[tix] = tb;
     const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
@@ -402,6 +442,7 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
             const int q = box_region_cell(i, tb, L);
 #pragma unroll
             for (int f = 0; f < kRegFields; f++) box[f][i] = R[f * L3 + q];
+            acc[0][i] = acc[1][i] = acc[2][i] = 0ull;
         }
     }
     __syncthreads();
@@ -410,21 +451,33 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
         const int k = mt.first + j;
         const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
         double v[kRegFields];
+        double W;
+        int i = 0, q = -1;
         if (tb.fits) {
-            double W;
-            const int i = box_node(X, lane, tb, W);
+            i = box_node(X, lane, tb, W);
 #pragma unroll
             for (int f = 0; f < kRegFields; f++) v[f] = W * (double)box[f][i];
         } else {
             const Node nd = stencil_node(X, lane, cd, B);
+            W = nd.W;
+            q = nd.q;
 #pragma unroll
-            for (int f = 0; f < kRegFields; f++) v[f] = nd.q >= 0 ? nd.W * (double)R[f * L3 + nd.q] : 0.0;
+            for (int f = 0; f < kRegFields; f++) v[f] = q >= 0 ? W * (double)R[f * L3 + q] : 0.0;
         }
+        // the butterfly leaves the same sum in every lane
 #pragma unroll
         for (int f = 0; f < kRegFields; f++) v[f] = wave_sum(v[f]);
         if (lane == 0) force_epilogue(p, k, B, v, tp[j]);
+        if (spread) {
+            const double h0[3] = {p.U[3 * k] - v[1], p.U[3 * k + 1] - v[2], p.U[3 * k + 2] - v[3]};
+            if (lane == 0)
+#pragma unroll
+                for (int a = 0; a < 3; a++) p.hk[3 * k + a] += h0[a];
+            spread_node(p, mt.c, tb, i, q, W * p.dS[k], h0, acc, H0, L3);
+        }
     }
     tile_part_sum(p, tix, mt.count, tp);
+    if (spread && tb.fits) spread_flush(tb, ncell, L, L3, acc, H0);
 }
 
 // Stress-integral parts of marker k on the parallel surface at distance
@@ -490,9 +543,9 @@ __global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int n_mtiles)
     tile_part_sum(p, tix, mt.count, tp);
 }
 
-// Spreading of the increments dh over a tile (H += S[dh], h_k += dh): LDS
-// accumulation, then one HBM atomic per touched cell.  With masked set, cases
-// whose sequence has ended are skipped.
+// Spreading of the increments dh over a tile into accumulator 0 (H += S[dh],
+// h_k += dh): LDS accumulation, then one HBM atomic per touched cell.  With
+// masked set, cases whose sequence has ended are skipped.
 __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, int masked)
 {
     __shared__ unsigned long long acc[3][kBoxCells];
@@ -523,37 +576,27 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, i
             W = nd.W;
             q = nd.q;
         }
-        const double wS = W * p.dS[k];
         const double dh[3] = {p.dh[3 * k], p.dh[3 * k + 1], p.dh[3 * k + 2]};
         if (lane == 0)
 #pragma unroll
             for (int a = 0; a < 3; a++) p.hk[3 * k + a] += dh[a];
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            const double v = dh[a] * wS;
-            long long fx = 0;
-            if (fabs(v) < 1.0e6) fx = __double2ll_rn(v * kFixScale);
-            else atomicOr(&p.body[mt.c].err, 2);
-            if (tb.fits) atomicAdd(&acc[a][i], (unsigned long long)fx);
-            else if (q >= 0) atomicAdd((unsigned long long *)&H[a * L3 + q], (unsigned long long)fx);
-        }
+        spread_node(p, mt.c, tb, i, q, W * p.dS[k], dh, acc, H, L3);
     }
     __syncthreads();
-    if (!tb.fits) return;
-    for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
-        const int q = box_region_cell(i, tb, L);
-#pragma unroll
-        for (int a = 0; a < 3; a++)
-            if (acc[a][i] != 0ull) atomicAdd((unsigned long long *)&H[a * L3 + q], acc[a][i]);
-    }
+    if (tb.fits) spread_flush(tb, ncell, L, L3, acc, H);
 }
 
-// Interpolation of u* + H over a tile (staged in LDS, FP64), the residual
-// U_k - I[u* + H](X_k), the next increment dh = that residual, and the
-// tile's largest residual component.
-__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked)
+// Interpolation of u* + H over a tile (staged in LDS, FP64; H the sum of
+// accumulators 0 .. nbuf-1), the residual U_k - I[u* + H](X_k), the next
+// increment dh = that residual, and the tile's largest residual component.
+// With spread_to >= 0 the same pass spreads dh (the next cycle's spread,
+// h_k += dh) into accumulator spread_to, which no interpolation of this
+// pass reads.
+__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked, int nbuf,
+                                                             int spread_to)
 {
     __shared__ double box[3][kBoxCells];
+    __shared__ unsigned long long acc[3][kBoxCells];
     __shared__ double wmax[4];
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
@@ -564,13 +607,23 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
     const int L = cd.L, L3 = L * L * L;
     const float *R = p.reg + cd.reg_off * kRegFields;
     const long long *H = p.H + cd.reg_off * 3;
+    long long *Hs = p.H + (spread_to > 0 ? spread_to : 0) * p.hstride + cd.reg_off * 3;
     const TileBox tb = p.tbox[tix];
     const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
+    // H at region cell q and component a: the exact integer sum of the accumulators
+    auto h_at = [&](int a, int q) {
+        long long h = H[a * L3 + q];
+        for (int b = 1; b < nbuf; b++) h += H[b * p.hstride + a * L3 + q];
+        return h;
+    };
     if (tb.fits) {
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
             const int q = box_region_cell(i, tb, L);
 #pragma unroll
-            for (int a = 0; a < 3; a++) box[a][i] = (double)R[(1 + a) * L3 + q] + (double)H[a * L3 + q] * kFixInv;
+            for (int a = 0; a < 3; a++) {
+                box[a][i] = (double)R[(1 + a) * L3 + q] + (double)h_at(a, q) * kFixInv;
+                acc[a][i] = 0ull;
+            }
         }
     }
     __syncthreads();
@@ -580,30 +633,38 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
         const int k = mt.first + j;
         const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
         double v[3];
+        double W;
+        int i = 0, q = -1;
         if (tb.fits) {
-            double W;
-            const int i = box_node(X, lane, tb, W);
+            i = box_node(X, lane, tb, W);
 #pragma unroll
             for (int a = 0; a < 3; a++) v[a] = W * box[a][i];
         } else {
             const Node nd = stencil_node(X, lane, cd, B);
+            W = nd.W;
+            q = nd.q;
 #pragma unroll
             for (int a = 0; a < 3; a++)
-                v[a] = nd.q >= 0 ? nd.W * ((double)R[(1 + a) * L3 + nd.q] + (double)H[a * L3 + nd.q] * kFixInv) : 0.0;
+                v[a] = q >= 0 ? W * ((double)R[(1 + a) * L3 + q] + (double)h_at(a, q) * kFixInv) : 0.0;
         }
+        // the butterfly leaves the same sum in every lane
 #pragma unroll
         for (int a = 0; a < 3; a++) v[a] = wave_sum(v[a]);
-        if (lane != 0) continue;
+        const double e[3] = {p.U[3 * k] - v[0], p.U[3 * k + 1] - v[1], p.U[3 * k + 2] - v[2]};
+        if (lane == 0) {
 #pragma unroll
-        for (int a = 0; a < 3; a++) {
-            const double e = p.U[3 * k + a] - v[a];
-            res = fmax(res, fabs(e));
-            p.dh[3 * k + a] = e;
+            for (int a = 0; a < 3; a++) {
+                res = fmax(res, fabs(e[a]));
+                p.dh[3 * k + a] = e[a];
+                if (spread_to >= 0) p.hk[3 * k + a] += e[a];
+            }
         }
+        if (spread_to >= 0) spread_node(p, mt.c, tb, i, q, W * p.dS[k], e, acc, Hs, L3);
     }
     if (lane == 0) wmax[wave] = res;
     __syncthreads();
     if (threadIdx.x == 0) p.res[tix] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    if (spread_to >= 0 && tb.fits) spread_flush(tb, ncell, L, L3, acc, Hs);
 }
 
 // Deterministic FP64 sums of the per-tile parts of one case: strided
@@ -738,9 +799,12 @@ __global__ void k_fallback_zero(DevPtrs p)
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= L3 || !p.mark[cd.reg_off + q]) return;
     long long *H = p.H + cd.reg_off * 3;
-    H[q] = 0;
-    H[L3 + q] = 0;
-    H[2 * L3 + q] = 0;
+#pragma unroll
+    for (int j = 0; j < kHBufs; j++) {
+        H[j * p.hstride + q] = 0;
+        H[j * p.hstride + L3 + q] = 0;
+        H[j * p.hstride + 2 * L3 + q] = 0;
+    }
 }
 
 // Training targets: the final h_k minus the previous step's h, over the
@@ -776,7 +840,13 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
     const int gz = B.org[2] + cc;
     if (gz < 0 || gz >= cd.nz) return;
     const long long *H = p.H + cd.reg_off * 3;
-    const long long h0 = H[q], h1 = H[L3 + q], h2 = H[2 * L3 + q];
+    long long h0 = 0, h1 = 0, h2 = 0;
+#pragma unroll
+    for (int j = 0; j < kHBufs; j++) {
+        h0 += H[j * p.hstride + q];
+        h1 += H[j * p.hstride + L3 + q];
+        h2 += H[j * p.hstride + 2 * L3 + q];
+    }
     if ((h0 | h1 | h2) == 0) return;
     const float *R = p.reg + cd.reg_off * kRegFields;
     const float rho = 1.0f + R[q];
@@ -865,7 +935,10 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     const dim3 mark_grid((Mtot + 255) / 256);
     hipLaunchKernelGGL(k_markers, dim3((Mtot + 3) / 4), blk, 0, s, p, Mtot);
     hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
-    hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p, n_mtiles);
+    // plain start with at most kHBufs cycles: each cycle's spread rides on
+    // the pass before it (force + spread 1, update c + spread c + 1)
+    const int fused = warm_mode == 0 && cycles <= kHBufs;
+    hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p, n_mtiles, fused);
     if (force_surface) hipLaunchKernelGGL(k_offset_force, tile_grid, blk, 0, s, p, n_mtiles);
     hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), dim3(1024), 0, s, p);
     // one sequence of multi-direct forcing cycles (Sec. 2.2, l = 1..4): spread
@@ -874,11 +947,21 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     auto sequence = [&](int ncyc, int slot0, int masked) {
         for (int cyc = 1; cyc <= ncyc; cyc++) {
             hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, masked);
-            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, masked);
+            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, masked, 1, -1);
             if (diag || cyc == ncyc)
                 hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, slot0 + cyc - 1, masked, 0);
         }
     };
+    if (fused) {
+        for (int cyc = 1; cyc <= cycles; cyc++) {
+            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, 0, cyc,
+                               cyc < cycles ? cyc : -1);
+            if (diag || cyc == cycles)
+                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, cyc - 1, 0, 0);
+        }
+        (void)cur;
+        return hipGetLastError();
+    }
     if (warm_mode != 0) {
         // learned (or previous-h) start: cycles until the case's residual is
         // at or below its gate, at most warm_cycles; the rest restart plain
@@ -892,7 +975,7 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
         hipLaunchKernelGGL(k_gate_begin, case_grid, case_blk, 0, s, p, n_cases);
         for (int cyc = 1; cyc <= warm_cycles; cyc++) {
             hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, 1);
-            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, 1);
+            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, 1, 1, -1);
             hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, cyc - 1, 1, cyc);
         }
         hipLaunchKernelGGL(k_gate, case_grid, case_blk, 0, s, p, n_cases);
