@@ -3,7 +3,8 @@
 // and their stream launchers.
 //
 //   k_body_advance        Sec. 2.3: leapfrog / predictor-corrector, FP64
-//   k_markers             Sec. 2.3: marker position, normal and rigid velocity
+//   k_markers             Sec. 2.3: marker position, normal and rigid velocity;
+//                         tile boxes and the marks of the cells they cover
 //   k_region_gather       Sec. 2.1 stress and Sec. 2.2 u* on the particle region
 //   k_interp_force_tiles  Sec. 2.2: l = 0 interpolation and the stress integral
 //                         (+ the first spread)
@@ -99,82 +100,44 @@ __global__ void k_body_advance(DevPtrs p, int n_cases)
 }
 
 // X_k = r + sum_j xb_kj d_j, n_k = sum_j nb_kj d_j, U_k = v + w x (X_k - r).
-// Marks stencil node `lane` of the point X as used in this step (region
-// cells outside every stencil are neither gathered nor corrected).
-__device__ inline void mark_node(const DevPtrs &p, const CaseDev &cd, const BodyDev &B, const double X[3], int lane)
+// The body fields the region and marker kernels read, copied into registers
+// at a kernel's start: after the kernel's first global store the compiler
+// must assume the body record may have changed and would reload each field
+// with a vector load and a wait of its own.
+struct BodyView {
+    int err, active;
+    int org[3];
+    int z0;
+    double r[3];
+};
+
+__device__ inline BodyView body_view(const BodyDev &B)
 {
-    const int off[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
-    const int n[3] = {cd.nx, cd.ny, cd.nz};
-    const int L = cd.L;
-    int r[3];
-    bool ok = true;
+    BodyView v;
+    v.err = B.err;
+    v.active = B.active;
+    v.z0 = B.z0;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        int rel = (int)floor(X[d]) - 1 + off[d] - B.org[d];
-        if (d < 2) rel = wrapi(rel, n[d]);
-        ok = ok && rel >= 0 && rel < L;
-        r[d] = rel;
+        v.org[d] = B.org[d];
+        v.r[d] = B.r[d];
     }
-    if (ok) p.mark[cd.reg_off + r[0] + L * (r[1] + L * r[2])] = 1;
-}
-
-// One wavefront per marker: every lane forms the marker's position; lane 0
-// stores X, n, U and checks the z range; lane l marks stencil node l of the
-// marker (and of its force-surface point).
-__global__ void __launch_bounds__(256) k_markers(DevPtrs p, int Mtot)
-{
-    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (k >= Mtot) return;
-    const int c = p.mcase[k];
-    const CaseDev &cd = p.cases[c];
-    const BodyDev &B = p.body[c];
-    if (B.err != 0) return;
-    const double xb[3] = {p.xb[3 * k], p.xb[3 * k + 1], p.xb[3 * k + 2]};
-    const double nb[3] = {p.nb[3 * k], p.nb[3 * k + 1], p.nb[3 * k + 2]};
-    double X[3], N[3], rel[3], wr[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        X[a] = B.r[a] + xb[0] * B.d[a] + xb[1] * B.d[3 + a] + xb[2] * B.d[6 + a];
-        N[a] = nb[0] * B.d[a] + nb[1] * B.d[3 + a] + nb[2] * B.d[6 + a];
-        rel[a] = X[a] - B.r[a];
-    }
-    const double dl = cd.force_offset;
-    if (lane == 0) {
-        cross3(B.w, rel, wr);
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            p.X[3 * k + a] = X[a];
-            p.N[3 * k + a] = N[a];
-            p.U[3 * k + a] = B.v[a] + wr[a];
-        }
-        const int fz = (int)floor(X[2]);
-        if (fz - 1 < 0 || fz + 2 > cd.nz - 1) atomicOr(&p.body[c].err, 1);
-        if (dl > 0.0) {
-            const int gz = (int)floor(X[2] + dl * N[2]);
-            if (gz - 1 < 0 || gz + 2 > cd.nz - 1) atomicOr(&p.body[c].err, 1);
-        }
-    }
-    mark_node(p, cd, B, X, lane);
-    if (dl > 0.0) {
-        const double Y[3] = {X[0] + dl * N[0], X[1] + dl * N[1], X[2] + dl * N[2]};
-        mark_node(p, cd, B, Y, lane);
-    }
+    return v;
 }
 
 // ------------------------------------------------------------ region fields
 // For every cell of the particle region: pull f(t+1) from the buffer the
 // lattice kernel read, then rho - 1, u* = sum xi f / sum f and the stress
 // sigma = -p I + (1/(2 tau) - 1) P1 with p = cs^2 (rho - 1) (Sec. 2.1).
-// Also clears the fixed-point immersed-force accumulator.  Only cells marked
-// by k_markers (inside some stencil) are visited; the others are read by no
-// interpolation and carry no force.
+// Also clears the fixed-point immersed-force accumulators.  Only cells marked
+// by k_markers (inside some tile's stencil box) are visited; the others are
+// read by no interpolation and carry no force.
 template <class CD>
 __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs p)
 {
     const int c = blockIdx.y;
-    const CaseDev &cd = p.cases[c];
-    const BodyDev &B = p.body[c];
+    const CaseDev cd = p.cases[c];
+    const BodyView B = body_view(p.body[c]);
     if (cd.M == 0 || B.err != 0) return;
     const int L = cd.L, L3 = L * L * L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -215,12 +178,16 @@ __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs 
 
 // --------------------------------------------------------- marker stencils
 // One-dimensional four-point weight function of Sec. 2.2 (two branches).
+// Written without branches (one square root per call): the lanes of a
+// stencil fall on both branches.
 __device__ inline double phi4(double r)
 {
     const double a = fabs(r);
-    if (a <= 1.0) return 0.125 * (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a));
-    if (a <= 2.0) return 0.125 * (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
-    return 0.0;
+    const bool inner = a <= 1.0;
+    const double arg = inner ? 1.0 + 4.0 * a - 4.0 * a * a : -7.0 + 12.0 * a - 4.0 * a * a;
+    const double sq = sqrt(fmax(arg, 0.0));   // arg >= 1 wherever the value is used
+    const double v = inner ? 0.125 * (3.0 - 2.0 * a + sq) : 0.125 * (5.0 - 2.0 * a - sq);
+    return a <= 2.0 ? v : 0.0;
 }
 
 struct Node {
@@ -228,7 +195,7 @@ struct Node {
     double W;     // tensor-product weight
 };
 
-__device__ inline Node stencil_node(const double X[3], int lane, const CaseDev &cd, const BodyDev &B)
+__device__ inline Node stencil_node(const double X[3], int lane, const CaseDev &cd, const BodyView &B)
 {
     const int off[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
     const int n[3] = {cd.nx, cd.ny, cd.nz};
@@ -274,39 +241,6 @@ __device__ inline int tile_of_block(int b, int n)
     return (b & 7) * per + (b >> 3);
 }
 
-// Box of a tile (once per step, by the force kernel; the marker positions do
-// not change during the cycles): one thread per marker, LDS min / max.
-__device__ inline TileBox tile_box_block(const DevPtrs &p, const MarkerTile &mt, const BodyDev &B, int L)
-{
-    __shared__ int ext[6];
-    if (threadIdx.x < 3) {
-        ext[threadIdx.x] = 1 << 30;
-        ext[3 + threadIdx.x] = -(1 << 30);
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < mt.count) {
-        const int k = mt.first + (int)threadIdx.x;
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            const int f = (int)floor(p.X[3 * k + d]);
-            atomicMin(&ext[d], f);
-            atomicMax(&ext[3 + d], f);
-        }
-    }
-    __syncthreads();
-    TileBox b;
-    b.fits = 1;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        b.lo[d] = ext[d] - 1;
-        b.o[d] = b.lo[d] - B.org[d];
-        b.e[d] = ext[3 + d] - ext[d] + 4;
-        b.fits = b.fits && b.o[d] >= 0 && b.o[d] + b.e[d] <= L;
-    }
-    b.fits = b.fits && b.e[0] * b.e[1] * b.e[2] <= kBoxCells;
-    return b;
-}
-
 // Box-local index of a lane's stencil node, and its weight.
 __device__ inline int box_node(const double X[3], int lane, const TileBox &b, double &W)
 {
@@ -329,11 +263,133 @@ __device__ inline int box_region_cell(int i, const TileBox &b, int L)
     return (b.o[0] + bx) + L * ((b.o[1] + by) + L * (b.o[2] + bz));
 }
 
-// Per-marker epilogue of the l = 0 interpolation: plain start, features and
-// the stress-integral parts into o[kPart] (v = interpolated rho - 1, u*, sigma).
-__device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B, const double v[kRegFields],
-                                      double *o)
+// Marks stencil node `lane` of the point X as used in this step (region
+// cells outside every stencil are neither gathered nor corrected).
+__device__ inline void mark_node(const DevPtrs &p, const CaseDev &cd, const BodyView &B, const double X[3], int lane)
 {
+    const int off[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+    const int n[3] = {cd.nx, cd.ny, cd.nz};
+    const int L = cd.L;
+    int r[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        int rel = (int)floor(X[d]) - 1 + off[d] - B.org[d];
+        if (d < 2) rel = wrapi(rel, n[d]);
+        ok = ok && rel >= 0 && rel < L;
+        r[d] = rel;
+    }
+    if (ok) p.mark[cd.reg_off + r[0] + L * (r[1] + L * r[2])] = 1;
+}
+
+// Box of the stencil nodes of the points P held by the lanes with `on` set
+// (at least one): first node lo = min floor(P) - 1 and extent
+// max floor(P) - min floor(P) + 4 per axis, by butterfly min / max.
+__device__ inline void wave_box(const double P[3], bool on, int lo[3], int e[3])
+{
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int f = (int)floor(P[d]);
+        int mn = on ? f : (1 << 30), mx = on ? f : -(1 << 30);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = min(mn, __shfl_xor(mn, o));
+            mx = max(mx, __shfl_xor(mx, o));
+        }
+        lo[d] = mn - 1;
+        e[d] = mx - mn + 4;
+    }
+}
+
+// Marks the stencil cells of the tile's points P (lane j < count holds
+// point j): the whole box when it lies inside the region, else node by node.
+// Returns the box as a TileBox.
+__device__ inline TileBox mark_points(const DevPtrs &p, const CaseDev &cd, const BodyView &B, const double P[3],
+                                      int count, int lane)
+{
+    TileBox b;
+    wave_box(P, lane < count, b.lo, b.e);
+    const int L = cd.L;
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        b.o[d] = b.lo[d] - B.org[d];
+        in = in && b.o[d] >= 0 && b.o[d] + b.e[d] <= L;
+    }
+    const int n = b.e[0] * b.e[1] * b.e[2];
+    b.fits = in && n <= kBoxCells;
+    if (in) {
+        unsigned char *mk = p.mark + cd.reg_off;
+        for (int i = lane; i < n; i += 64) mk[box_region_cell(i, b, L)] = 1;
+    } else {
+        for (int j = 0; j < count; j++) {
+            const double Pj[3] = {__shfl(P[0], j), __shfl(P[1], j), __shfl(P[2], j)};
+            mark_node(p, cd, B, Pj, lane);
+        }
+    }
+    return b;
+}
+
+// One wavefront per marker tile (Sec. 2.3 kinematics): lane j < count forms
+// the position, normal and rigid velocity of marker first + j and checks the
+// z range; the tile's stencil box goes to the tile table, and the cells of
+// that box (and of the force-surface points' box) are marked for this step.
+__global__ void __launch_bounds__(64) k_markers(DevPtrs p, int n_mtiles)
+{
+    const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
+    if (tix >= n_mtiles) return;
+    const MarkerTile mt = p.mtiles[tix];
+    const CaseDev cd = p.cases[mt.c];
+    const BodyDev &Bd = p.body[mt.c];
+    const BodyView B = body_view(Bd);
+    if (B.err != 0) return;
+    const int lane = threadIdx.x;
+    const bool on = lane < mt.count;
+    const int k = mt.first + (on ? lane : 0);
+    const double xb[3] = {p.xb[3 * k], p.xb[3 * k + 1], p.xb[3 * k + 2]};
+    const double nb[3] = {p.nb[3 * k], p.nb[3 * k + 1], p.nb[3 * k + 2]};
+    double X[3], N[3], rel[3], wr[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        X[a] = B.r[a] + xb[0] * Bd.d[a] + xb[1] * Bd.d[3 + a] + xb[2] * Bd.d[6 + a];
+        N[a] = nb[0] * Bd.d[a] + nb[1] * Bd.d[3 + a] + nb[2] * Bd.d[6 + a];
+        rel[a] = X[a] - B.r[a];
+    }
+    const double w[3] = {Bd.w[0], Bd.w[1], Bd.w[2]}, vb[3] = {Bd.v[0], Bd.v[1], Bd.v[2]};
+    const double dl = cd.force_offset;
+    if (on) {
+        cross3(w, rel, wr);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            p.X[3 * k + a] = X[a];
+            p.N[3 * k + a] = N[a];
+            p.U[3 * k + a] = vb[a] + wr[a];
+        }
+        const int fz = (int)floor(X[2]);
+        if (fz - 1 < 0 || fz + 2 > cd.nz - 1) atomicOr(&p.body[mt.c].err, 1);
+        if (dl > 0.0) {
+            const int gz = (int)floor(X[2] + dl * N[2]);
+            if (gz - 1 < 0 || gz + 2 > cd.nz - 1) atomicOr(&p.body[mt.c].err, 1);
+        }
+    }
+    const TileBox tb = mark_points(p, cd, B, X, mt.count, lane);
+    if (lane == 0) p.tbox[tix] = tb;
+    if (dl > 0.0) {
+        const double Y[3] = {X[0] + dl * N[0], X[1] + dl * N[1], X[2] + dl * N[2]};
+        mark_points(p, cd, B, Y, mt.count, lane);
+    }
+}
+
+// Per-marker epilogue of the l = 0 interpolation: plain start, features and
+// the stress-integral parts into o[kPart] (vin = interpolated rho - 1, u*,
+// sigma; o may alias vin).  h_k becomes h0 when the first spread has been
+// done (spread set), else 0.
+__device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyView &B, const double *vin, double *o,
+                                      int spread)
+{
+    double v[kRegFields];
+#pragma unroll
+    for (int f = 0; f < kRegFields; f++) v[f] = vin[f];
     const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
     const double pr = (double)CS2 * v[0];
     const double sg[3][3] = {{v[4], v[7], v[8]}, {v[7], v[5], v[9]}, {v[8], v[9], v[6]}};
@@ -363,7 +419,7 @@ __device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B,
         ft[9 + a] = (float)(hp[a] / sc);
         // h_k holds what has been spread so far; dh is the next increment
         p.h0[3 * k + a] = h0[a];
-        p.hk[3 * k + a] = 0.0;
+        p.hk[3 * k + a] = spread ? 0.0 + h0[a] : 0.0;
         p.dh[3 * k + a] = h0[a];
     }
     cross3(rel, s, ts);
@@ -375,8 +431,10 @@ __device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyDev &B,
     }
 }
 
-// Tile sums of the per-marker parts, in marker order (deterministic).
-__device__ inline void tile_part_sum(const DevPtrs &p, int tix, int count, const double (*tp)[kPart])
+// Tile sums of the per-marker parts (the first kPart entries of each row of
+// tp, a row per marker), in marker order (deterministic).
+template <int W>
+__device__ inline void tile_part_sum(const DevPtrs &p, int tix, int count, const double (*tp)[W])
 {
     __syncthreads();
     if ((int)threadIdx.x < kPart) {
@@ -417,6 +475,16 @@ __device__ inline void spread_flush(const TileBox &tb, int ncell, int L, int L3,
     }
 }
 
+// Entry f of marker k's record: X (0..2), U (3..5), dS (6), h_k (7..9).
+__device__ inline double marker_record(const DevPtrs &p, int k, int f)
+{
+    if (f < 3) return p.X[3 * k + f];
+    if (f < 6) return p.U[3 * k + f - 3];
+    if (f == 6) return p.dS[k];
+    return p.hk[3 * k + f - 7];
+}
+static_assert(kTileMarkers * 10 <= 256, "a tile's marker records take one load per thread");
+
 // l = 0 and the stress integral over a tile (wave w takes markers w, w+4, ...).
 // With spread set, also the first forcing cycle's spread of the plain start
 // h0 into accumulator 0 (h_k = h0).
@@ -424,19 +492,22 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
 {
     __shared__ float box[kRegFields][kBoxCells];
     __shared__ unsigned long long acc[3][kBoxCells];
-    __shared__ double tp[kTileMarkers][kPart];
+    __shared__ double ep[kTileMarkers][kRegFields];   // interpolated fields, then the marker's parts
+    __shared__ double mrec[kTileMarkers][7];          // X (3), U (3), dS of the tile's markers
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
-    const CaseDev &cd = p.cases[mt.c];
-    const BodyDev &B = p.body[mt.c];
+    const CaseDev cd = p.cases[mt.c];
+    const BodyView B = body_view(p.body[mt.c]);
     if (B.err != 0) return;
     const int L = cd.L, L3 = L * L * L;
     const float *R = p.reg + cd.reg_off * kRegFields;
     long long *H0 = p.H + cd.reg_off * 3;
-    const TileBox tb = tile_box_block(p, mt, B, L);
-    if (threadIdx.x == 0) p.tbox[tix] = tb;
+    const TileBox tb = p.tbox[tix];
     const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
+    // the markers' records load in the same round as the box
+    const int rj = (int)threadIdx.x / 7, rf = (int)threadIdx.x - 7 * rj;
+    const double rv = rj < mt.count ? marker_record(p, mt.first + rj, rf) : 0.0;
     if (tb.fits) {
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
             const int q = box_region_cell(i, tb, L);
@@ -445,11 +516,12 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
             acc[0][i] = acc[1][i] = acc[2][i] = 0ull;
         }
     }
+    if (rj < mt.count) mrec[rj][rf] = rv;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
         const int k = mt.first + j;
-        const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
+        const double X[3] = {mrec[j][0], mrec[j][1], mrec[j][2]};
         double v[kRegFields];
         double W;
         int i = 0, q = -1;
@@ -467,23 +539,25 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
         // the butterfly leaves the same sum in every lane
 #pragma unroll
         for (int f = 0; f < kRegFields; f++) v[f] = wave_sum(v[f]);
-        if (lane == 0) force_epilogue(p, k, B, v, tp[j]);
-        if (spread) {
-            const double h0[3] = {p.U[3 * k] - v[1], p.U[3 * k + 1] - v[2], p.U[3 * k + 2] - v[3]};
-            if (lane == 0)
+        if (lane == 0)
 #pragma unroll
-                for (int a = 0; a < 3; a++) p.hk[3 * k + a] += h0[a];
-            spread_node(p, mt.c, tb, i, q, W * p.dS[k], h0, acc, H0, L3);
+            for (int f = 0; f < kRegFields; f++) ep[j][f] = v[f];
+        if (spread) {
+            const double h0[3] = {mrec[j][3] - v[1], mrec[j][4] - v[2], mrec[j][5] - v[3]};
+            spread_node(p, mt.c, tb, i, q, W * mrec[j][6], h0, acc, H0, L3);
         }
     }
-    tile_part_sum(p, tix, mt.count, tp);
+    // the tile's epilogues side by side, one thread per marker
+    __syncthreads();
+    if ((int)threadIdx.x < mt.count) force_epilogue(p, mt.first + threadIdx.x, B, ep[threadIdx.x], ep[threadIdx.x], spread);
+    tile_part_sum(p, tix, mt.count, ep);
     if (spread && tb.fits) spread_flush(tb, ncell, L, L3, acc, H0);
 }
 
 // Stress-integral parts of marker k on the parallel surface at distance
 // force_offset outside it (point Y = X_k + delta n_k, same normal, area dSo):
 // one wavefront, parts into o[kPart] by lane 0.
-__device__ inline void offset_part(const DevPtrs &p, int k, const CaseDev &cd, const BodyDev &B, const float *R,
+__device__ inline void offset_part(const DevPtrs &p, int k, const CaseDev &cd, const BodyView &B, const float *R,
                                    int L3, int lane, double *o)
 {
     const double nk[3] = {p.N[3 * k], p.N[3 * k + 1], p.N[3 * k + 2]};
@@ -530,8 +604,8 @@ __global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int n_mtiles)
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
-    const CaseDev &cd = p.cases[mt.c];
-    const BodyDev &B = p.body[mt.c];
+    const CaseDev cd = p.cases[mt.c];
+    const BodyView B = body_view(p.body[mt.c]);
     if (B.err != 0 || !(cd.force_offset > 0.0)) return;
     const int L3 = cd.L * cd.L * cd.L;
     const float *R = p.reg + cd.reg_off * kRegFields;
@@ -552,8 +626,8 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, i
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
-    const CaseDev &cd = p.cases[mt.c];
-    const BodyDev &B = p.body[mt.c];
+    const CaseDev cd = p.cases[mt.c];
+    const BodyView B = body_view(p.body[mt.c]);
     if (B.err != 0 || (masked && !B.active)) return;
     const int L = cd.L, L3 = L * L * L;
     long long *H = p.H + cd.reg_off * 3;
@@ -587,22 +661,23 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, i
 }
 
 // Interpolation of u* + H over a tile (staged in LDS, FP64; H the sum of
-// accumulators 0 .. nbuf-1), the residual U_k - I[u* + H](X_k), the next
+// accumulators 0 .. NB-1), the residual U_k - I[u* + H](X_k), the next
 // increment dh = that residual, and the tile's largest residual component.
 // With spread_to >= 0 the same pass spreads dh (the next cycle's spread,
 // h_k += dh) into accumulator spread_to, which no interpolation of this
 // pass reads.
-__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked, int nbuf,
-                                                             int spread_to)
+template <int NB>
+__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked, int spread_to)
 {
     __shared__ double box[3][kBoxCells];
     __shared__ unsigned long long acc[3][kBoxCells];
+    __shared__ double mrec[kTileMarkers][10];   // X (3), U (3), dS, h_k (3) of the tile's markers
     __shared__ double wmax[4];
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
-    const CaseDev &cd = p.cases[mt.c];
-    const BodyDev &B = p.body[mt.c];
+    const CaseDev cd = p.cases[mt.c];
+    const BodyView B = body_view(p.body[mt.c]);
     if (B.err != 0 || (masked && !B.active)) return;
     const int L = cd.L, L3 = L * L * L;
     const float *R = p.reg + cd.reg_off * kRegFields;
@@ -611,11 +686,16 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
     const TileBox tb = p.tbox[tix];
     const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
     // H at region cell q and component a: the exact integer sum of the accumulators
+    const long long hstride = p.hstride;
     auto h_at = [&](int a, int q) {
         long long h = H[a * L3 + q];
-        for (int b = 1; b < nbuf; b++) h += H[b * p.hstride + a * L3 + q];
+#pragma unroll
+        for (int b = 1; b < NB; b++) h += H[b * hstride + a * L3 + q];
         return h;
     };
+    // the markers' records load in the same round as the box
+    const int rj = (int)threadIdx.x / 10, rf = (int)threadIdx.x - 10 * rj;
+    const double rv = rj < mt.count ? marker_record(p, mt.first + rj, rf) : 0.0;
     if (tb.fits) {
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
             const int q = box_region_cell(i, tb, L);
@@ -626,12 +706,13 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
             }
         }
     }
+    if (rj < mt.count) mrec[rj][rf] = rv;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double res = 0.0;
     for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
         const int k = mt.first + j;
-        const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
+        const double X[3] = {mrec[j][0], mrec[j][1], mrec[j][2]};
         double v[3];
         double W;
         int i = 0, q = -1;
@@ -650,16 +731,16 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
         // the butterfly leaves the same sum in every lane
 #pragma unroll
         for (int a = 0; a < 3; a++) v[a] = wave_sum(v[a]);
-        const double e[3] = {p.U[3 * k] - v[0], p.U[3 * k + 1] - v[1], p.U[3 * k + 2] - v[2]};
+        const double e[3] = {mrec[j][3] - v[0], mrec[j][4] - v[1], mrec[j][5] - v[2]};
         if (lane == 0) {
 #pragma unroll
             for (int a = 0; a < 3; a++) {
                 res = fmax(res, fabs(e[a]));
                 p.dh[3 * k + a] = e[a];
-                if (spread_to >= 0) p.hk[3 * k + a] += e[a];
+                if (spread_to >= 0) p.hk[3 * k + a] = mrec[j][7 + a] + e[a];
             }
         }
-        if (spread_to >= 0) spread_node(p, mt.c, tb, i, q, W * p.dS[k], e, acc, Hs, L3);
+        if (spread_to >= 0) spread_node(p, mt.c, tb, i, q, W * mrec[j][6], e, acc, Hs, L3);
     }
     if (lane == 0) wmax[wave] = res;
     __syncthreads();
@@ -827,8 +908,8 @@ template <class CD>
 __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
 {
     const int c = blockIdx.y;
-    const CaseDev &cd = p.cases[c];
-    const BodyDev &B = p.body[c];
+    const CaseDev cd = p.cases[c];
+    const BodyView B = body_view(p.body[c]);
     if (cd.M == 0 || B.err != 0) return;
     const int L = cd.L, L3 = L * L * L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -839,7 +920,14 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
     const int a = q % L, b = (q / L) % L, cc = q / (L * L);
     const int gz = B.org[2] + cc;
     if (gz < 0 || gz >= cd.nz) return;
+    const int gx = wrapi(B.org[0] + a, cd.nx), gy = wrapi(B.org[1] + b, cd.ny);
+    int zc = gz + B.z0;
+    if (zc >= cd.nz) zc -= cd.nz;
+    const int off = (zc * cd.ny + gy) * cd.nx + gx;
+    typename CD::T *dst = cur + cd.pop_off;
+    // the accumulators, the fields and the populations in one round of loads
     const long long *H = p.H + cd.reg_off * 3;
+    const float *R = p.reg + cd.reg_off * kRegFields;
     long long h0 = 0, h1 = 0, h2 = 0;
 #pragma unroll
     for (int j = 0; j < kHBufs; j++) {
@@ -847,10 +935,14 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
         h1 += H[j * p.hstride + L3 + q];
         h2 += H[j * p.hstride + 2 * L3 + q];
     }
-    if ((h0 | h1 | h2) == 0) return;
-    const float *R = p.reg + cd.reg_off * kRegFields;
     const float rho = 1.0f + R[q];
     const float u[3] = {R[L3 + q], R[2 * L3 + q], R[3 * L3 + q]};
+    float g[Q];
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        g[i] = CD::template dec<i>(dst[(long long)i * cd.plane + off]);
+    });
+    if ((h0 | h1 | h2) == 0) return;
     const float tau = tau_at(cd.tau0, cd.nz, cd.sponge, gz);
     const float us[3] = {u[0] + tau * (float)((double)h0 * kFixInv), u[1] + tau * (float)((double)h1 * kFixInv),
                          u[2] + tau * (float)((double)h2 * kFixInv)};
@@ -865,15 +957,9 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
         A[9] -= k * (float)((double)h2 * kFixInv);
     }
     hermite_to_populations(A, d);
-    const int gx = wrapi(B.org[0] + a, cd.nx), gy = wrapi(B.org[1] + b, cd.ny);
-    int zc = gz + B.z0;
-    if (zc >= cd.nz) zc -= cd.nz;
-    const int off = (zc * cd.ny + gy) * cd.nx + gx;
-    typename CD::T *dst = cur + cd.pop_off;
     Unroll<0, Q>::run([&](auto I) {
         constexpr int i = decltype(I)::value;
-        typename CD::T &ref = dst[(long long)i * cd.plane + off];
-        ref = CD::template enc<i>(CD::template dec<i>(ref) + d[i]);
+        dst[(long long)i * cd.plane + off] = CD::template enc<i>(g[i] + d[i]);
     });
 }
 
@@ -933,10 +1019,11 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     const dim3 reg_grid((maxL3 + 255) / 256, n_cases);
     const dim3 tile_grid((n_mtiles + 7) / 8 * 8);
     const dim3 mark_grid((Mtot + 255) / 256);
-    hipLaunchKernelGGL(k_markers, dim3((Mtot + 3) / 4), blk, 0, s, p, Mtot);
+    hipLaunchKernelGGL(k_markers, tile_grid, dim3(64), 0, s, p, n_mtiles);
     hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
     // plain start with at most kHBufs cycles: each cycle's spread rides on
     // the pass before it (force + spread 1, update c + spread c + 1)
+    static_assert(kHBufs == 4, "the launch below instantiates 1..4 accumulators");
     const int fused = warm_mode == 0 && cycles <= kHBufs;
     hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p, n_mtiles, fused);
     if (force_surface) hipLaunchKernelGGL(k_offset_force, tile_grid, blk, 0, s, p, n_mtiles);
@@ -947,15 +1034,20 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     auto sequence = [&](int ncyc, int slot0, int masked) {
         for (int cyc = 1; cyc <= ncyc; cyc++) {
             hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, masked);
-            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, masked, 1, -1);
+            hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, masked, -1);
             if (diag || cyc == ncyc)
                 hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, slot0 + cyc - 1, masked, 0);
         }
     };
     if (fused) {
         for (int cyc = 1; cyc <= cycles; cyc++) {
-            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, 0, cyc,
-                               cyc < cycles ? cyc : -1);
+            const int to = cyc < cycles ? cyc : -1;
+            switch (cyc) {
+            case 1: hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, 0, to); break;
+            case 2: hipLaunchKernelGGL(k_interp_update_tiles<2>, tile_grid, blk, 0, s, p, n_mtiles, 0, to); break;
+            case 3: hipLaunchKernelGGL(k_interp_update_tiles<3>, tile_grid, blk, 0, s, p, n_mtiles, 0, to); break;
+            default: hipLaunchKernelGGL(k_interp_update_tiles<4>, tile_grid, blk, 0, s, p, n_mtiles, 0, to); break;
+            }
             if (diag || cyc == cycles)
                 hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, cyc - 1, 0, 0);
         }
@@ -975,7 +1067,7 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
         hipLaunchKernelGGL(k_gate_begin, case_grid, case_blk, 0, s, p, n_cases);
         for (int cyc = 1; cyc <= warm_cycles; cyc++) {
             hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, 1);
-            hipLaunchKernelGGL(k_interp_update_tiles, tile_grid, blk, 0, s, p, n_mtiles, 1, 1, -1);
+            hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, 1, -1);
             hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, cyc - 1, 1, cyc);
         }
         hipLaunchKernelGGL(k_gate, case_grid, case_blk, 0, s, p, n_cases);
