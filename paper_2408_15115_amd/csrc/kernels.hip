@@ -217,11 +217,36 @@ __device__ inline Node stencil_node(const double X[3], int lane, const CaseDev &
     return nd;
 }
 
+// v + the value of the lane that the DPP pattern CTRL pairs with this one
+// (both 32-bit halves moved by DPP; no LDS traffic).
+template <int CTRL>
+__device__ inline double dpp_pair_add(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double lane_value(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront (all active), the same bits in every
+// lane: inside each row of 16 lanes, pairs (lane ^ 1), quads (lane ^ 2),
+// half rows (mirror of 8) and rows (mirror of 16); each step adds the same
+// two operands in both lanes of a pair, so a row ends uniform; then the
+// four row totals in a fixed order.
 __device__ inline double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v = dpp_pair_add<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v = dpp_pair_add<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v = dpp_pair_add<0x141>(v);   // row_half_mirror
+    v = dpp_pair_add<0x140>(v);   // row_mirror
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // ------------------------------------------------------------ marker tiles
