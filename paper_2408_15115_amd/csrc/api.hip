@@ -36,7 +36,7 @@ struct Plan {
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
         off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox,
-        off_mark, aux_bytes;
+        off_mark, off_wt, aux_bytes;
     int block = 256;
 };
 
@@ -259,6 +259,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_h0 = take(sizeof(double) * 3 * M);
     P.off_hs = take(sizeof(double) * M);
     P.off_dSo = take(sizeof(double) * M);
+    P.off_wt = take(sizeof(double) * 12 * M);
     P.off_mtiles = take(sizeof(MarkerTile) * NT);
     P.off_tbox = take(sizeof(TileBox) * NT);
     P.aux_bytes = o;
@@ -397,6 +398,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.H = (long long *)(a + P.off_H);
     p.hstride = 3 * std::max<long long>(P.reg_cells, 1);
     p.mark = (unsigned char *)(a + P.off_mark);
+    p.wt = (double *)(a + P.off_wt);
     p.mtiles = (MarkerTile *)(a + P.off_mtiles);
     p.feat = (float *)(a + P.off_feat);
     p.h0 = (double *)(a + P.off_h0);

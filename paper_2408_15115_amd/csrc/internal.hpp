@@ -69,10 +69,10 @@ constexpr double kTileSpan = 3.0;
 // LDS box capacity: a tile spans at most kTileSpan per axis in the body frame,
 // so its box is at most 7^3 cells axis-aligned and stays at or below 448
 // cells in the rotations measured (random orientations of the 12k-marker
-// ellipsoid); larger boxes take the per-node HBM path.  464 keeps the force
+// ellipsoid); larger boxes take the per-node HBM path.  448 keeps the force
 // kernel (10 FP32 fields + 3 int64 accumulators per cell, plus the markers'
 // records) under 32 KB of LDS, five workgroups per CU.
-constexpr int kBoxCells = 464;
+constexpr int kBoxCells = 448;
 
 // Fixed-point scale of the deterministic immersed-force accumulator.
 constexpr double kFixScale = 1099511627776.0;   // 2^40
@@ -97,6 +97,7 @@ struct DevPtrs {
     double *X, *N, *U, *hk, *dh;
     double *part;    // per-tile force, torque and pressure-force sums (kPart each)
     double *res;     // per-tile max residual of the last interpolation
+    double *wt;      // per-marker one-dimensional stencil weights, w[4 d + o] for node floor(X_d) - 1 + o
     unsigned char *mark;   // per region cell: 1 if inside a tile's stencil box this step
     float *reg;
     long long *H;    // kHBufs fixed-point immersed-force accumulators, hstride elements apart

@@ -281,6 +281,22 @@ __device__ inline int box_node(const double X[3], int lane, const TileBox &b, do
     return r[0] + b.e[0] * (r[1] + b.e[1] * r[2]);
 }
 
+// The same from the marker's one-dimensional weights w[4 d + o] (k_markers
+// evaluates them once per step; the product is formed in the same order).
+__device__ inline int box_node_w(const double X[3], const double *w, int lane, const TileBox &b, double &W)
+{
+    const int off[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+    int r[3];
+    W = 1.0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int node = (int)floor(X[d]) - 1 + off[d];
+        W *= w[4 * d + off[d]];
+        r[d] = node - b.lo[d];
+    }
+    return r[0] + b.e[0] * (r[1] + b.e[1] * r[2]);
+}
+
 // Region cell index of box cell i.
 __device__ inline int box_region_cell(int i, const TileBox &b, int L)
 {
@@ -389,6 +405,13 @@ __global__ void __launch_bounds__(64) k_markers(DevPtrs p, int n_mtiles)
             p.X[3 * k + a] = X[a];
             p.N[3 * k + a] = N[a];
             p.U[3 * k + a] = vb[a] + wr[a];
+        }
+        // the marker's one-dimensional stencil weights for this step
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const int n0 = (int)floor(X[d]) - 1;
+#pragma unroll
+            for (int o = 0; o < 4; o++) p.wt[12 * k + 4 * d + o] = phi4((double)(n0 + o) - X[d]);
         }
         const int fz = (int)floor(X[2]);
         if (fz - 1 < 0 || fz + 2 > cd.nz - 1) atomicOr(&p.body[mt.c].err, 1);
@@ -500,15 +523,42 @@ __device__ inline void spread_flush(const TileBox &tb, int ncell, int L, int L3,
     }
 }
 
-// Entry f of marker k's record: X (0..2), U (3..5), dS (6), h_k (7..9).
+// Entry f of marker k's record: X (0..2), U (3..5), dS (6), the stencil
+// weights (7..18), h_k (19..21).  The force kernel keeps entries 0..18.
+constexpr int kRecW = 7, kRecH = 19, kRecForce = 19, kRecUpdate = 22;
 __device__ inline double marker_record(const DevPtrs &p, int k, int f)
 {
     if (f < 3) return p.X[3 * k + f];
     if (f < 6) return p.U[3 * k + f - 3];
     if (f == 6) return p.dS[k];
-    return p.hk[3 * k + f - 7];
+    if (f < kRecH) return p.wt[12 * k + f - kRecW];
+    return p.hk[3 * k + f - kRecH];
 }
-static_assert(kTileMarkers * 10 <= 256, "a tile's marker records take one load per thread");
+
+// A tile's marker records into LDS (row j = marker first + j), in two loads
+// per thread issued together; the caller stores them after its other loads
+// and before its barrier.
+template <int NREC>
+struct RecordLoad {
+    static_assert(kTileMarkers * NREC <= 512, "two loads per thread of a 256-thread workgroup");
+    double v[2];
+    __device__ inline void load(const DevPtrs &p, const MarkerTile &mt)
+    {
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int t = (int)threadIdx.x + 256 * u;
+            v[u] = t < mt.count * NREC ? marker_record(p, mt.first + t / NREC, t % NREC) : 0.0;
+        }
+    }
+    __device__ inline void store(const MarkerTile &mt, double (*rec)[NREC]) const
+    {
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int t = (int)threadIdx.x + 256 * u;
+            if (t < mt.count * NREC) rec[t / NREC][t % NREC] = v[u];
+        }
+    }
+};
 
 // l = 0 and the stress integral over a tile (wave w takes markers w, w+4, ...).
 // With spread set, also the first forcing cycle's spread of the plain start
@@ -518,7 +568,7 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
     __shared__ float box[kRegFields][kBoxCells];
     __shared__ unsigned long long acc[3][kBoxCells];
     __shared__ double ep[kTileMarkers][kRegFields];   // interpolated fields, then the marker's parts
-    __shared__ double mrec[kTileMarkers][7];          // X (3), U (3), dS of the tile's markers
+    __shared__ double mrec[kTileMarkers][kRecForce];  // the tile's marker records
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
@@ -531,8 +581,8 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
     const TileBox tb = p.tbox[tix];
     const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
     // the markers' records load in the same round as the box
-    const int rj = (int)threadIdx.x / 7, rf = (int)threadIdx.x - 7 * rj;
-    const double rv = rj < mt.count ? marker_record(p, mt.first + rj, rf) : 0.0;
+    RecordLoad<kRecForce> rl;
+    rl.load(p, mt);
     if (tb.fits) {
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
             const int q = box_region_cell(i, tb, L);
@@ -541,7 +591,7 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
             acc[0][i] = acc[1][i] = acc[2][i] = 0ull;
         }
     }
-    if (rj < mt.count) mrec[rj][rf] = rv;
+    rl.store(mt, mrec);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
@@ -551,7 +601,7 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
         double W;
         int i = 0, q = -1;
         if (tb.fits) {
-            i = box_node(X, lane, tb, W);
+            i = box_node_w(X, mrec[j] + kRecW, lane, tb, W);
 #pragma unroll
             for (int f = 0; f < kRegFields; f++) v[f] = W * (double)box[f][i];
         } else {
@@ -696,7 +746,7 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
 {
     __shared__ double box[3][kBoxCells];
     __shared__ unsigned long long acc[3][kBoxCells];
-    __shared__ double mrec[kTileMarkers][10];   // X (3), U (3), dS, h_k (3) of the tile's markers
+    __shared__ double mrec[kTileMarkers][kRecUpdate];   // the tile's marker records
     __shared__ double wmax[4];
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
@@ -719,8 +769,8 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
         return h;
     };
     // the markers' records load in the same round as the box
-    const int rj = (int)threadIdx.x / 10, rf = (int)threadIdx.x - 10 * rj;
-    const double rv = rj < mt.count ? marker_record(p, mt.first + rj, rf) : 0.0;
+    RecordLoad<kRecUpdate> rl;
+    rl.load(p, mt);
     if (tb.fits) {
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
             const int q = box_region_cell(i, tb, L);
@@ -731,7 +781,7 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
             }
         }
     }
-    if (rj < mt.count) mrec[rj][rf] = rv;
+    rl.store(mt, mrec);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double res = 0.0;
@@ -742,7 +792,7 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
         double W;
         int i = 0, q = -1;
         if (tb.fits) {
-            i = box_node(X, lane, tb, W);
+            i = box_node_w(X, mrec[j] + kRecW, lane, tb, W);
 #pragma unroll
             for (int a = 0; a < 3; a++) v[a] = W * box[a][i];
         } else {
@@ -762,7 +812,7 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
             for (int a = 0; a < 3; a++) {
                 res = fmax(res, fabs(e[a]));
                 p.dh[3 * k + a] = e[a];
-                if (spread_to >= 0) p.hk[3 * k + a] = mrec[j][7 + a] + e[a];
+                if (spread_to >= 0) p.hk[3 * k + a] = mrec[j][kRecH + a] + e[a];
             }
         }
         if (spread_to >= 0) spread_node(p, mt.c, tb, i, q, W * mrec[j][6], e, acc, Hs, L3);
