@@ -235,17 +235,24 @@ __device__ inline double lane_value(double v, int l)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum over the 64 lanes of a wavefront (all active), the same bits in every
-// lane: inside each row of 16 lanes, pairs (lane ^ 1), quads (lane ^ 2),
-// half rows (mirror of 8) and rows (mirror of 16); each step adds the same
-// two operands in both lanes of a pair, so a row ends uniform; then the
-// four row totals in a fixed order.
-__device__ inline double wave_sum(double v)
+// Sum over a row of 16 lanes (all active), the same bits in every lane of
+// the row: pairs (lane ^ 1), quads (lane ^ 2), half rows (mirror of 8) and
+// rows (mirror of 16); each step adds the same two operands in both lanes of
+// a pair, so the row ends uniform.
+__device__ inline double row_sum(double v)
 {
     v = dpp_pair_add<0xB1>(v);    // quad_perm [1, 0, 3, 2]
     v = dpp_pair_add<0x4E>(v);    // quad_perm [2, 3, 0, 1]
     v = dpp_pair_add<0x141>(v);   // row_half_mirror
     v = dpp_pair_add<0x140>(v);   // row_mirror
+    return v;
+}
+
+// Sum over the 64 lanes of a wavefront (all active), the same bits in every
+// lane: row sums, then the four row totals in a fixed order.
+__device__ inline double wave_sum(double v)
+{
+    v = row_sum(v);
     return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
@@ -295,6 +302,46 @@ __device__ inline int box_node_w(const double X[3], const double *w, int lane, c
         r[d] = node - b.lo[d];
     }
     return r[0] + b.e[0] * (r[1] + b.e[1] * r[2]);
+}
+
+// Lane layout of the interpolation passes: thread t takes marker t / 16 of
+// the tile and the stencil column (t & 3, (t >> 2) & 3); its nodes are the
+// four z levels of that column.  A row of 16 lanes is one marker, so the
+// stencil sums are row sums and the tile's markers run side by side.
+static_assert(kTileMarkers * 16 == 256, "one workgroup row of 16 lanes per tile marker");
+struct Column {
+    int i[4];       // box cells of the four nodes (box path)
+    int q[4];       // region cells of the four nodes (per-node path; -1 outside)
+    double W[4];    // node weights
+};
+
+// The column's nodes from the marker's one-dimensional weights w (box path;
+// W = (w_x w_y) w_z, the product order of box_node) or from stencil_node.
+__device__ inline Column column_nodes(const double X[3], const double *w, int col, const TileBox &tb,
+                                      const CaseDev &cd, const BodyView &B)
+{
+    Column cn;
+    const int cx = col & 3, cy = col >> 2;
+    if (tb.fits) {
+        const double wxy = (1.0 * w[cx]) * w[4 + cy];
+        const int b0 = ((int)floor(X[0]) - 1 + cx - tb.lo[0]) +
+                       tb.e[0] * (((int)floor(X[1]) - 1 + cy - tb.lo[1]) + tb.e[1] * ((int)floor(X[2]) - 1 - tb.lo[2]));
+#pragma unroll
+        for (int z = 0; z < 4; z++) {
+            cn.W[z] = wxy * w[8 + z];
+            cn.i[z] = b0 + z * tb.e[0] * tb.e[1];
+            cn.q[z] = -1;
+        }
+    } else {
+#pragma unroll
+        for (int z = 0; z < 4; z++) {
+            const Node nd = stencil_node(X, col + 16 * z, cd, B);
+            cn.W[z] = nd.W;
+            cn.q[z] = nd.q;
+            cn.i[z] = 0;
+        }
+    }
+    return cn;
 }
 
 // Region cell index of box cell i.
@@ -560,7 +607,31 @@ struct RecordLoad {
     }
 };
 
-// l = 0 and the stress integral over a tile (wave w takes markers w, w+4, ...).
+// Spread of the tile's per-marker increments d[j] (LDS rows) after a
+// barrier: wavefront w takes markers w, w+4, ...; lane l is stencil node l,
+// so the 64 LDS atomics of one instruction go to 64 different cells.
+__device__ inline void spread_tile(const DevPtrs &p, const MarkerTile &mt, const TileBox &tb, const CaseDev &cd,
+                                   const BodyView &B, const double *rbase, int nrec, const double (*d)[3],
+                                   unsigned long long (*acc)[kBoxCells], long long *Hc, int L3)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
+        const double *rc = rbase + j * nrec;
+        const double X[3] = {rc[0], rc[1], rc[2]};
+        double W;
+        int i = 0, q = -1;
+        if (tb.fits) {
+            i = box_node_w(X, rc + kRecW, lane, tb, W);
+        } else {
+            const Node nd = stencil_node(X, lane, cd, B);
+            W = nd.W;
+            q = nd.q;
+        }
+        spread_node(p, mt.c, tb, i, q, W * rc[6], d[j], acc, Hc, L3);
+    }
+}
+
+// l = 0 and the stress integral over a tile (a row of 16 lanes per marker).
 // With spread set, also the first forcing cycle's spread of the plain start
 // h0 into accumulator 0 (h_k = h0).
 __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mtiles, int spread)
@@ -569,6 +640,7 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
     __shared__ unsigned long long acc[3][kBoxCells];
     __shared__ double ep[kTileMarkers][kRegFields];   // interpolated fields, then the marker's parts
     __shared__ double mrec[kTileMarkers][kRecForce];  // the tile's marker records
+    __shared__ double dinc[kTileMarkers][3];          // the markers' increments (h0) to spread
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
@@ -593,37 +665,36 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
     }
     rl.store(mt, mrec);
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
-        const int k = mt.first + j;
-        const double X[3] = {mrec[j][0], mrec[j][1], mrec[j][2]};
-        double v[kRegFields];
-        double W;
-        int i = 0, q = -1;
+    // rows past the tile's markers repeat marker 0 and store nothing
+    const int j = threadIdx.x >> 4, col = threadIdx.x & 15;
+    const bool on = j < mt.count;
+    const double *rc = mrec[on ? j : 0];
+    const double X[3] = {rc[0], rc[1], rc[2]};
+    const Column cn = column_nodes(X, rc + kRecW, col, tb, cd, B);
+    double v[kRegFields];
+#pragma unroll
+    for (int f = 0; f < kRegFields; f++) v[f] = 0.0;
+#pragma unroll
+    for (int z = 0; z < 4; z++) {
         if (tb.fits) {
-            i = box_node_w(X, mrec[j] + kRecW, lane, tb, W);
 #pragma unroll
-            for (int f = 0; f < kRegFields; f++) v[f] = W * (double)box[f][i];
-        } else {
-            const Node nd = stencil_node(X, lane, cd, B);
-            W = nd.W;
-            q = nd.q;
+            for (int f = 0; f < kRegFields; f++) v[f] += cn.W[z] * (double)box[f][cn.i[z]];
+        } else if (cn.q[z] >= 0) {
 #pragma unroll
-            for (int f = 0; f < kRegFields; f++) v[f] = q >= 0 ? W * (double)R[f * L3 + q] : 0.0;
-        }
-        // the butterfly leaves the same sum in every lane
-#pragma unroll
-        for (int f = 0; f < kRegFields; f++) v[f] = wave_sum(v[f]);
-        if (lane == 0)
-#pragma unroll
-            for (int f = 0; f < kRegFields; f++) ep[j][f] = v[f];
-        if (spread) {
-            const double h0[3] = {mrec[j][3] - v[1], mrec[j][4] - v[2], mrec[j][5] - v[3]};
-            spread_node(p, mt.c, tb, i, q, W * mrec[j][6], h0, acc, H0, L3);
+            for (int f = 0; f < kRegFields; f++) v[f] += cn.W[z] * (double)R[f * L3 + cn.q[z]];
         }
     }
-    // the tile's epilogues side by side, one thread per marker
+#pragma unroll
+    for (int f = 0; f < kRegFields; f++) v[f] = row_sum(v[f]);
+    if (on && col == 0) {
+#pragma unroll
+        for (int f = 0; f < kRegFields; f++) ep[j][f] = v[f];
+#pragma unroll
+        for (int a = 0; a < 3; a++) dinc[j][a] = rc[3 + a] - v[1 + a];
+    }
     __syncthreads();
+    if (spread) spread_tile(p, mt, tb, cd, B, &mrec[0][0], kRecForce, dinc, acc, H0, L3);
+    // the tile's epilogues side by side, one thread per marker
     if ((int)threadIdx.x < mt.count) force_epilogue(p, mt.first + threadIdx.x, B, ep[threadIdx.x], ep[threadIdx.x], spread);
     tile_part_sum(p, tix, mt.count, ep);
     if (spread && tb.fits) spread_flush(tb, ncell, L, L3, acc, H0);
@@ -747,7 +818,8 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
     __shared__ double box[3][kBoxCells];
     __shared__ unsigned long long acc[3][kBoxCells];
     __shared__ double mrec[kTileMarkers][kRecUpdate];   // the tile's marker records
-    __shared__ double wmax[4];
+    __shared__ double dinc[kTileMarkers][3];            // the markers' increments e to spread
+    __shared__ double rmax[kTileMarkers];
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
@@ -783,43 +855,48 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
     }
     rl.store(mt, mrec);
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double res = 0.0;
-    for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
-        const int k = mt.first + j;
-        const double X[3] = {mrec[j][0], mrec[j][1], mrec[j][2]};
-        double v[3];
-        double W;
-        int i = 0, q = -1;
-        if (tb.fits) {
-            i = box_node_w(X, mrec[j] + kRecW, lane, tb, W);
+    // rows past the tile's markers repeat marker 0 and store nothing
+    const int j = threadIdx.x >> 4, col = threadIdx.x & 15;
+    const bool on = j < mt.count;
+    const double *rc = mrec[on ? j : 0];
+    const double X[3] = {rc[0], rc[1], rc[2]};
+    const Column cn = column_nodes(X, rc + kRecW, col, tb, cd, B);
+    double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-            for (int a = 0; a < 3; a++) v[a] = W * box[a][i];
-        } else {
-            const Node nd = stencil_node(X, lane, cd, B);
-            W = nd.W;
-            q = nd.q;
+    for (int z = 0; z < 4; z++) {
+        if (tb.fits) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) v[a] += cn.W[z] * box[a][cn.i[z]];
+        } else if (cn.q[z] >= 0) {
+            const int q = cn.q[z];
 #pragma unroll
             for (int a = 0; a < 3; a++)
-                v[a] = q >= 0 ? W * ((double)R[(1 + a) * L3 + q] + (double)h_at(a, q) * kFixInv) : 0.0;
+                v[a] += cn.W[z] * ((double)R[(1 + a) * L3 + q] + (double)h_at(a, q) * kFixInv);
         }
-        // the butterfly leaves the same sum in every lane
-#pragma unroll
-        for (int a = 0; a < 3; a++) v[a] = wave_sum(v[a]);
-        const double e[3] = {mrec[j][3] - v[0], mrec[j][4] - v[1], mrec[j][5] - v[2]};
-        if (lane == 0) {
-#pragma unroll
-            for (int a = 0; a < 3; a++) {
-                res = fmax(res, fabs(e[a]));
-                p.dh[3 * k + a] = e[a];
-                if (spread_to >= 0) p.hk[3 * k + a] = mrec[j][kRecH + a] + e[a];
-            }
-        }
-        if (spread_to >= 0) spread_node(p, mt.c, tb, i, q, W * mrec[j][6], e, acc, Hs, L3);
     }
-    if (lane == 0) wmax[wave] = res;
+#pragma unroll
+    for (int a = 0; a < 3; a++) v[a] = row_sum(v[a]);
+    const double e[3] = {rc[3] - v[0], rc[4] - v[1], rc[5] - v[2]};
+    if (on && col == 0) {
+        const int k = mt.first + j;
+        double res = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            res = fmax(res, fabs(e[a]));
+            p.dh[3 * k + a] = e[a];
+            if (spread_to >= 0) p.hk[3 * k + a] = rc[kRecH + a] + e[a];
+            dinc[j][a] = e[a];
+        }
+        rmax[j] = res;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) p.res[tix] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    if (spread_to >= 0) spread_tile(p, mt, tb, cd, B, &mrec[0][0], kRecUpdate, dinc, acc, Hs, L3);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int t = 0; t < mt.count; t++) m = fmax(m, rmax[t]);
+        p.res[tix] = m;
+    }
     if (spread_to >= 0 && tb.fits) spread_flush(tb, ncell, L, L3, acc, Hs);
 }
 
