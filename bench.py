@@ -122,14 +122,14 @@ def copy_bandwidth(T, torch, nbytes=4 << 30, reps=10):
 
 def batch_run(T, W, torch, steps, storage):
     """The batched form: 64 independent cases (64^3 .. 192x192x384; spheres,
-    spheroids, perturbed spheres) in one context; schedule from the autotuner."""
+    spheroids, perturbed spheres) in one context; schedule tuned on whole coupled steps."""
     from paper_2408_15115_amd import autotune
     batch = W.batch_cases(64)
     cases = [c for c, _ in batch]
     bodies = [b for _, b in batch]
-    tuned = autotune.tune(cases, storage=storage)
-    log(f"batch: schedule {tuned['best']} ({'cached' if tuned['cached'] else 'tuned'}, "
-        f"{tuned['ms']:.3f} ms per lattice launch)")
+    tuned = autotune.tune_step(cases, bodies, storage=storage)
+    log(f"batch: schedule {tuned['best']} ({'cached' if tuned['cached'] else 'tuned'} on whole steps, "
+        f"{tuned['ms']:.3f} ms per step, lattice kernel alone {tuned['lattice_ms']:.3f} ms)")
     S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), **tuned["best"])
     total_ms, k1_ms = timed_steps(S, torch, steps, 3)
     errs = [S.body_state(c, check=False)["err"] for c in range(len(cases))]
@@ -387,7 +387,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--variant-steps", type=int, default=400)
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -84,11 +84,73 @@ def tune(cases, storage="f32", candidates=None, launches=8, warmup=2, use_cache=
     res = {"best": best["options"], "ms": best["ms"], "table": table, "key": key, "arch": arch,
            "storage": storage, "cached": False}
     if use_cache:
-        db = _load(path)
-        db[key] = {k: v for k, v in res.items() if k != "cached"}
-        os.makedirs(os.path.dirname(path), exist_ok=True)
-        tmp = path + ".tmp"
-        with open(tmp, "w") as f:
-            json.dump(db, f, indent=1)
-        os.replace(tmp, path)
+        _store(path, key, res)
+    return res
+
+
+def _store(path, key, res):
+    db = _load(path)
+    db[key] = {k: v for k, v in res.items() if k != "cached"}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1)
+    os.replace(tmp, path)
+
+
+def tune_step(cases, bodies, storage="f32", top=3, steps=12, warmup=3, use_cache=True, path=None, candidates=None):
+    """Schedule for the whole coupled step rather than the lattice kernel
+    alone: the coupling can run on the library's second stream beside the
+    lattice kernel, and a schedule that leaves room on the CUs can hide it
+    (how much it hides also depends on the runtime giving the two streams
+    different hardware queues).  Times full steps (body advance, lattice
+    kernel, coupling, window) for the `top` fastest lattice-kernel schedules
+    of tune() and the fastest persistent one with the coupling beside, and
+    the fastest schedule with the coupling after the lattice kernel
+    (serial_ibm), and keeps the fastest step.  Returns {"best" (schedule and
+    serial_ibm), "ms" (per step), "lattice_ms" (the lattice kernel alone
+    under that schedule), "table", "key", "cached"}."""
+    import torch
+
+    from . import turret as T
+
+    path = path or cache_path()
+    lat = tune(cases, storage=storage, candidates=candidates, use_cache=use_cache, path=path)
+    key = lat["key"] + "-step-" + hashlib.sha1(
+        json.dumps([int(b["x_body"].shape[0]) if b is not None else 0 for b in bodies]).encode()).hexdigest()[:8]
+    db = _load(path) if use_cache else {}
+    if key in db:
+        hit = dict(db[key])
+        hit["cached"] = True
+        return hit
+    ranked = sorted(lat["table"], key=lambda r: r["ms"])
+    picks = [r["options"] for r in ranked[:top]]
+    persistent = [r["options"] for r in ranked if r["options"]["schedule"] >= 2]
+    if persistent and persistent[0] not in picks:
+        picks.append(persistent[0])
+    lat_ms = {json.dumps(r["options"], sort_keys=True): r["ms"] for r in ranked}
+    # each schedule with the coupling beside the lattice kernel, and the
+    # fastest lattice schedule with the coupling after it on one stream
+    picks = [dict(c, serial_ibm=0) for c in picks] + [dict(picks[0], serial_ibm=1)]
+    table = []
+    for cand in picks:
+        stream = torch.cuda.Stream()
+        S = T.Solver(cases, bodies, storage=storage, stream=stream, **cand)
+        S.run(warmup)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        S.run(steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        sched = {k: v for k, v in cand.items() if k != "serial_ibm"}
+        table.append({"options": cand, "ms": a.elapsed_time(b) / steps,
+                      "lattice_ms": lat_ms[json.dumps(sched, sort_keys=True)]})
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+    best = min(table, key=lambda r: r["ms"])
+    res = {"best": best["options"], "ms": best["ms"], "lattice_ms": best["lattice_ms"], "table": table,
+           "key": key, "storage": storage, "cached": False}
+    if use_cache:
+        _store(path, key, res)
     return res

@@ -136,3 +136,20 @@ def test_autotuner_returns_and_caches(T, tmp_path):
     assert not r1["cached"] and r1["best"] in cands and len(r1["table"]) == 2
     r2 = autotune.tune(cases, candidates=cands, path=path)
     assert r2["cached"] and r2["best"] == r1["best"]
+
+
+def test_step_tuner_times_whole_steps_and_caches(T, tmp_path):
+    """The whole-step selection times coupled steps (lattice kernel, coupling
+    beside it, window) for the leading lattice schedules and caches its pick."""
+    from paper_2408_15115_amd import autotune
+    cases, bodies = small_batch()
+    path = os.path.join(tmp_path, "tune.json")
+    cands = [dict(block=256, schedule=0, persist_wgs=0, tile_order=0),
+             dict(block=256, schedule=3, persist_wgs=64, tile_order=2)]
+    r1 = autotune.tune_step(cases, bodies, candidates=cands, path=path, steps=3, warmup=1)
+    sched = {k: v for k, v in r1["best"].items() if k != "serial_ibm"}
+    assert not r1["cached"] and sched in cands and r1["best"]["serial_ibm"] in (0, 1)
+    assert len(r1["table"]) == 3   # both schedules beside, the faster one serial
+    assert r1["ms"] > 0 and r1["lattice_ms"] > 0
+    r2 = autotune.tune_step(cases, bodies, candidates=cands, path=path, steps=3, warmup=1)
+    assert r2["cached"] and r2["best"] == r1["best"]
