@@ -273,23 +273,9 @@ __device__ inline int tile_of_block(int b, int n)
     return (b & 7) * per + (b >> 3);
 }
 
-// Box-local index of a lane's stencil node, and its weight.
-__device__ inline int box_node(const double X[3], int lane, const TileBox &b, double &W)
-{
-    const int off[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
-    int r[3];
-    W = 1.0;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        const int node = (int)floor(X[d]) - 1 + off[d];
-        W *= phi4((double)node - X[d]);
-        r[d] = node - b.lo[d];
-    }
-    return r[0] + b.e[0] * (r[1] + b.e[1] * r[2]);
-}
-
-// The same from the marker's one-dimensional weights w[4 d + o] (k_markers
-// evaluates them once per step; the product is formed in the same order).
+// Box-local index of a lane's stencil node and its weight W = (w_x w_y) w_z
+// from the marker's one-dimensional weights w[4 d + o] (k_markers evaluates
+// them once per step).
 __device__ inline int box_node_w(const double X[3], const double *w, int lane, const TileBox &b, double &W)
 {
     const int off[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
@@ -316,7 +302,7 @@ struct Column {
 };
 
 // The column's nodes from the marker's one-dimensional weights w (box path;
-// W = (w_x w_y) w_z, the product order of box_node) or from stencil_node.
+// W = (w_x w_y) w_z, the product order of box_node_w) or from stencil_node.
 __device__ inline Column column_nodes(const double X[3], const double *w, int col, const TileBox &tb,
                                       const CaseDev &cd, const BodyView &B)
 {
@@ -769,6 +755,8 @@ __global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int n_mtiles)
 __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, int masked)
 {
     __shared__ unsigned long long acc[3][kBoxCells];
+    __shared__ double mrec[kTileMarkers][kRecForce];   // the tile's marker records
+    __shared__ double dinc[kTileMarkers][3];           // the increments dh to spread
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
@@ -779,29 +767,28 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, i
     long long *H = p.H + cd.reg_off * 3;
     const TileBox tb = p.tbox[tix];
     const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
+    RecordLoad<kRecForce> rl;
+    rl.load(p, mt);
+    // thread j < count: marker j's increment, and h_k += dh
+    const int t = threadIdx.x;
+    double dh[3] = {0.0, 0.0, 0.0}, hk[3] = {0.0, 0.0, 0.0};
+    if (t < mt.count)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            dh[a] = p.dh[3 * (mt.first + t) + a];
+            hk[a] = p.hk[3 * (mt.first + t) + a];
+        }
     if (tb.fits)
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[0][i] = acc[1][i] = acc[2][i] = 0ull;
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
-        const int k = mt.first + j;
-        const double X[3] = {p.X[3 * k], p.X[3 * k + 1], p.X[3 * k + 2]};
-        double W;
-        int i = 0;
-        int q = -1;
-        if (tb.fits) {
-            i = box_node(X, lane, tb, W);
-        } else {
-            const Node nd = stencil_node(X, lane, cd, B);
-            W = nd.W;
-            q = nd.q;
-        }
-        const double dh[3] = {p.dh[3 * k], p.dh[3 * k + 1], p.dh[3 * k + 2]};
-        if (lane == 0)
+    rl.store(mt, mrec);
+    if (t < mt.count)
 #pragma unroll
-            for (int a = 0; a < 3; a++) p.hk[3 * k + a] += dh[a];
-        spread_node(p, mt.c, tb, i, q, W * p.dS[k], dh, acc, H, L3);
-    }
+        for (int a = 0; a < 3; a++) {
+            dinc[t][a] = dh[a];
+            p.hk[3 * (mt.first + t) + a] = hk[a] + dh[a];
+        }
+    __syncthreads();
+    spread_tile(p, mt, tb, cd, B, &mrec[0][0], kRecForce, dinc, acc, H, L3);
     __syncthreads();
     if (tb.fits) spread_flush(tb, ncell, L, L3, acc, H);
 }
