@@ -272,24 +272,29 @@ def _freq_for_area(area, target_dS=0.5):
     return max(4, int(round(math.sqrt(area / target_dS / 10.0))))
 
 
-def case_sphere_settling(D=16.0, re=5.0, kappa=2.7, force_offset=0.0, w_d=10, h_d=30, domain="free-slip"):
+def case_sphere_settling(D=16.0, re=5.0, kappa=2.7, force_offset=0.0, w_d=10, h_d=30, domain="free-slip",
+                         v_t=None, h_ini_d=None, h_end_d=None, sponge_d=None):
     """A sphere of diameter D (lattice units) settling from rest in a
     w = w_d D by w_d D by h = h_d D box (the paper's w* = 10, h* = 30 domain of
     its low-Re sphere cases): periodic x/y, free-slip top and bottom (or, with
     domain="paper", the Sec. 3 layout: no-slip bottom, constant-pressure top),
-    sponge 0.08 h, window re-injection from 0.75 h by 4 D.  Gravity from the
+    sponge 0.08 h, window re-injection from 0.75 h by 4 D (or from h_ini_d D
+    down to h_end_d D, sponge sponge_d D, as in Table 2).  Gravity from the
     Clift-Gauvin drag so that the unbounded terminal velocity is v_T (0.02,
-    lowered to keep tau <= 1).  Markers at the vertices of a geodesic mesh
-    with mean area about 0.5.  Returns (case, body, v_T)."""
+    lowered to keep tau <= 1, unless given).  Markers at the vertices of a
+    geodesic mesh with mean area about 0.5.  Returns (case, body, v_T)."""
     R = D / 2.0
     w, h = int(round(w_d * D)), int(round(h_d * D))
     V, F = geodesic_sphere(_freq_for_area(4 * math.pi * R * R))
-    v_t = min(V_TERMINAL_LU, re * TAU_MAX_BATCH_NU / D)
+    if v_t is None:
+        v_t = min(V_TERMINAL_LU, re * TAU_MAX_BATCH_NU / D)
     nu, tau, g = lattice_scaling(D, re, kappa, v_t)
-    z0 = 0.75 * h
+    z0 = 0.75 * h if h_ini_d is None else h_ini_d * D
+    z1 = z0 - 4 * D if h_end_d is None else h_end_d * D
+    sponge = int(round(0.08 * h)) if sponge_d is None else int(round(sponge_d * D))
     body = mesh_body(V * R, F, kappa, [(w - 1) / 2.0, (w - 1) / 2.0, z0], force_offset=force_offset)
     lo, hi = (BC_NOSLIP, BC_PRESSURE) if domain == "paper" else (BC_FREESLIP, BC_FREESLIP)
-    case = make_case(w, w, h, tau, lo, hi, int(round(0.08 * h)), g, h_ini=z0, h_end=z0 - 4 * D)
+    case = make_case(w, w, h, tau, lo, hi, sponge, g, h_ini=z0, h_end=z1)
     case["re"], case["d_eq"], case["v_terminal"] = re, D, v_t
     return case, body, v_t
 
