@@ -48,16 +48,17 @@ def drag_factor(u, r, nu, drag):
     return clift_gauvin_cd(re) * re / 24.0
 
 
-def settle(kappa, g, nu, r, dt, nsteps, history=True, added_mass=True, drag="stokes"):
+def settle(kappa, g, nu, r, dt, nsteps, history=True, added_mass=True, drag="stokes", drag_scale=1.0):
     """Speeds u_0 = 0, u_1 .. u_nsteps at t_n = n dt (implicit Euler).
 
     With m = kappa (+ 1/2 for the added mass), k = 9 nu / (2 r^2) phi(u_n),
     c = (9 / (2 r)) sqrt(nu / pi) (0 without the history term) and
     H_n = sum_j (u_j - u_{j-1}) / dt * 2 (sqrt(t_n - t_{j-1}) - sqrt(t_n - t_j)),
     each step solves m (u_n - u_{n-1}) / dt = kappa g - k u_n - c H_n for u_n;
-    H_n is linear in u_n through its last interval."""
+    H_n is linear in u_n through its last interval.  drag_scale multiplies
+    the drag term (a drag law scaled to a given terminal speed)."""
     m = kappa + (0.5 if added_mass else 0.0)
-    k0 = 9.0 * nu / (2.0 * r * r)
+    k0 = 9.0 * nu / (2.0 * r * r) * drag_scale
     c = 9.0 / (2.0 * r) * math.sqrt(nu / math.pi) if history else 0.0
     u = np.zeros(nsteps + 1)
     du = np.zeros(nsteps + 1)          # du[j] = u_j - u_{j-1}
@@ -104,3 +105,24 @@ def stokes_exact(kappa, g, nu, r, t, added_mass=True):
     e2 = wofz(-1j * p2 * rt)
     u = kappa * g / (m * (p1 - p2)) * (-(1.0 - e1) / p1 + (1.0 - e2) / p2)
     return u.real
+
+
+def terminal_speed(kappa, g, nu, r, drag="stokes", drag_scale=1.0):
+    """The speed at which the (scaled) drag balances the weight kappa g:
+    drag_scale (9 nu / (2 r^2)) phi(u) u = kappa g, by bisection."""
+    k0 = 9.0 * nu / (2.0 * r * r) * drag_scale
+    lo, hi = 0.0, kappa * g / k0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if k0 * drag_factor(mid, r, nu, drag) * mid < kappa * g:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def drag_scale_for(u_target, kappa, g, nu, r, drag="stokes"):
+    """The drag scale whose terminal speed is u_target (the weight over the
+    unscaled drag at that speed)."""
+    k0 = 9.0 * nu / (2.0 * r * r)
+    return kappa * g / (k0 * drag_factor(u_target, r, nu, drag) * u_target)

@@ -1,21 +1,22 @@
-"""Transient settling of a sphere from rest against the Basset-Boussinesq-Oseen
-equation of App. B (oracle/bbo.py), the comparison the paper makes for its
-Sphere-2 case (Sec. 3.1): the GPU trajectory of the coupled solver next to the
-implicit Euler solution of the equation with the same density ratio, gravity,
-viscosity and radius, and the Clift-Gauvin drag law.
+"""Transient settling of a heavy sphere from rest against the Basset-Boussinesq-
+Oseen equation of App. B (oracle/bbo.py) with the Clift-Gauvin drag: the
+comparison the paper makes for its Sphere-2 case (Sec. 3.1; Table 2: density
+ratio 996.26, Re 4.49, w* = 10, h* = 40, window from 35 D down to 5 D,
+sponge 4 D), scaled to a lattice terminal speed of 0.045.
 
-Not a parity test: both sides are physics.  The bounds come from what is
-known before the run:
-
-* the terminal speed on the parallel force surface comes out at 0.90 of the
-  Clift-Gauvin value at D = 16 in this box (the steady settling test of this
-  suite), so the GPU plateau lies 5-15 % below the equation's;
-* normalized by each curve's own plateau, the approach to it (times to 50 %
-  and 90 %) is what the equation predicts, within the confinement of the
-  10 D box and the diffuse interface (20 %).
-
-The heavy-particle case (density ratio 996, as in Sphere-2) needs about 10^5
-steps per relaxation time; it runs only with TURRET_LONG=1."""
+Not a parity test: both sides are physics.  At this density ratio the added
+mass is below 1/1000 of the inertia; the history force, relative to the
+drag, is about r / sqrt(pi nu t) whatever the density ratio (a few percent
+over these runs).  The steady terminal speed of the solver carries the
+resolution and confinement error of the force evaluation (about 10 % at
+D = 16 in the steady settling test of this suite, more at D = 8).  The test
+* bounds the solver's plateau against the equation's terminal speed, loosely
+  (within 0.75 .. 1.05 of it);
+* scales the equation's drag so that its terminal speed is the solver's
+  plateau, and compares the whole velocity history over four relaxation
+  times: with the history term dropped (the drag law's relaxation) within
+  1.5 % of the plateau; with it, as printed, the solver may run ahead of the
+  curve by up to the history term's weight (5 %) but not behind it (1 %)."""
 import json
 import os
 
@@ -27,6 +28,8 @@ from tests.gpu_util import say
 
 pytestmark = pytest.mark.gpu
 
+KAPPA = 996.26
+
 
 @pytest.fixture(scope="module")
 def T():
@@ -36,68 +39,56 @@ def T():
     return turret
 
 
-def crossing(t, v, frac, plateau):
-    """First time v reaches frac of plateau (linear between samples)."""
-    target = frac * plateau
-    i = int(np.argmax(v >= target))
-    if i == 0:
-        return float(t[0])
-    return float(t[i - 1] + (target - v[i - 1]) * (t[i] - t[i - 1]) / (v[i] - v[i - 1]))
-
-
-def run_transient(T, case, body, steps, every):
+def heavy_sphere_transient(T, D, relax=4.0, every=500, tag=None):
+    from oracle import bbo
+    case, body, v_t = W.case_sphere_settling(D, 4.49, KAPPA, force_offset=3.0, w_d=10, h_d=40, domain="paper",
+                                             v_t=0.045, h_ini_d=35, h_end_d=5, sponge_d=4)
+    nu = (case["tau"] - 0.5) / 3.0
+    r, g = D / 2.0, case["gravity"]
+    u_t = bbo.terminal_speed(KAPPA, g, nu, r, "clift_gauvin")
+    # relaxation time of the drag law at the terminal speed
+    t_relax = KAPPA * u_t / (KAPPA * g)
+    steps = int(relax * t_relax) // every * every
     S = T.Solver([case], [body])
     v = [0.0]
     for _ in range(steps // every):
         S.run(every)
         v.append(-S.body_state()["v"][2])
     S.close()
-    return np.arange(0, steps + 1, every, dtype=float), np.array(v)
-
-
-def compare(T, case, body, kappa, D, steps, every, tail, bbo_dt):
-    from oracle import bbo
-    t, v = run_transient(T, case, body, steps, every)
-    nu = (case["tau"] - 0.5) / 3.0
-    u = bbo.settle(kappa, case["gravity"], nu, D / 2.0, bbo_dt, int(steps / bbo_dt), drag="clift_gauvin")
-    tu = bbo_dt * np.arange(u.size)
-    ui = np.interp(t, tu, u)
-    n_tail = max(2, int(tail / every))
-    pg, pb = float(np.mean(v[-n_tail:])), float(np.mean(ui[-n_tail:]))
-    out = {"plateau_ratio": pg / pb}
-    for frac in (0.5, 0.9):
-        out[f"t{int(frac * 100)}_ratio"] = crossing(t, v, frac, pg) / crossing(t, ui, frac, pb)
-    return out, t, v, ui
-
-
-def test_transient_settling_follows_bbo(T):
-    case, body, v_t = W.case_sphere_settling(16.0, 5.0, 2.7, force_offset=3.0, domain="paper")
-    out, t, v, u = compare(T, case, body, 2.7, 16.0, 6000, 25, 1000, 1.0)
-    say(f"sphere D 16, kappa 2.7, Re 5: GPU / BBO plateau {out['plateau_ratio']:.4f}, "
-        f"t50 ratio {out['t50_ratio']:.4f}, t90 ratio {out['t90_ratio']:.4f}")
-    assert 0.85 < out["plateau_ratio"] < 0.95
-    assert abs(out["t50_ratio"] - 1.0) < 0.2
-    assert abs(out["t90_ratio"] - 1.0) < 0.2
-
-
-@pytest.mark.skipif(os.environ.get("TURRET_LONG") != "1", reason="about 10^5 steps per relaxation time; TURRET_LONG=1")
-def test_heavy_sphere_transient_follows_bbo(T):
-    """Sphere-2 layout (Table 2: w* = 10, h* = 40, from 35 D down to 5 D, sponge
-    4 D, density ratio 996.26, Re 4.49) at D = 16 with a lattice terminal speed
-    of 0.045 (tau 0.98): 4 relaxation times."""
-    kappa = 996.26
-    case, body, v_t = W.case_sphere_settling(16.0, 4.49, kappa, force_offset=3.0, w_d=10, h_d=40, domain="paper",
-                                             v_t=0.045, h_ini_d=35, h_end_d=5, sponge_d=4)
-    nu = (case["tau"] - 0.5) / 3.0
-    tau_p = kappa * 16.0 ** 2 / (18.0 * nu)
-    steps = int(4 * tau_p) // 500 * 500
-    out, t, v, u = compare(T, case, body, kappa, 16.0, steps, 500, steps // 8, 25.0)
-    say(f"sphere D 16, kappa 996.26, Re 4.49, {steps} steps: GPU / BBO plateau {out['plateau_ratio']:.4f}, "
-        f"t50 ratio {out['t50_ratio']:.4f}, t90 ratio {out['t90_ratio']:.4f}")
+    t = np.arange(0, steps + 1, every, dtype=float)
+    v = np.array(v)
+    plateau = float(np.mean(v[-max(2, len(v) // 16):]))
+    scale = bbo.drag_scale_for(plateau, KAPPA, g, nu, r, "clift_gauvin")
+    dt = 25.0
+    curves = {}
+    for name, hist in (("bbo", True), ("drag_only", False)):
+        u = bbo.settle(KAPPA, g, nu, r, dt, int(steps / dt), history=hist, drag="clift_gauvin", drag_scale=scale)
+        curves[name] = np.interp(t, dt * np.arange(u.size), u)
+    dev = {k: (v - c) / plateau for k, c in curves.items()}
+    out = {"D": D, "steps": steps, "relaxation_time": t_relax, "plateau_over_terminal": plateau / u_t,
+           "drag_scale": scale, "ahead_of_bbo": float(dev["bbo"].max()), "behind_bbo": float(-dev["bbo"].min()),
+           "max_dev_drag_only": float(np.abs(dev["drag_only"]).max())}
+    say(f"heavy sphere D {D}: {steps} steps ({relax} relaxation times of {t_relax:.0f}), plateau / "
+        f"Clift-Gauvin terminal {out['plateau_over_terminal']:.4f}, drag scale {scale:.4f}; over the "
+        f"plateau: ahead of the BBO curve by up to {out['ahead_of_bbo']:.4f}, behind by {out['behind_bbo']:.4f}, "
+        f"off the drag-law relaxation by {out['max_dev_drag_only']:.4f}")
     outdir = os.environ.get("TURRET_RESULTS_DIR")
-    if outdir:
-        with open(os.path.join(outdir, "transient_heavy_sphere.json"), "w") as f:
-            json.dump({"t": t.tolist(), "v_gpu": v.tolist(), "v_bbo": u.tolist(), **out}, f)
-    assert 0.85 < out["plateau_ratio"] < 0.95
-    assert abs(out["t50_ratio"] - 1.0) < 0.2
-    assert abs(out["t90_ratio"] - 1.0) < 0.2
+    if outdir and tag:
+        with open(os.path.join(outdir, f"transient_{tag}.json"), "w") as f:
+            json.dump({"t": t.tolist(), "v_gpu": v.tolist(), **{k: c.tolist() for k, c in curves.items()}, **out}, f)
+    return out
+
+
+def check(out):
+    assert 0.75 < out["plateau_over_terminal"] < 1.05
+    assert out["max_dev_drag_only"] < 0.015
+    assert out["ahead_of_bbo"] < 0.05 and out["behind_bbo"] < 0.01
+
+
+def test_heavy_sphere_transient_follows_bbo(T):
+    check(heavy_sphere_transient(T, 8.0, tag="heavy_sphere_d8"))
+
+
+@pytest.mark.skipif(os.environ.get("TURRET_LONG") != "1", reason="3.5e5 steps at D = 16; TURRET_LONG=1")
+def test_heavy_sphere_transient_follows_bbo_d16(T):
+    check(heavy_sphere_transient(T, 16.0, tag="heavy_sphere_d16"))

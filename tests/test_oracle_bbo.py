@@ -77,5 +77,13 @@ def test_clift_gauvin_terminal_speed_balances_the_weight():
         else:
             hi = mid
     assert u[-1] == pytest.approx(0.5 * (lo + hi), rel=1e-6)
+    assert bbo.terminal_speed(KAPPA, g, NU, R, "clift_gauvin") == pytest.approx(0.5 * (lo + hi), rel=1e-9)
     # the Stokes drag would be lower: the corrected speed is below the Stokes one
     assert u[-1] < KAPPA * g / K
+    # a drag scale for a given terminal speed reproduces that speed, and
+    # scaling the drag up slows the sphere
+    c = bbo.drag_scale_for(0.9 * u[-1], KAPPA, g, NU, R, "clift_gauvin")
+    assert c > 1.0
+    assert bbo.terminal_speed(KAPPA, g, NU, R, "clift_gauvin", c) == pytest.approx(0.9 * u[-1], rel=1e-9)
+    us = bbo.settle(KAPPA, g, NU, R, 1.0, n, history=False, drag="clift_gauvin", drag_scale=c)
+    assert us[-1] == pytest.approx(0.9 * u[-1], rel=1e-6)
