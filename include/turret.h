@@ -91,7 +91,10 @@ typedef struct {
  *                   integral there equals the force the body exerts through
  *                   the immersed forcing.  The particle region grows by delta.
  *   dS_offset       host, n_markers: marker areas of that parallel surface
- *                   (required when force_offset > 0; ignored otherwise) */
+ *                   (required when force_offset > 0; ignored otherwise)
+ *   torque          constant external torque, lab frame, added to the fluid
+ *                   torque in the angular update of Sec. 2.3 (App. B spins a
+ *                   sphere up from rest this way); zeros for settling */
 typedef struct {
     int32_t n_markers;
     const double *x_body;
@@ -102,6 +105,7 @@ typedef struct {
     double r0[3], d0[9], v0[3], w0[3];
     double force_offset;
     const double *dS_offset;
+    double torque[3];
 } lbm_body;
 
 /* Options.

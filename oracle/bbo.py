@@ -126,3 +126,70 @@ def drag_scale_for(u_target, kappa, g, nu, r, drag="stokes"):
     unscaled drag at that speed)."""
     k0 = 9.0 * nu / (2.0 * r * r)
     return kappa * g / (k0 * drag_factor(u_target, r, nu, drag) * u_target)
+
+
+# ------------------------------------------------------------ rotation
+# The rotational equation of App. B (Basset; Feuillebois & Lasek): a sphere of
+# moment of inertia I spun up from rest by a constant torque T, fluid
+# density 1, K0 = 8 pi nu r^3:
+#
+#   I dw/dt = T - K0 w - K0 (r / (3 sqrt(pi nu))) int_0^t w'(s) / sqrt(t - s) ds
+#               + (K0 / 3) int_0^t w'(s) exp(a (t - s)) erfc(sqrt(a (t - s))) ds,
+#   a = nu / r^2.
+#
+# Its Laplace transform is the unsteady Stokes torque on a rotating sphere,
+# K0 W (1 + lam r + lam^2 r^2 / 3) / (1 + lam r) with lam = sqrt(s / nu).
+
+def _erfc_kernel_integral(a, tau):
+    """G(tau) = int_0^tau exp(a x) erfc(sqrt(a x)) dx
+    = (exp(a tau) erfc(sqrt(a tau)) - 1 + 2 sqrt(a tau / pi)) / a."""
+    from scipy.special import erfcx
+    x = np.sqrt(a * np.asarray(tau, dtype=float))
+    return (erfcx(x) - 1.0 + 2.0 * x / math.sqrt(math.pi)) / a
+
+
+def spin_up(I, T, nu, r, dt, nsteps, history=True):
+    """Angular speeds w_0 = 0, w_1 .. w_nsteps at t_n = n dt (implicit Euler,
+    w' constant on each step: the 1/sqrt kernel integrates as in settle, the
+    exp-erfc kernel through its antiderivative G)."""
+    K0 = 8.0 * math.pi * nu * r ** 3
+    c1 = r / (3.0 * math.sqrt(math.pi * nu)) if history else 0.0
+    c2 = 1.0 / 3.0 if history else 0.0
+    a = nu / (r * r)
+    w = np.zeros(nsteps + 1)
+    dw = np.zeros(nsteps + 1)
+    sq = np.sqrt(dt * np.arange(nsteps + 1))
+    wt1 = np.zeros(nsteps + 1)
+    wt1[1:nsteps] = 2.0 * (sq[2:nsteps + 1] - sq[1:nsteps]) / dt
+    Gs = _erfc_kernel_integral(a, dt * np.arange(nsteps + 1))
+    wt2 = np.zeros(nsteps + 1)
+    wt2[1:nsteps] = (Gs[2:nsteps + 1] - Gs[1:nsteps]) / dt
+    l1, l2 = 2.0 / math.sqrt(dt), Gs[1] / dt     # the last interval's weights
+    for n in range(1, nsteps + 1):
+        h1 = float(np.dot(dw[n - 1:0:-1], wt1[1:n])) if n > 1 else 0.0
+        h2 = float(np.dot(dw[n - 1:0:-1], wt2[1:n])) if n > 1 else 0.0
+        # I (w_n - w_{n-1}) / dt = T - K0 w_n - K0 c1 (h1 + l1 dw_n) + K0 c2 (h2 + l2 dw_n)
+        lhs = I / dt + K0 + K0 * c1 * l1 - K0 * c2 * l2
+        rhs = T + (I / dt + K0 * c1 * l1 - K0 * c2 * l2) * w[n - 1] - K0 * c1 * h1 + K0 * c2 * h2
+        w[n] = rhs / lhs
+        dw[n] = w[n] - w[n - 1]
+    return w
+
+
+def spin_up_exact(I, T, nu, r, t):
+    """Closed form from the Laplace transform.  With p = sqrt(s) and
+    b = sqrt(nu) / r, W(s) = (T / I) (p + b) / (p^2 C(p)), C the cubic
+    p^3 + (b + K0 / (3 b I)) p^2 + (K0 / I) p + K0 b / I with roots p_i; by
+    partial fractions w(t) = (T / I) sum_i A_i (-(1 - E(p_i)) / p_i),
+    A_i = (p_i + b) / prod_{j != i} (p_i - p_j), E(p) = exp(p^2 t) erfc(-p sqrt(t))."""
+    from scipy.special import wofz
+    K0 = 8.0 * math.pi * nu * r ** 3
+    b = math.sqrt(nu) / r
+    roots = np.roots([1.0, b + K0 / (3.0 * b * I), K0 / I, K0 * b / I]).astype(complex)
+    t = np.asarray(t, dtype=float)
+    rt = np.sqrt(t)
+    out = np.zeros(t.shape, dtype=complex)
+    for i, pi in enumerate(roots):
+        Ai = (pi + b) / np.prod([pi - pj for j, pj in enumerate(roots) if j != i])
+        out += Ai * (-(1.0 - wofz(-1j * pi * rt)) / pi)
+    return (T / I * out).real

@@ -75,6 +75,7 @@ def lib():
         L.orc_sim_new.restype = C.c_void_p
         L.orc_sim_free.argtypes = [C.c_void_p]
         L.orc_sim_set_force_surface.argtypes = [C.c_void_p, d, pd]
+        L.orc_sim_set_torque.argtypes = [C.c_void_p, pd]
         L.orc_sim_set_f.argtypes = [C.c_void_p, pd]
         L.orc_sim_get_f.argtypes = [C.c_void_p, pd]
         L.orc_sim_get_h.argtypes = [C.c_void_p, pd]
@@ -246,6 +247,10 @@ class OracleSim:
         self.M = M
         self._keep = (dims, ip, dp, xb, nb, dS, bp)
         self._p = L.orc_sim_new(_pi(dims), _pi(ip), _pd(dp), M, _pd(xb), _pd(nb), _pd(dS), _pd(bp))
+        if body is not None and body.get("torque") is not None:
+            tq = _f64(body["torque"])
+            self._keep = self._keep + (tq,)
+            L.orc_sim_set_torque(self._p, _pd(tq))
         if body is not None and body.get("force_offset", 0.0) > 0.0:
             dSo = _f64(body["dS_offset"])
             self._keep = self._keep + (dSo,)

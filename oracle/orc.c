@@ -527,13 +527,14 @@ static void matvec(const double A[9], const double x[3], double y[3])
  * State: r, rows d_0..d_2 of the matrix M, v(t-1/2), w(t-1/2).
  *   a      = g + F / (kappa V)
  *   v     += a;           r += v
- *   w     += M^-1 (J/m)^-1 M T / (kappa V)
+ *   w     += M^-1 (J/m)^-1 M (T + T_ext) / (kappa V)   (T_ext: constant external torque)
  *   d_pred = d + w x d;   d += w x (d + d_pred)/2
  * M^-1 is the true inverse (the paper writes M^-1; the d_i are not
  * re-orthonormalised).  Gravity g = (0, 0, -gravity). */
 typedef struct {
     double r[3], d[9], v[3], w[3];
     double kappa, vol, Jm[9], gravity;
+    double Text[3];
 } body_t;
 
 static void body_advance(body_t *B, const double F[3], const double T[3])
@@ -547,7 +548,8 @@ static void body_advance(body_t *B, const double F[3], const double T[3])
     double Minv[9], Jinv[9], t1[3], t2[3], t3[3];
     inv3(B->d, Minv);
     inv3(B->Jm, Jinv);
-    matvec(B->d, T, t1);
+    const double Ttot[3] = {T[0] + B->Text[0], T[1] + B->Text[1], T[2] + B->Text[2]};
+    matvec(B->d, Ttot, t1);
     matvec(Jinv, t1, t2);
     matvec(Minv, t2, t3);
     for (int d = 0; d < 3; d++) B->w[d] += t3[d] / kv;
@@ -565,6 +567,7 @@ static void body_advance(body_t *B, const double F[3], const double T[3])
 void orc_body_advance(double *state, const double *FT, const double *params)
 {
     body_t B;
+    memset(&B, 0, sizeof B);   /* FT holds the whole torque: no external part */
     memcpy(B.r, state, 3 * sizeof(double));
     memcpy(B.d, state + 3, 9 * sizeof(double));
     memcpy(B.v, state + 12, 3 * sizeof(double));
@@ -660,6 +663,13 @@ orc_sim *orc_sim_new(const int32_t *dims, const int32_t *ip, const double *dp, i
 
 /* Force surface variant: the stress integral on the parallel surface at
  * distance delta outside the markers, with its marker areas dSo (M values). */
+/* Constant external torque (lab frame) added to the fluid torque in the
+ * angular update (App. B spins a sphere up from rest this way). */
+void orc_sim_set_torque(orc_sim *S, const double *T)
+{
+    for (int a = 0; a < 3; a++) S->B.Text[a] = T[a];
+}
+
 void orc_sim_set_force_surface(orc_sim *S, double delta, const double *dSo)
 {
     S->force_offset = delta;

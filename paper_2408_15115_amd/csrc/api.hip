@@ -61,6 +61,8 @@ std::string check_case(const lbm_case &c, const lbm_body *b)
             rb = std::max(rb, std::sqrt(s));
         }
         if (!(b->force_offset >= 0.0) || b->force_offset > 64.0) return "force_offset must be in [0, 64]";
+        for (int a = 0; a < 3; a++)
+            if (!std::isfinite(b->torque[a])) return "external torque must be finite";
         if (b->force_offset > 0.0 && !b->dS_offset) return "force_offset > 0 needs dS_offset";
         const double ro = rb + b->force_offset;   // reach of the force-evaluation points
         const double lo = b->r0[2] - ro, hi = b->r0[2] + ro;
@@ -430,6 +432,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
             std::memcpy(B.d, b.d0, sizeof B.d);
             std::memcpy(B.v, b.v0, sizeof B.v);
             std::memcpy(B.w, b.w0, sizeof B.w);
+            std::memcpy(B.Text, b.torque, sizeof B.Text);
             const double *J = b.J_over_m;
             const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
             const double inv = 1.0 / (J[0] * c00 + J[1] * c01 + J[2] * c02);

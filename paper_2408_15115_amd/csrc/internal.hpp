@@ -29,6 +29,7 @@ struct CaseDev {
 struct BodyDev {
     double r[3], d[9], v[3], w[3];
     double F[3], T[3], Fp[3];
+    double Text[3];  // constant external torque (lab frame)
     double kappa, vol, Jm_inv[9], gravity, Rb, resid;
     int z0;          // ring origin: physical row z is stored in slot (z + z0) mod nz
     int shift_now;   // 1 if the window moved during the last window_shift

@@ -61,8 +61,9 @@ __device__ inline void mv3(const double A[9], const double x[3], double y[3])
 }
 
 // Sec. 2.3 leapfrog with F(t), T(t): a = g + F/(kappa V), v(t+1/2), r(t+1);
-// w(t+1/2) through M^-1 (J/m)^-1 M; orientation predictor-corrector.  Then
-// the IBM region origin for the new position.
+// w(t+1/2) through M^-1 (J/m)^-1 M with the fluid torque plus the body's
+// constant external torque; orientation predictor-corrector.  Then the IBM
+// region origin for the new position.
 __global__ void k_body_advance(DevPtrs p, int n_cases)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -79,7 +80,8 @@ __global__ void k_body_advance(DevPtrs p, int n_cases)
     }
     double Minv[9], t1[3], t2[3], t3[3];
     inverse3(B.d, Minv);
-    mv3(B.d, B.T, t1);
+    const double Ttot[3] = {B.T[0] + B.Text[0], B.T[1] + B.Text[1], B.T[2] + B.Text[2]};
+    mv3(B.d, Ttot, t1);
     mv3(B.Jm_inv, t1, t2);
     mv3(Minv, t2, t3);
 #pragma unroll

@@ -36,7 +36,7 @@ class lbm_body(C.Structure):
                 ("dS", C.POINTER(C.c_double)), ("kappa", C.c_double), ("volume", C.c_double),
                 ("J_over_m", C.c_double * 9), ("r0", C.c_double * 3), ("d0", C.c_double * 9),
                 ("v0", C.c_double * 3), ("w0", C.c_double * 3), ("force_offset", C.c_double),
-                ("dS_offset", C.POINTER(C.c_double))]
+                ("dS_offset", C.POINTER(C.c_double)), ("torque", C.c_double * 3)]
 
 
 class lbm_options(C.Structure):
@@ -136,6 +136,8 @@ def make_body(d: dict | None, keep: list) -> lbm_body:
     b.d0[:] = [float(v) for v in np.ravel(d["d0"])]
     b.v0[:] = [float(v) for v in np.ravel(d["v0"])]
     b.w0[:] = [float(v) for v in np.ravel(d["w0"])]
+    if d.get("torque") is not None:
+        b.torque[:] = [float(v) for v in np.ravel(d["torque"])]
     if d.get("force_offset", 0.0) > 0.0:
         b.force_offset = float(d["force_offset"])
         if d.get("dS_offset") is not None:   # else NULL: the library rejects the body

@@ -60,6 +60,7 @@ def test_required_bytes_of_the_sphere_case():
     (lambda c, b: b.update(r0=np.array([23.5, 23.5, 4.0])), "wall"),
     (lambda c, b: c.update(bc_zlo=0), "periodic"),
     (lambda c, b: c.update(nx=12, ny=12), "region"),
+    (lambda c, b: b.update(torque=np.array([0.0, np.nan, 0.0])), "torque"),
 ])
 def test_invalid_cases_rejected_on_host(mutate, needle):
     from paper_2408_15115_amd import turret as T

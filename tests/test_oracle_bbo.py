@@ -87,3 +87,43 @@ def test_clift_gauvin_terminal_speed_balances_the_weight():
     assert bbo.terminal_speed(KAPPA, g, NU, R, "clift_gauvin", c) == pytest.approx(0.9 * u[-1], rel=1e-9)
     us = bbo.settle(KAPPA, g, NU, R, 1.0, n, history=False, drag="clift_gauvin", drag_scale=c)
     assert us[-1] == pytest.approx(0.9 * u[-1], rel=1e-6)
+
+
+# ------------------------------------------------------------ rotation
+KR, RR, NUR, TQ = 100.0, 8.0, 0.1, 1e-3
+IR = KR * 4.0 / 3.0 * math.pi * RR ** 3 * 0.4 * RR * RR
+K0R = 8.0 * math.pi * NUR * RR ** 3
+
+
+def test_spin_up_without_history_is_the_exponential():
+    errs = []
+    for dt in (40.0, 20.0, 10.0):
+        n = int(4 * IR / K0R / dt)
+        w = bbo.spin_up(IR, TQ, NUR, RR, dt, n, history=False)
+        t = dt * np.arange(n + 1)
+        errs.append(np.abs(w - TQ / K0R * (1.0 - np.exp(-K0R * t / IR))).max() / (TQ / K0R))
+    assert errs[-1] < 5e-4
+    for a, b in zip(errs, errs[1:]):
+        assert 1.8 < a / b < 2.2
+
+
+def test_spin_up_converges_to_the_laplace_closed_form():
+    errs = []
+    for dt in (40.0, 10.0, 2.5):
+        n = int(4 * IR / K0R / dt)
+        w = bbo.spin_up(IR, TQ, NUR, RR, dt, n)
+        t = dt * np.arange(n + 1)
+        errs.append(np.abs(w - bbo.spin_up_exact(IR, TQ, NUR, RR, t)).max() / (TQ / K0R))
+    assert errs[-1] < 2e-4
+    for a, b in zip(errs, errs[1:]):
+        assert 3.2 < a / b < 4.8
+
+
+def test_spin_up_closed_form_limits():
+    w = bbo.spin_up_exact(IR, TQ, NUR, RR, np.array([0.0, 1e-3, 1e10]))
+    assert abs(w[0]) < 1e-20
+    assert abs(w[1] / 1e-3 / (TQ / IR) - 1.0) < 1e-3     # initial slope T / I
+    assert abs(w[2] / (TQ / K0R) - 1.0) < 1e-8          # steady rotlet: T = 8 pi nu r^3 w
+    # the history terms slow the approach: below the exponential at one relaxation time
+    t1 = IR / K0R
+    assert bbo.spin_up_exact(IR, TQ, NUR, RR, np.array([t1]))[0] < TQ / K0R * (1.0 - math.exp(-1.0))

@@ -70,3 +70,28 @@ def test_anisotropic_inertia_uses_body_frame(orc):
         T = 1e-3 * d[j]
         st = orc.body_advance(st, np.zeros(3), T, 2.0, 10.0, Jm, 0.0)
         assert np.allclose(st["w"], T / (2.0 * 10.0 * Jm[j, j]), atol=1e-17)
+
+
+def test_external_torque_enters_the_angular_update(orc):
+    """A body with a constant external torque in a fluid at rest: after the
+    first step (fluid torque T(0) = 0) w = w0 + (J/m)^-1 T_ext / (kappa V),
+    with the inertia in the body frame of a rotated ellipsoid."""
+    from paper_2408_15115_amd import workloads as W
+    case = W.make_case(24, 24, 40, 0.7, W.BC_FREESLIP, W.BC_FREESLIP, 0, 0.0)
+    V, F = W.ellipsoid_mesh(4.0, 3.0, 2.5, 5)
+    M = W.rotation_matrix([1.0, 2.0, 0.5], 0.6).T
+    body = W.mesh_body(V, F, 3.0, [11.5, 11.5, 19.5], d0=M)
+    Text = np.array([2e-3, -1e-3, 5e-4])
+    body["torque"] = Text
+    s = orc.OracleSim(case, body)
+    s.step(1)
+    st = s.body_state()
+    Jm = np.asarray(body["J_over_m"]).reshape(3, 3)
+    D = np.asarray(body["d0"]).reshape(3, 3)          # rows d_0..d_2
+    want = np.linalg.inv(D) @ np.linalg.solve(Jm, D @ Text) / (body["kappa"] * body["volume"])
+    assert np.allclose(st["w"], np.asarray(body["w0"]) + want, rtol=1e-12, atol=1e-18)
+    # without it the body stays at rest
+    body.pop("torque")
+    s2 = orc.OracleSim(case, body)
+    s2.step(1)
+    assert np.allclose(s2.body_state()["w"], body["w0"], atol=1e-18)
