@@ -16,6 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "orc.c")
+SRC19_PATH = os.path.join(_HERE, "orc19.c")     # the D3Q19 comparison lattice
 # A test of the pins themselves may point this at a build with a planted mistake.
 _OVERRIDE = os.environ.get("ORACLE_LIB_OVERRIDE")
 
@@ -24,10 +25,11 @@ BC_PERIODIC, BC_FREESLIP, BC_NOSLIP, BC_PRESSURE = 0, 1, 2, 3
 
 def build(force: bool = False) -> str:
     """Compile orc.c with gcc (-O2, OpenMP, strict IEEE: no fast-math)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
+            os.path.getmtime(SRC_PATH), os.path.getmtime(SRC19_PATH)):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
-                               SRC_PATH, "-o", tmp, "-lm"])
+                               SRC_PATH, SRC19_PATH, "-o", tmp, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -76,6 +78,11 @@ def lib():
         L.orc_sim_free.argtypes = [C.c_void_p]
         L.orc_sim_set_force_surface.argtypes = [C.c_void_p, d, pd]
         L.orc_sim_set_torque.argtypes = [C.c_void_p, pd]
+        L.orc19_lattice.argtypes = [pi, pd]
+        L.orc19_feq.argtypes = [d, pd, pd]
+        L.orc19_f1.argtypes = [pd, pd, pd]
+        L.orc19_collide_cell.argtypes = [pd, d, i32, pd]
+        L.orc19_run.argtypes = [i32, i32, i32, d, i32, pd, i32]
         L.orc_sim_set_f.argtypes = [C.c_void_p, pd]
         L.orc_sim_get_f.argtypes = [C.c_void_p, pd]
         L.orc_sim_get_h.argtypes = [C.c_void_p, pd]
@@ -212,6 +219,42 @@ def body_advance(state, F, T, kappa, volume, J_over_m, gravity):
     prm = _f64(np.concatenate([[kappa, volume], np.ravel(J_over_m), [gravity]]))
     lib().orc_body_advance(_pd(st), _pd(FT), _pd(prm))
     return {"r": st[0:3].copy(), "d": st[3:12].reshape(3, 3).copy(), "v": st[12:15].copy(), "w": st[15:18].copy()}
+
+
+# ------------------------------------------------------------ D3Q19 lattice
+def lattice19():
+    """(xi (19, 3) int, w (19,)) of the D3Q19 comparison lattice."""
+    xi = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    lib().orc19_lattice(_pi(xi), _pd(w))
+    return xi, w
+
+
+def feq19(rho, u):
+    out = np.zeros(19)
+    lib().orc19_feq(float(rho), _pd(_f64(u)), _pd(out))
+    return out
+
+
+def f1_19(P1, u):
+    out = np.zeros(19)
+    lib().orc19_f1(_pd(_f64(P1, (3, 3))), _pd(_f64(u)), _pd(out))
+    return out
+
+
+def collide19(f, tau, collision=0):
+    out = np.zeros(19)
+    lib().orc19_collide_cell(_pd(_f64(f)), float(tau), int(collision), _pd(out))
+    return out
+
+
+def run19(f, tau, nsteps, collision=0):
+    """nsteps of the D3Q19 fluid step on a periodic box; f is (nz, ny, nx, 19)."""
+    f = np.array(f, np.float64, order="C")
+    nz, ny, nx, q = f.shape
+    assert q == 19
+    lib().orc19_run(nx, ny, nz, float(tau), int(collision), _pd(f), int(nsteps))
+    return f
 
 
 # ------------------------------------------------------------- simulation
