@@ -380,16 +380,19 @@ def settling_sweep(T, W, torch, diameters, re=5.0, offsets=(0.0, 3.0), domain="p
 def stability_run(T, W, torch, n=64, U0=0.1, steps=2000):
     """3-D Taylor-Green vortex (n^3, U0 = 0.1): the smallest relaxation time
     that runs `steps` steps without tripping the lattice kernel's guard, for
-    the recursive-regularized collision and for BGK on the same lattice."""
+    the recursive-regularized collision and for BGK, on D3Q27 and on the D3Q19
+    comparison lattice."""
     import numpy as np
     taus = [0.52, 0.51, 0.505, 0.502, 0.501, 0.5005, 0.5002, 0.5001]
-    f0 = np.moveaxis(W.taylor_green_populations(n, U0), -1, 0)
+    f27 = np.moveaxis(W.taylor_green_populations(n, U0), -1, 0)
+    f19 = np.moveaxis(W.taylor_green_populations19(n, U0), -1, 0)
     out = {"workload": f"Taylor-Green vortex {n}^3, U0 {U0}, {steps} steps", "taus_tried": taus}
-    for name, coll in (("regularized", 0), ("bgk", 1)):
+    for name, coll, q, f0 in (("regularized", 0, 27, f27), ("bgk", 1, 27, f27),
+                              ("regularized_d3q19", 0, 19, f19), ("bgk_d3q19", 1, 19, f19)):
         low = None
         for tau in taus:
             S = T.Solver([W.make_case(n, n, n, tau, W.BC_PERIODIC, W.BC_PERIODIC, 0)], collision=coll,
-                         stream=torch.cuda.Stream())
+                         stream=torch.cuda.Stream(), lattice=q)
             S.set_populations(f0)
             ok = True
             for _ in range(steps // 250):
@@ -403,6 +406,35 @@ def stability_run(T, W, torch, n=64, U0=0.1, steps=2000):
             low = tau
         out[name] = {"smallest_stable_tau": low,
                      "reynolds": round(U0 * n / (2 * math.pi) / ((low - 0.5) / 3.0), 1) if low else None}
+    return out
+
+
+def lattice_rate_run(T, W, torch, n=(256, 256, 768), steps=20, warmup=3):
+    """Fluid-only periodic box, FP32 storage, recursive-regularized collision:
+    the lattice kernel alone on D3Q27 and on the D3Q19 comparison lattice;
+    GLUPS and the algorithmic bandwidth (q populations read and written)."""
+    import numpy as np
+    nx, ny, nz = n
+    out = {"workload": f"fluid-only periodic {nx}x{ny}x{nz}, FP32, recursive regularized, {steps} steps"}
+    for q in (27, 19):
+        S = T.Solver([W.make_case(nx, ny, nz, 0.6, W.BC_PERIODIC, W.BC_PERIODIC, 0)], lattice=q,
+                     stream=torch.cuda.Stream())
+        for _ in range(warmup):
+            S.lbm_step()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(S.stream)
+        for _ in range(steps):
+            S.lbm_step()
+        t1.record(S.stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        err = S.body_state(0, check=False)["err"]
+        S.close()
+        cells = nx * ny * nz
+        out[f"d3q{q}"] = {"ms_per_step": round(ms, 4), "glups": round(cells / (ms * 1e-3) / 1e9, 2),
+                          "gbps": round(cells * q * 8 / (ms * 1e-3) / 1e9, 1), "err": int(err)}
+    torch.cuda.empty_cache()
     return out
 
 
@@ -579,7 +611,13 @@ def main():
     if not args.no_variants and not args.no_stability:
         sb = stability_run(T, W, torch)
         variants["stability"] = sb
-        log(f"  Taylor-Green stability, smallest stable tau: regularized {sb['regularized']}, BGK {sb['bgk']}")
+        log(f"  Taylor-Green stability, smallest stable tau: regularized {sb['regularized']}, BGK {sb['bgk']}; "
+            f"D3Q19 regularized {sb['regularized_d3q19']}, BGK {sb['bgk_d3q19']}")
+
+    if not args.no_variants and not args.no_stability:
+        lr19 = lattice_rate_run(T, W, torch)
+        variants["lattice_rate"] = lr19
+        log(f"  fluid-only lattice kernel: D3Q27 {lr19['d3q27']}, D3Q19 {lr19['d3q19']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -140,7 +140,16 @@ typedef struct {
  *   collision   0 = the recursive-regularized collision of Sec. 2.1 / App. A
  *               (the default); 1 = BGK for comparison: the same rule with the
  *               raw off-equilibrium f - f0(p, u) in place of f1 (all its
- *               moments relax by 1 - 1/tau); runs with schedule 0 */
+ *               moments relax by 1 - 1/tau); runs with schedule 0
+ *   lattice     0 or 27 = D3Q27 (Sec. 2.1, the default); 19 = D3Q19, the
+ *               lattice the paper compares its choice with for stability:
+ *               the same collision construction on the Hermite
+ *               polynomials D3Q19 carries (third order through the
+ *               orthogonal pairs H_xxy +- H_yzz, H_yyz +- H_xxz,
+ *               H_zzx +- H_xyy; no fourth order).  Fluid-only contexts
+ *               (no markers), FP32 storage, periodic z, no sponge,
+ *               schedule 0; populations are then [19][nz][ny][nx] with
+ *               the D3Q27 direction order, corners left out */
 typedef struct {
     int32_t storage;
     int32_t ibm_cycles;
@@ -152,6 +161,7 @@ typedef struct {
     int32_t forcing;
     int32_t serial_ibm;
     int32_t collision;
+    int32_t lattice;
 } lbm_options;
 
 /* Caller-owned device buffers (byte sizes from lbm_required_bytes):

@@ -83,6 +83,8 @@ def lib():
         L.orc19_f1.argtypes = [pd, pd, pd]
         L.orc19_collide_cell.argtypes = [pd, d, i32, pd]
         L.orc19_run.argtypes = [i32, i32, i32, d, i32, pd, i32]
+        L.orc19_collide_grid.argtypes = [i32, i32, i32, d, i32, pd]
+        L.orc19_stream.argtypes = [i32, i32, i32, pd]
         L.orc_sim_set_f.argtypes = [C.c_void_p, pd]
         L.orc_sim_get_f.argtypes = [C.c_void_p, pd]
         L.orc_sim_get_h.argtypes = [C.c_void_p, pd]
@@ -254,6 +256,24 @@ def run19(f, tau, nsteps, collision=0):
     nz, ny, nx, q = f.shape
     assert q == 19
     lib().orc19_run(nx, ny, nz, float(tau), int(collision), _pd(f), int(nsteps))
+    return f
+
+
+def collide_grid19(f, tau, collision=0):
+    """The D3Q19 collision on every cell of an (nz, ny, nx, 19) field."""
+    f = np.array(f, np.float64, order="C")
+    nz, ny, nx, q = f.shape
+    assert q == 19
+    lib().orc19_collide_grid(nx, ny, nz, float(tau), int(collision), _pd(f))
+    return f
+
+
+def stream19(f):
+    """Periodic pull-streaming of an (nz, ny, nx, 19) field."""
+    f = np.array(f, np.float64, order="C")
+    nz, ny, nx, q = f.shape
+    assert q == 19
+    lib().orc19_stream(nx, ny, nz, _pd(f))
     return f
 
 

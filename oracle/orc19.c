@@ -161,6 +161,36 @@ static int wrap19(int v, int n)
     return v < 0 ? v + n : v;
 }
 
+/* Collision alone on every cell of an nx x ny x nz grid, f in place. */
+void orc19_collide_grid(int32_t nx, int32_t ny, int32_t nz, double tau, int32_t collision, double *f)
+{
+    orc19_init();
+    const long long n = (long long)nx * ny * nz;
+#pragma omp parallel for
+    for (long long c = 0; c < n; c++) {
+        double out[Q19];
+        orc19_collide_cell(f + c * Q19, tau, collision, out);
+        memcpy(f + c * Q19, out, sizeof(out));
+    }
+}
+
+/* Pull-streaming alone, f_i(x) <- f_i(x - xi_i), periodic, f in place. */
+void orc19_stream(int32_t nx, int32_t ny, int32_t nz, double *f)
+{
+    orc19_init();
+    const size_t n = (size_t)nx * ny * nz;
+    double *C = (double *)malloc(n * Q19 * sizeof(double));
+    memcpy(C, f, n * Q19 * sizeof(double));
+    for (size_t c = 0; c < n; c++) {
+        const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((size_t)nx * ny));
+        for (int i = 0; i < Q19; i++) {
+            const int xs = wrap19(x - xi19[i][0], nx), ys = wrap19(y - xi19[i][1], ny), zs = wrap19(z - xi19[i][2], nz);
+            f[c * Q19 + i] = C[(((size_t)zs * ny + ys) * nx + xs) * Q19 + i];
+        }
+    }
+    free(C);
+}
+
 /* nsteps of collide + pull-stream on an nx x ny x nz periodic box;
  * f is [nz][ny][nx][19], updated in place. */
 void orc19_run(int32_t nx, int32_t ny, int32_t nz, double tau, int32_t collision, double *f, int32_t nsteps)

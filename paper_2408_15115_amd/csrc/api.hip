@@ -33,6 +33,7 @@ struct Plan {
     long long max_tiles = 0;    // tile table capacity: the count at the smallest block (64)
     int Mtot = 0, maxL3 = 0, max_slab = 0;
     int force_surface = 0;    // some case evaluates its force on the parallel surface
+    int q = 27;               // populations per cell: 27, or 19 for the D3Q19 comparison lattice
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
         off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox,
@@ -95,6 +96,7 @@ std::string check_options(const lbm_options *o)
     if (o->forcing < 0 || o->forcing > 1) return "forcing must be 0 or 1";
     if (o->serial_ibm < 0 || o->serial_ibm > 1) return "serial_ibm must be 0 or 1";
     if (o->collision < 0 || o->collision > 1) return "collision must be 0 or 1";
+    if (o->lattice != 0 && o->lattice != 19 && o->lattice != 27) return "lattice must be 27 (or 0) or 19";
     return "";
 }
 
@@ -177,6 +179,11 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     if (!e.empty()) return e;
     P.block = (opt && opt->block) ? opt->block : 256;
     const int eb = elem_bytes(opt ? opt->storage : LBM_F32);
+    P.q = (opt && opt->lattice == 19) ? 19 : 27;
+    if (P.q == 19) {
+        if (opt->storage != LBM_F32) return "the D3Q19 lattice runs with FP32 storage";
+        if (opt->schedule != 0) return "the D3Q19 lattice runs with schedule 0";
+    }
     P.cd.assign(n, CaseDev{});
     long long pop = 0, reg = 0;
     int moff = 0;
@@ -185,6 +192,11 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         const lbm_body *b = bodies ? &bodies[c] : nullptr;
         e = check_case(k, b);
         if (!e.empty()) return "case " + std::to_string(c) + ": " + e;
+        if (P.q == 19) {
+            if (b && b->n_markers > 0) return "case " + std::to_string(c) + ": the D3Q19 lattice is fluid-only (no markers)";
+            if (k.bc_zlo != LBM_BC_PERIODIC || k.bc_zhi != LBM_BC_PERIODIC || k.sponge_cells != 0)
+                return "case " + std::to_string(c) + ": the D3Q19 lattice needs periodic z and no sponge";
+        }
         CaseDev &d = P.cd[c];
         d.nx = k.nx;
         d.ny = k.ny;
@@ -201,7 +213,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         d.cells = (long long)k.nx * k.ny * k.nz;
         d.plane = (d.cells + 127) / 128 * 128;   // 256-byte aligned direction planes
         d.pop_off = pop;
-        pop += Q * d.plane;
+        pop += P.q * d.plane;
         d.M = b ? std::max(0, b->n_markers) : 0;
         d.force_offset = (b && d.M > 0) ? b->force_offset : 0.0;
         if (d.force_offset > 0.0) P.force_surface = 1;
@@ -500,11 +512,17 @@ static int32_t do_lbm_step(lbm_ctx *ctx)
 {
     const int src = ctx->cur, dst = 1 - ctx->cur;
     if (ctx->has_body) HIPCHK(ctx, hipEventRecord(ctx->fork, ctx->stream), "record fork event");
-    HIPCHK(ctx,
-           launch_stream_collide(ctx->opt.storage, ctx->pop[src], ctx->pop[dst], ctx->p, (int)ctx->plan.tiles.size(),
-                                 ctx->opt.block, ctx->opt.schedule, ctx->opt.persist_wgs, ctx->opt.collision,
-                                 ctx->stream),
-           "lbm_step");
+    if (ctx->plan.q == 19)
+        HIPCHK(ctx,
+               launch_stream_collide19(ctx->pop[src], ctx->pop[dst], ctx->p, (int)ctx->plan.tiles.size(),
+                                       ctx->opt.block, ctx->opt.collision, ctx->stream),
+               "lbm_step");
+    else
+        HIPCHK(ctx,
+               launch_stream_collide(ctx->opt.storage, ctx->pop[src], ctx->pop[dst], ctx->p,
+                                     (int)ctx->plan.tiles.size(), ctx->opt.block, ctx->opt.schedule,
+                                     ctx->opt.persist_wgs, ctx->opt.collision, ctx->stream),
+               "lbm_step");
     ctx->cur = dst;
     ctx->needs_ibm = ctx->has_body;
     return LBM_OK;
@@ -594,8 +612,10 @@ int32_t lbm_set_schedule(lbm_ctx *ctx, const lbm_options *opt)
     std::string e = check_options(opt);
     if (!e.empty()) return fail(ctx, LBM_EINVAL, e);
     const int cyc = opt->ibm_cycles ? opt->ibm_cycles : 4;
-    if (opt->storage != ctx->opt.storage || cyc != ctx->opt.ibm_cycles || opt->forcing != ctx->opt.forcing)
-        return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage, ibm_cycles or forcing");
+    if (opt->storage != ctx->opt.storage || cyc != ctx->opt.ibm_cycles || opt->forcing != ctx->opt.forcing ||
+        (opt->lattice == 19) != (ctx->plan.q == 19))
+        return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage, ibm_cycles, forcing or lattice");
+    if (ctx->plan.q == 19 && opt->schedule != 0) return fail(ctx, LBM_EINVAL, "the D3Q19 lattice runs with schedule 0");
     if (opt->serial_ibm != ctx->opt.serial_ibm || opt->collision != ctx->opt.collision) drop_graph(ctx);
     ctx->opt.serial_ibm = opt->serial_ibm;
     ctx->opt.collision = opt->collision;
@@ -664,6 +684,21 @@ int32_t lbm_graph_launch(lbm_ctx *ctx)
 }
 
 // ------------------------------------------------------------ host copies
+// Weight of direction i: D3Q27, or D3Q19 (the D3Q27 order with the corners
+// left out: 1/3, 1/18, 1/36).
+static double lattice_weight(int q, int i)
+{
+    if (q == 27) return wq(i);
+    int j = 0;
+    for (int k = 0; k < 27; k++) {
+        const int n = (k % 3 - 1) * (k % 3 - 1) + ((k / 3) % 3 - 1) * ((k / 3) % 3 - 1) + (k / 9 - 1) * (k / 9 - 1);
+        if (n == 3) continue;
+        if (j == i) return n == 0 ? 1.0 / 3.0 : (n == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+        j++;
+    }
+    return 0.0;
+}
+
 static float host_dec(int storage, const void *raw, size_t idx, int i)
 {
     const double inv = wq(i) / kScaleBase;
@@ -707,17 +742,18 @@ int32_t lbm_get_populations(lbm_ctx *ctx, int32_t c, double *out)
     if (r) return r;
     const CaseDev &d = ctx->plan.cd[c];
     const int eb = elem_bytes(ctx->opt.storage);
-    std::vector<char> raw((size_t)Q * d.plane * eb);
+    const int q = ctx->plan.q;
+    std::vector<char> raw((size_t)q * d.plane * eb);
     const char *src = (const char *)ctx->pop[ctx->cur] + (size_t)d.pop_off * eb;
     HIPCHK(ctx, hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, ctx->stream), "copy populations");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     const size_t slab = (size_t)d.nx * d.ny;
-    for (int i = 0; i < Q; i++)
+    for (int i = 0; i < q; i++)
         for (int z = 0; z < d.nz; z++) {
             const int zc = (z + B.z0) % d.nz;
-            for (size_t q = 0; q < slab; q++)
-                out[((size_t)i * d.nz + z) * slab + q] =
-                    wq(i) + (double)host_dec(ctx->opt.storage, raw.data(), (size_t)i * d.plane + zc * slab + q, i);
+            for (size_t k = 0; k < slab; k++)
+                out[((size_t)i * d.nz + z) * slab + k] =
+                    lattice_weight(q, i) + (double)host_dec(ctx->opt.storage, raw.data(), (size_t)i * d.plane + zc * slab + k, i);
         }
     return B.err ? fail(ctx, LBM_EUNSTABLE, "unstable: marker stencil left the box or non-finite IBM value") : LBM_OK;
 }
@@ -731,14 +767,15 @@ int32_t lbm_set_populations(lbm_ctx *ctx, int32_t c, const double *in)
     if (r) return r;
     const CaseDev &d = ctx->plan.cd[c];
     const int eb = elem_bytes(ctx->opt.storage);
-    std::vector<char> raw((size_t)Q * d.plane * eb);
+    const int q = ctx->plan.q;
+    std::vector<char> raw((size_t)q * d.plane * eb);
     const size_t slab = (size_t)d.nx * d.ny;
-    for (int i = 0; i < Q; i++)
+    for (int i = 0; i < q; i++)
         for (int z = 0; z < d.nz; z++) {
             const int zc = (z + B.z0) % d.nz;
-            for (size_t q = 0; q < slab; q++)
-                host_enc(ctx->opt.storage, raw.data(), (size_t)i * d.plane + zc * slab + q, i,
-                         (float)(in[((size_t)i * d.nz + z) * slab + q] - wq(i)));
+            for (size_t k = 0; k < slab; k++)
+                host_enc(ctx->opt.storage, raw.data(), (size_t)i * d.plane + zc * slab + k, i,
+                         (float)(in[((size_t)i * d.nz + z) * slab + k] - lattice_weight(q, i)));
         }
     char *dst = (char *)ctx->pop[ctx->cur] + (size_t)d.pop_off * eb;
     HIPCHK(ctx, hipMemcpyAsync(dst, raw.data(), raw.size(), hipMemcpyHostToDevice, ctx->stream), "copy populations");

@@ -116,6 +116,9 @@ struct DevPtrs {
 // collision: 0 = recursive regularized, 1 = BGK (comparison; plain schedule)
 hipError_t launch_stream_collide(int storage, const void *src, void *dst, const DevPtrs &p, int ntiles,
                                  int block, int schedule, int persist_wgs, int collision, hipStream_t s);
+// The D3Q19 comparison lattice (fluid only, FP32, periodic, plain schedule).
+hipError_t launch_stream_collide19(const void *src, void *dst, const DevPtrs &p, int ntiles, int block,
+                                   int collision, hipStream_t s);
 hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
 // IBM coupling.  With a warm start (warm_mode 1: the previous step's final
 // h_k; 2: the network th16) cycles run from that start until a case's

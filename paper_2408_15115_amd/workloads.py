@@ -35,6 +35,11 @@ V_TERMINAL_LU = 0.02
 # near-rest population fields.
 _W1 = {-1: 1.0 / 6.0, 0: 2.0 / 3.0, 1: 1.0 / 6.0}
 D3Q27_W = np.array([_W1[i % 3 - 1] * _W1[(i // 3) % 3 - 1] * _W1[i // 9 - 1] for i in range(27)])
+# D3Q19 (the comparison lattice): the D3Q27 directions without the eight
+# corners, same order; weights 1/3, 1/18, 1/36.
+D3Q19_XI = np.array([[i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1] for i in range(27)
+                     if abs(i % 3 - 1) + abs((i // 3) % 3 - 1) + abs(i // 9 - 1) < 3], np.float64)
+D3Q19_W = np.array([{0: 1.0 / 3.0, 1: 1.0 / 18.0, 2: 1.0 / 36.0}[int(np.abs(v).sum())] for v in D3Q19_XI])
 
 
 # ---------------------------------------------------------------- meshes
@@ -377,6 +382,27 @@ def taylor_green_populations(n, U0):
     xu = u @ xi.T
     uu = (u * u).sum(-1, keepdims=True)
     return D3Q27_W * (1.0 + 3.0 * xu + 4.5 * xu * xu - 1.5 * uu)
+
+
+def taylor_green_populations19(n, U0):
+    """The same Taylor-Green state on the D3Q19 lattice.  Layout (nz, ny, nx, 19)."""
+    t = 2 * math.pi * np.arange(n) / n
+    c, b, a = np.meshgrid(t, t, t, indexing="ij")
+    u = np.stack([U0 * np.sin(a) * np.cos(b) * np.cos(c), -U0 * np.cos(a) * np.sin(b) * np.cos(c),
+                  np.zeros_like(a)], axis=-1)
+    xu = u @ D3Q19_XI.T
+    uu = (u * u).sum(-1, keepdims=True)
+    return D3Q19_W * (1.0 + 3.0 * xu + 4.5 * xu * xu - 1.5 * uu)
+
+
+def random_populations19(seed, nx, ny, nz, amp=0.02):
+    """Near-rest D3Q19 field f_i = w_i (1 + amp * eta_i(x)), smooth random
+    eta_i.  Layout (nz, ny, nx, 19)."""
+    rng = np.random.default_rng(seed)
+    f = np.empty((nz, ny, nx, 19))
+    for i in range(19):
+        f[..., i] = D3Q19_W[i] * (1.0 + amp * smooth_noise(rng, (nz, ny, nx)))
+    return f
 
 
 def random_populations(seed, nx, ny, nz, amp=0.02):

@@ -138,3 +138,27 @@ def test_degenerate_and_maximum_sizes_on_host():
     a = T.required_bytes([case, case], [body, None])
     b = T.required_bytes([case], [body])
     assert a[0] == 2 * b[0] and a[2] >= b[2]
+
+
+def test_d3q19_lattice_option():
+    """The D3Q19 comparison lattice: 19 planes per case, FP32 storage and
+    schedule 0 only, fluid-only, periodic z, no sponge."""
+    from paper_2408_15115_amd import turret as T
+    case = W.make_case(24, 20, 16, 0.6, W.BC_PERIODIC, W.BC_PERIODIC, 0)
+    a, b, _ = T.required_bytes([case], None, lattice=19)
+    assert a == b == 19 * 24 * 20 * 16 * 4
+    assert T.required_bytes([case], None)[0] == 27 * 24 * 20 * 16 * 4
+    bad = [({"storage": "f16"}, "FP32"), ({"schedule": 1}, "schedule 0"), ({"lattice": 21}, "lattice")]
+    for kw, needle in bad:
+        with pytest.raises(T.TurretError) as e:
+            T.required_bytes([case], None, **dict({"lattice": 19}, **kw))
+        assert needle in str(e.value)
+    for c in (dict(case, bc_zlo=W.BC_FREESLIP, bc_zhi=W.BC_FREESLIP), dict(case, sponge=2)):
+        with pytest.raises(T.TurretError) as e:
+            T.required_bytes([c], None, lattice=19)
+        assert "periodic z" in str(e.value)
+    sc, sb = W.case_sphere48()
+    sc = dict(sc, bc_zlo=W.BC_PERIODIC, bc_zhi=W.BC_PERIODIC)
+    with pytest.raises(T.TurretError) as e:
+        T.required_bytes([sc], [sb], lattice=19)
+    assert "fluid-only" in str(e.value)

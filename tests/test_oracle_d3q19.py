@@ -135,3 +135,26 @@ def test_taylor_green_viscosity(orc, collision):
     e64 = abs(tgv_viscosity19(orc, 64, tau, collision) / nu - 1)
     assert e64 < 2e-3
     assert e64 < e32 / 2.5       # second order in space
+
+
+def test_streaming_moves_each_population_along_its_velocity(orc, lat):
+    xi, _ = lat
+    nz, ny, nx = 5, 6, 7
+    f = np.zeros((nz, ny, nx, 19))
+    z, y, x = 0, 5, 3
+    f[z, y, x, :] = 1.0 + np.arange(19)
+    g = orc.stream19(f)
+    assert g.sum() == pytest.approx(f.sum())
+    for i in range(19):
+        t = ((z + xi[i, 2]) % nz, (y + xi[i, 1]) % ny, (x + xi[i, 0]) % nx)
+        assert g[t + (i,)] == 1.0 + i
+
+
+def test_grid_step_is_collide_then_stream(orc, lat):
+    _, w = lat
+    rng = np.random.default_rng(3)
+    f = w * (1.0 + 0.02 * rng.normal(size=(4, 5, 6, 19)))
+    for collision in (0, 1):
+        g = orc.stream19(orc.collide_grid19(f, 0.7, collision))
+        assert np.array_equal(g, orc.run19(f, 0.7, 1, collision))
+        assert np.array_equal(orc.collide_grid19(f, 0.7, collision)[2, 3, 1], orc.collide19(f[2, 3, 1], 0.7, collision))
