@@ -377,6 +377,88 @@ def settling_sweep(T, W, torch, diameters, re=5.0, offsets=(0.0, 3.0), domain="p
     return rows
 
 
+TABLE3_RE = (0.58, 1.39, 4.49, 6.18, 28.3, 127.88)
+
+
+def settling_table3(T, W, torch, D, res=TABLE3_RE, kappa=2.7):
+    """The terminal-velocity comparison of Table 3 (Sec. 3.2) at one
+    resolution: a sphere of diameter D cells settling from rest in the
+    paper's box (w* = 10, h* = 30, no-slip bottom, constant-pressure top;
+    h_ini* = 27 below Re 20 and 23 above, h_end* = 3, sponge 2.4 D), force on
+    the parallel surface 3 cells out, max(500 D, 8 drag-law relaxation
+    times, 3 Oseen times nu / v^2) steps: at low Re the history force
+    approaches the terminal speed as t^(-1/2) until the Oseen time, so the
+    speed is also extrapolated by a fit v = v_inf - c t^(-1/2) over the
+    second half of the run.  Per Re: the terminal speed over the Clift-Gauvin value
+    (the weight balanced by the drag law, solved by bisection) and, below
+    Re 1, over Stokes' law; the paper's own measure (the reference speed
+    from C_D at the simulated Re); the force balance Delta F = (F_g - F_D) / F_g;
+    and p*, the pressure share of the drag on that surface.  The density
+    ratio sets only the transient, so a light sphere (kappa 2.7) reaches the
+    same steady balance in fewer steps than the paper's 996."""
+    import numpy as np
+    rows = []
+    for re in res:
+        h_ini = 27.0 if re < 20 else 23.0
+        case, body, v_t = W.case_sphere_settling(float(D), re, kappa, force_offset=3.0, domain="paper",
+                                                 h_ini_d=h_ini, h_end_d=3.0, sponge_d=2.4)
+        nu, g = (case["tau"] - 0.5) / 3.0, case["gravity"]
+        t_relax = v_t / g * (kappa + 0.5) / kappa
+        chunk = 250
+        steps = int(max(500 * D, 8 * t_relax, 3 * nu / v_t ** 2)) // chunk * chunk + chunk
+        S = T.Solver([case], [body], stream=torch.cuda.Stream())
+        nch = steps // chunk
+        tail = max(8, nch // 4)
+        v, F, Fp, hist = [], [], [], []
+        t0 = time.perf_counter()
+        for k in range(nch):
+            S.run(chunk)
+            if k >= nch // 2:
+                st = S.body_state()
+                hist.append(((k + 1) * chunk, -st["v"][2]))
+                if k >= nch - tail:
+                    v.append(-st["v"][2])
+                    F.append(st["F"][2])
+                    Fp.append(st["F_pressure"][2])
+            if k % 16 == 15:
+                log(f"  Table 3, D {D}, Re {re}: step {(k + 1) * chunk} of {steps}, v_z {S.body_state()['v'][2]:.5f}")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        vol = float(body["volume"])
+        Fg = kappa * g * vol
+        area = math.pi * D * D / 4.0
+
+        def drag(u):
+            return 0.5 * W.clift_gauvin_cd(u * D / nu) * area * u * u
+
+        lo, hi = 1e-7, 1.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if drag(mid) < Fg else (lo, mid)
+        v_cg = 0.5 * (lo + hi)
+        vT = float(np.mean(v))
+        th = np.array(hist)
+        fit = np.polyfit(th[:, 0] ** -0.5, th[:, 1], 1)   # v = v_inf + slope t^(-1/2)
+        v_inf = float(fit[1])
+        re_sim = vT * D / nu
+        cd_sim = 24.0 / re_sim if re < 1 else W.clift_gauvin_cd(re_sim)
+        v_ref = math.sqrt(8.0 * Fg / (math.pi * D * D * cd_sim))
+        Fd = float(np.mean(F))
+        row = {"re_target": re, "D": D, "box": [case["nx"], case["ny"], case["nz"]], "tau": round(case["tau"], 5),
+               "steps": steps, "v_T_lattice": round(vT, 6), "re_simulated": round(re_sim, 3),
+               "vT_over_clift_gauvin": round(vT / v_cg, 4), "v_inf_over_clift_gauvin": round(v_inf / v_cg, 4),
+               "vT_over_stokes": round(vT / (Fg / (3.0 * math.pi * nu * D)), 4) if re < 1 else None,
+               "delta_vT_paper_measure": round((vT - v_ref) / vT, 4),
+               "delta_F": round((Fg - Fd) / Fg, 4), "p_star": round(float(np.mean(Fp)) / Fd, 4),
+               "drift": round(float(np.ptp(v)) / vT, 4), "mlups": round(case["nx"] * case["ny"] * case["nz"] * steps / dt / 1e6, 1)}
+        rows.append(row)
+        log(f"  {row}")
+    return rows
+
+
 def stability_run(T, W, torch, n=64, U0=0.1, steps=2000):
     """3-D Taylor-Green vortex (n^3, U0 = 0.1): the smallest relaxation time
     that runs `steps` steps without tripping the lattice kernel's guard, for
@@ -410,14 +492,15 @@ def stability_run(T, W, torch, n=64, U0=0.1, steps=2000):
 
 
 def lattice_rate_run(T, W, torch, n=(256, 256, 768), steps=20, warmup=3):
-    """Fluid-only periodic box, FP32 storage, recursive-regularized collision:
-    the lattice kernel alone on D3Q27 and on the D3Q19 comparison lattice;
-    GLUPS and the algorithmic bandwidth (q populations read and written)."""
-    import numpy as np
+    """Fluid-only periodic box, FP32, recursive-regularized collision: the
+    lattice kernel alone on D3Q27, on the D3Q19 comparison lattice, and on
+    D3Q27 with moment storage; GLUPS and the algorithmic bandwidth (the
+    stored values read and written: q populations, or 10 moments)."""
     nx, ny, nz = n
     out = {"workload": f"fluid-only periodic {nx}x{ny}x{nz}, FP32, recursive regularized, {steps} steps"}
-    for q in (27, 19):
-        S = T.Solver([W.make_case(nx, ny, nz, 0.6, W.BC_PERIODIC, W.BC_PERIODIC, 0)], lattice=q,
+    for name, q, storage, per_cell in (("d3q27", 27, "f32", 27), ("d3q19", 19, "f32", 19),
+                                       ("d3q27_moments", 27, "mom", 10)):
+        S = T.Solver([W.make_case(nx, ny, nz, 0.6, W.BC_PERIODIC, W.BC_PERIODIC, 0)], lattice=q, storage=storage,
                      stream=torch.cuda.Stream())
         for _ in range(warmup):
             S.lbm_step()
@@ -432,8 +515,8 @@ def lattice_rate_run(T, W, torch, n=(256, 256, 768), steps=20, warmup=3):
         err = S.body_state(0, check=False)["err"]
         S.close()
         cells = nx * ny * nz
-        out[f"d3q{q}"] = {"ms_per_step": round(ms, 4), "glups": round(cells / (ms * 1e-3) / 1e9, 2),
-                          "gbps": round(cells * q * 8 / (ms * 1e-3) / 1e9, 1), "err": int(err)}
+        out[name] = {"ms_per_step": round(ms, 4), "glups": round(cells / (ms * 1e-3) / 1e9, 2),
+                     "gbps": round(cells * per_cell * 8 / (ms * 1e-3) / 1e9, 1), "err": int(err)}
     torch.cuda.empty_cache()
     return out
 
@@ -477,6 +560,8 @@ def main():
     ap.add_argument("--settling-sweep", type=str, default=None,
                     help="comma-separated sphere diameters: run only the terminal-velocity resolution sweep")
     ap.add_argument("--no-stability", action="store_true")
+    ap.add_argument("--table3", type=str, default=None,
+                    help="D[:Re1,Re2,...]: run only the terminal-velocity comparison of Table 3 at diameter D cells")
     ap.add_argument("--coupling", default="auto", choices=["auto", "serial", "beside"],
                     help="where the coupling runs: chosen by timing both (auto), after the lattice kernel, or "
                          "beside it on a second stream")
@@ -493,6 +578,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.table3:
+        d, _, rl = args.table3.partition(":")
+        res = [float(r) for r in rl.split(",")] if rl else TABLE3_RE
+        rows = settling_table3(T, W, torch, int(d), res)
+        print(json.dumps({"metric": "sphere terminal velocity against Clift-Gauvin / Stokes across Re (Table 3)",
+                          "data": "synthetic", "rows": rows}))
+        return
     if args.settling_sweep:
         rows = settling_sweep(T, W, torch, [int(d) for d in args.settling_sweep.split(",")])
         print(json.dumps({"metric": "sphere terminal velocity / Clift-Gauvin against resolution",
@@ -617,7 +709,8 @@ def main():
     if not args.no_variants and not args.no_stability:
         lr19 = lattice_rate_run(T, W, torch)
         variants["lattice_rate"] = lr19
-        log(f"  fluid-only lattice kernel: D3Q27 {lr19['d3q27']}, D3Q19 {lr19['d3q19']}")
+        log(f"  fluid-only lattice kernel: D3Q27 {lr19['d3q27']}, D3Q19 {lr19['d3q19']}, "
+            f"D3Q27 moment storage {lr19['d3q27_moments']}")
 
     cpu = None
     if not args.no_cpu_baseline:

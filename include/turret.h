@@ -45,7 +45,7 @@ enum {
     LBM_ESTATE = -5      /* call out of order (see the step sequence below) */
 };
 
-enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 };                   /* population storage */
+enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2, LBM_MOM = 3 };      /* population storage */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_FREESLIP = 1, LBM_BC_NOSLIP = 2, LBM_BC_PRESSURE = 3 }; /* z walls */
 
 /* One settling case (Sec. 2.5 and Table 2).
@@ -109,7 +109,20 @@ typedef struct {
 } lbm_body;
 
 /* Options.
- *   storage     LBM_F32, LBM_F16 or LBM_BF16
+ *   storage     LBM_F32, LBM_F16 or LBM_BF16: the 27 populations as deviations
+ *               from the weights, in that precision;
+ *               LBM_MOM: moment storage.  The recursive-regularized
+ *               post-collision state of a cell depends only on rho, u and the
+ *               off-equilibrium stress P1 (App. A), so each cell stores ten
+ *               FP32 numbers instead of 27 populations: rho - 1, rho u and
+ *               (1 - 1/tau) P1 (xx, yy, zz, xy, xz, yz), layout
+ *               [10][nz][ny][nx] per case.  The step reconstructs the
+ *               populations it pulls and gives the same result as LBM_F32 up to
+ *               rounding.  Fluid-only cases with periodic z, lattice 27,
+ *               collision 0 and schedule 0 only.  lbm_get_populations returns
+ *               the reconstructed populations; lbm_set_populations keeps the
+ *               regularized part of what it is given (exact for a
+ *               post-collision state of this collision)
  *   ibm_cycles  multi-direct forcing cycles n (the paper uses 4), 1..16
  *               (0 = default 4)
  *   block       threads per block of the lattice kernel, which is also the

@@ -23,7 +23,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-int elem_bytes(int storage) { return storage == LBM_F32 ? 4 : 2; }
+int elem_bytes(int storage) { return (storage == LBM_F32 || storage == LBM_MOM) ? 4 : 2; }
 
 struct Plan {
     std::vector<CaseDev> cd;
@@ -34,6 +34,7 @@ struct Plan {
     int Mtot = 0, maxL3 = 0, max_slab = 0;
     int force_surface = 0;    // some case evaluates its force on the parallel surface
     int q = 27;               // populations per cell: 27, or 19 for the D3Q19 comparison lattice
+    int planes = 27;          // stored planes per case: q, or 10 with moment storage
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
         off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox,
@@ -86,7 +87,7 @@ std::string check_case(const lbm_case &c, const lbm_body *b)
 std::string check_options(const lbm_options *o)
 {
     if (!o) return "";
-    if (o->storage < LBM_F32 || o->storage > LBM_BF16) return "unknown storage";
+    if (o->storage < LBM_F32 || o->storage > LBM_MOM) return "unknown storage";
     if (o->ibm_cycles < 0 || o->ibm_cycles > 16) return "ibm_cycles must be 1..16 (0 = default 4)";
     if (o->block && o->block != 64 && o->block != 128 && o->block != 256) return "block must be 64, 128 or 256";
     if (o->schedule < 0 || o->schedule > 3) return "schedule must be 0..3";
@@ -123,6 +124,17 @@ void build_tiles(Plan &P, int block, int order)
     } else {
         for (int c : ord)
             for (int t = 0; t < nt[c]; t++) P.tiles.push_back(tile(c, t));
+    }
+}
+
+// Tile table of the moment-storage step: one entry per column tile and z
+// chunk of each case, `first` holding the tile's index inside its case.
+void build_moment_tiles(Plan &P)
+{
+    P.tiles.clear();
+    for (int c = 0; c < (int)P.cd.size(); c++) {
+        const int nt = moment_tiles(P.cd[c].nx, P.cd[c].ny, P.cd[c].nz);
+        for (int t = 0; t < nt; t++) P.tiles.push_back(Tile{c, t});
     }
 }
 
@@ -184,6 +196,13 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         if (opt->storage != LBM_F32) return "the D3Q19 lattice runs with FP32 storage";
         if (opt->schedule != 0) return "the D3Q19 lattice runs with schedule 0";
     }
+    const bool mom = opt && opt->storage == LBM_MOM;
+    if (mom) {
+        if (P.q != 27) return "moment storage is a D3Q27 form";
+        if (opt->collision != 0) return "moment storage holds regularized states only (collision 0)";
+        if (opt->schedule != 0) return "moment storage runs with schedule 0";
+    }
+    P.planes = mom ? 10 : P.q;
     P.cd.assign(n, CaseDev{});
     long long pop = 0, reg = 0;
     int moff = 0;
@@ -196,6 +215,11 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
             if (b && b->n_markers > 0) return "case " + std::to_string(c) + ": the D3Q19 lattice is fluid-only (no markers)";
             if (k.bc_zlo != LBM_BC_PERIODIC || k.bc_zhi != LBM_BC_PERIODIC || k.sponge_cells != 0)
                 return "case " + std::to_string(c) + ": the D3Q19 lattice needs periodic z and no sponge";
+        }
+        if (mom) {
+            if (b && b->n_markers > 0) return "case " + std::to_string(c) + ": moment storage is fluid-only (no markers)";
+            if (k.bc_zlo != LBM_BC_PERIODIC || k.bc_zhi != LBM_BC_PERIODIC)
+                return "case " + std::to_string(c) + ": moment storage needs periodic z";
         }
         CaseDev &d = P.cd[c];
         d.nx = k.nx;
@@ -213,7 +237,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         d.cells = (long long)k.nx * k.ny * k.nz;
         d.plane = (d.cells + 127) / 128 * 128;   // 256-byte aligned direction planes
         d.pop_off = pop;
-        pop += P.q * d.plane;
+        pop += P.planes * d.plane;
         d.M = b ? std::max(0, b->n_markers) : 0;
         d.force_offset = (b && d.M > 0) ? b->force_offset : 0.0;
         if (d.force_offset > 0.0) P.force_surface = 1;
@@ -239,7 +263,10 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         if (d.M > 0) P.max_slab = std::max(P.max_slab, d.dz * k.nx * k.ny);
         P.max_tiles += (d.cells + 63) / 64;
     }
-    build_tiles(P, P.block, opt ? opt->tile_order : 0);
+    if (mom)
+        build_moment_tiles(P);
+    else
+        build_tiles(P, P.block, opt ? opt->tile_order : 0);
     P.pop_elems = pop;
     P.reg_cells = reg;
     P.Mtot = moff;
@@ -512,7 +539,10 @@ static int32_t do_lbm_step(lbm_ctx *ctx)
 {
     const int src = ctx->cur, dst = 1 - ctx->cur;
     if (ctx->has_body) HIPCHK(ctx, hipEventRecord(ctx->fork, ctx->stream), "record fork event");
-    if (ctx->plan.q == 19)
+    if (ctx->opt.storage == LBM_MOM)
+        HIPCHK(ctx, launch_moment_step(ctx->pop[src], ctx->pop[dst], ctx->p, (int)ctx->plan.tiles.size(), ctx->stream),
+               "lbm_step");
+    else if (ctx->plan.q == 19)
         HIPCHK(ctx,
                launch_stream_collide19(ctx->pop[src], ctx->pop[dst], ctx->p, (int)ctx->plan.tiles.size(),
                                        ctx->opt.block, ctx->opt.collision, ctx->stream),
@@ -616,12 +646,17 @@ int32_t lbm_set_schedule(lbm_ctx *ctx, const lbm_options *opt)
         (opt->lattice == 19) != (ctx->plan.q == 19))
         return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage, ibm_cycles, forcing or lattice");
     if (ctx->plan.q == 19 && opt->schedule != 0) return fail(ctx, LBM_EINVAL, "the D3Q19 lattice runs with schedule 0");
+    if (ctx->opt.storage == LBM_MOM && (opt->schedule != 0 || opt->collision != 0))
+        return fail(ctx, LBM_EINVAL, "moment storage runs with schedule 0 and collision 0");
     if (opt->serial_ibm != ctx->opt.serial_ibm || opt->collision != ctx->opt.collision) drop_graph(ctx);
     ctx->opt.serial_ibm = opt->serial_ibm;
     ctx->opt.collision = opt->collision;
     if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "lbm_set_schedule between lbm_step and ibm_couple");
     const int block = opt->block ? opt->block : 256;
-    build_tiles(ctx->plan, block, opt->tile_order);
+    if (ctx->opt.storage == LBM_MOM)
+        build_moment_tiles(ctx->plan);
+    else
+        build_tiles(ctx->plan, block, opt->tile_order);
     ctx->plan.block = block;
     HIPCHK(ctx, hipMemcpyAsync(ctx->p.tiles, ctx->plan.tiles.data(), sizeof(Tile) * ctx->plan.tiles.size(),
                                hipMemcpyHostToDevice, ctx->stream), "upload tile table");
@@ -741,19 +776,31 @@ int32_t lbm_get_populations(lbm_ctx *ctx, int32_t c, double *out)
     int32_t r = read_body(ctx, c, B);
     if (r) return r;
     const CaseDev &d = ctx->plan.cd[c];
-    const int eb = elem_bytes(ctx->opt.storage);
+    const bool mom = ctx->opt.storage == LBM_MOM;
+    const int st = mom ? LBM_F32 : ctx->opt.storage;
+    const int eb = elem_bytes(st);
     const int q = ctx->plan.q;
     std::vector<char> raw((size_t)q * d.plane * eb);
     const char *src = (const char *)ctx->pop[ctx->cur] + (size_t)d.pop_off * eb;
-    HIPCHK(ctx, hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, ctx->stream), "copy populations");
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    if (mom) {   // reconstruct the populations on the device
+        float *tmp = nullptr;
+        HIPCHK(ctx, hipMalloc(&tmp, raw.size()), "allocate population buffer");
+        hipError_t he = launch_moments_expand((const float *)src, tmp, d.plane, d.cells, ctx->stream);
+        if (he == hipSuccess) he = hipMemcpyAsync(raw.data(), tmp, raw.size(), hipMemcpyDeviceToHost, ctx->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+        (void)hipFree(tmp);
+        HIPCHK(ctx, he, "reconstruct populations");
+    } else {
+        HIPCHK(ctx, hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, ctx->stream), "copy populations");
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    }
     const size_t slab = (size_t)d.nx * d.ny;
     for (int i = 0; i < q; i++)
         for (int z = 0; z < d.nz; z++) {
             const int zc = (z + B.z0) % d.nz;
             for (size_t k = 0; k < slab; k++)
                 out[((size_t)i * d.nz + z) * slab + k] =
-                    lattice_weight(q, i) + (double)host_dec(ctx->opt.storage, raw.data(), (size_t)i * d.plane + zc * slab + k, i);
+                    lattice_weight(q, i) + (double)host_dec(st, raw.data(), (size_t)i * d.plane + zc * slab + k, i);
         }
     return B.err ? fail(ctx, LBM_EUNSTABLE, "unstable: marker stencil left the box or non-finite IBM value") : LBM_OK;
 }
@@ -766,7 +813,9 @@ int32_t lbm_set_populations(lbm_ctx *ctx, int32_t c, const double *in)
     int32_t r = read_body(ctx, c, B);
     if (r) return r;
     const CaseDev &d = ctx->plan.cd[c];
-    const int eb = elem_bytes(ctx->opt.storage);
+    const bool mom = ctx->opt.storage == LBM_MOM;
+    const int st = mom ? LBM_F32 : ctx->opt.storage;
+    const int eb = elem_bytes(st);
     const int q = ctx->plan.q;
     std::vector<char> raw((size_t)q * d.plane * eb);
     const size_t slab = (size_t)d.nx * d.ny;
@@ -774,12 +823,22 @@ int32_t lbm_set_populations(lbm_ctx *ctx, int32_t c, const double *in)
         for (int z = 0; z < d.nz; z++) {
             const int zc = (z + B.z0) % d.nz;
             for (size_t k = 0; k < slab; k++)
-                host_enc(ctx->opt.storage, raw.data(), (size_t)i * d.plane + zc * slab + k, i,
+                host_enc(st, raw.data(), (size_t)i * d.plane + zc * slab + k, i,
                          (float)(in[((size_t)i * d.nz + z) * slab + k] - lattice_weight(q, i)));
         }
     char *dst = (char *)ctx->pop[ctx->cur] + (size_t)d.pop_off * eb;
-    HIPCHK(ctx, hipMemcpyAsync(dst, raw.data(), raw.size(), hipMemcpyHostToDevice, ctx->stream), "copy populations");
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    if (mom) {   // project onto the stored moments on the device
+        float *tmp = nullptr;
+        HIPCHK(ctx, hipMalloc(&tmp, raw.size()), "allocate population buffer");
+        hipError_t he = hipMemcpyAsync(tmp, raw.data(), raw.size(), hipMemcpyHostToDevice, ctx->stream);
+        if (he == hipSuccess) he = launch_moments_project(tmp, (float *)dst, d.plane, d.cells, ctx->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+        (void)hipFree(tmp);
+        HIPCHK(ctx, he, "project populations");
+    } else {
+        HIPCHK(ctx, hipMemcpyAsync(dst, raw.data(), raw.size(), hipMemcpyHostToDevice, ctx->stream), "copy populations");
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    }
     return LBM_OK;
 }
 

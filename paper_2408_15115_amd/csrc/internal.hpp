@@ -119,6 +119,13 @@ hipError_t launch_stream_collide(int storage, const void *src, void *dst, const 
 // The D3Q19 comparison lattice (fluid only, FP32, periodic, plain schedule).
 hipError_t launch_stream_collide19(const void *src, void *dst, const DevPtrs &p, int ntiles, int block,
                                    int collision, hipStream_t s);
+// Moment storage (fluid only, FP32, periodic): the z-marching step over the
+// moment tile table, and per-case conversions between moments and
+// population deviations ([10][plane] <-> [27][plane]).
+int moment_tiles(int nx, int ny, int nz);
+hipError_t launch_moment_step(const void *src, void *dst, const DevPtrs &p, int ntiles, hipStream_t s);
+hipError_t launch_moments_expand(const float *src, float *dst, long long plane, long long cells, hipStream_t s);
+hipError_t launch_moments_project(const float *src, float *dst, long long plane, long long cells, hipStream_t s);
 hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
 // IBM coupling.  With a warm start (warm_mode 1: the previous step's final
 // h_k; 2: the network th16) cycles run from that start until a case's

@@ -17,11 +17,11 @@ LIB_PATH = os.path.join(HERE, "libturret.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "turret.h")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
-LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
+LBM_F32, LBM_F16, LBM_BF16, LBM_MOM = 0, 1, 2, 3
 LBM_WARM_NONE, LBM_WARM_PREVIOUS, LBM_WARM_MLP = 0, 1, 2
 MLP_PARAMS = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
-STORAGE = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
-ELEM_BYTES = {LBM_F32: 4, LBM_F16: 2, LBM_BF16: 2}
+STORAGE = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16, "mom": LBM_MOM}
+ELEM_BYTES = {LBM_F32: 4, LBM_F16: 2, LBM_BF16: 2, LBM_MOM: 4}
 ERRNAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE", -5: "LBM_ESTATE"}
 
 

@@ -162,3 +162,28 @@ def test_d3q19_lattice_option():
     with pytest.raises(T.TurretError) as e:
         T.required_bytes([sc], [sb], lattice=19)
     assert "fluid-only" in str(e.value)
+
+
+def test_moment_storage_option():
+    """Moment storage: 10 FP32 planes per case; D3Q27 regularized,
+    fluid-only, periodic z, schedule 0 only."""
+    from paper_2408_15115_amd import turret as T
+    case = W.make_case(24, 20, 40, 0.6, W.BC_PERIODIC, W.BC_PERIODIC, 0)
+    cells = 24 * 20 * 40
+    plane = (cells + 127) // 128 * 128
+    a, b, _ = T.required_bytes([case], None, storage="mom")
+    assert a == b == 10 * plane * 4
+    T.required_bytes([dict(case, sponge=6)], None, storage="mom")
+    bad = [({"collision": 1}, "collision 0"), ({"schedule": 2}, "schedule 0"), ({"lattice": 19}, "FP32")]
+    for kw, needle in bad:
+        with pytest.raises(T.TurretError) as e:
+            T.required_bytes([case], None, **dict({"storage": "mom"}, **kw))
+        assert needle in str(e.value)
+    with pytest.raises(T.TurretError) as e:
+        T.required_bytes([dict(case, bc_zlo=W.BC_NOSLIP, bc_zhi=W.BC_PRESSURE)], None, storage="mom")
+    assert "periodic z" in str(e.value)
+    sc, sb = W.case_sphere48()
+    sc = dict(sc, bc_zlo=W.BC_PERIODIC, bc_zhi=W.BC_PERIODIC)
+    with pytest.raises(T.TurretError) as e:
+        T.required_bytes([sc], [sb], storage="mom")
+    assert "fluid-only" in str(e.value)
