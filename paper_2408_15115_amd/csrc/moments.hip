@@ -20,9 +20,14 @@
 namespace turret {
 
 namespace mom {
-constexpr int MX = 16, MY = 12, LZ = 32;
-constexpr int HX = MX + 2, HY = MY + 2, NH = HX * HY;   // 252 halo cells <= 256 threads
-constexpr int kBlock = 256;
+#ifndef TURRET_MOM_TILE
+#define TURRET_MOM_TILE 32, 5, 32, 256
+#endif
+// x, y extent of a column tile; z planes per chunk; threads per workgroup
+constexpr int kTile[4] = {TURRET_MOM_TILE};
+constexpr int MX = kTile[0], MY = kTile[1], LZ = kTile[2];
+constexpr int HX = MX + 2, HY = MY + 2, NH = HX * HY;   // halo cells, one per thread
+constexpr int kBlock = kTile[3];
 static_assert(NH <= kBlock && MX * MY <= kBlock, "tile does not fit the workgroup");
 
 __device__ __forceinline__ int wrap1(int v, int n)

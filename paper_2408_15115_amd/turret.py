@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libturret.so")
+LIB_PATH = os.environ.get("TURRET_LIB") or os.path.join(HERE, "libturret.so")   # TURRET_LIB: another build
 HEADER = os.path.join(os.path.dirname(HERE), "include", "turret.h")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5

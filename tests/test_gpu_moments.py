@@ -50,7 +50,7 @@ def run_pair(T, orc, nx, ny, nz, tau, sponge, steps, seed, amp=0.05):
 
 
 CASES = [
-    # nx, ny, nz, tau, sponge: tiles are 16 x 12 cells, z chunks 32 planes
+    # nx, ny, nz, tau, sponge: tiles are 32 x 5 cells, z chunks 32 planes
     (8, 9, 10, 0.6, 0),
     (20, 14, 40, 0.8, 0),
     (33, 25, 70, 0.51, 0),
@@ -81,8 +81,8 @@ def test_round_trip_of_a_regularized_state(T, orc):
     assert max_rel(back, oracle_to_soa(C0)) < 1e-6
 
 
-def test_matches_population_storage(T, orc):
-    nx, ny, nz, tau = 33, 25, 70, 0.55
+@pytest.mark.parametrize("nx,ny,nz,tau", [(33, 25, 70, 0.55), (96, 40, 100, 0.52)])
+def test_matches_population_storage(T, orc, nx, ny, nz, tau):
     case = W.make_case(nx, ny, nz, tau, W.BC_PERIODIC, W.BC_PERIODIC, 0)
     C0 = oracle_to_soa(regularized_state(orc, 5, nx, ny, nz, tau, 0, 0.03))
     out = []
