@@ -61,7 +61,13 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_FREESLIP = 1, LBM_BC_NOSLIP = 2, LBM_BC_PRESS
  *   gravity         magnitude of g along -z
  *   h_ini, h_end    falling-frame window (Sec. 2.5): when the body centre
  *                   drops below h_end, the whole content moves up by
- *                   round(h_ini - h_end) rows; h_end <= 0 disables it */
+ *                   round(h_ini - h_end) rows; h_end <= 0 disables it
+ *   u_wall          x velocity of the bottom and top wall, |u| <= 0.2; non-zero
+ *                   only on a no-slip wall, which then moves in its own plane
+ *                   (the shear flow of the rotation case of Sec. 3.1):
+ *                   bounce-back adds the wall's momentum,
+ *                   f_i = C_opp(i) + 6 w_i (xi_i . u_wall) at density 1.
+ *                   Zero for a resting wall (the settling cases) */
 typedef struct {
     int32_t nx, ny, nz;
     int32_t bc_zlo, bc_zhi;
@@ -69,6 +75,7 @@ typedef struct {
     double tau;
     double gravity;
     double h_ini, h_end;
+    double u_wall[2];
 } lbm_case;
 
 /* The rigid particle of a case (Sec. 2.2 markers, Sec. 2.3 body).

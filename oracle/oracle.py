@@ -68,6 +68,8 @@ def lib():
         L.orc_collide_grid_v.argtypes = [pi, d, i32, i32, pd, pd, pd]
         L.orc_collide_grid_m.argtypes = [pi, d, i32, i32, i32, pd, pd, pd]
         L.orc_stream_grid.argtypes = [pi, i32, i32, pd, pd]
+        L.orc_stream_grid_w.argtypes = [pi, i32, i32, pd, pd, pd]
+        L.orc_sim_set_walls.argtypes = [C.c_void_p, pd]
         L.orc_interp.argtypes = [pi, pd, i32, i32, pd, pd]
         L.orc_interp.restype = i32
         L.orc_spread.argtypes = [pi, i32, pd, pd, pd, pd]
@@ -182,12 +184,15 @@ def collide_grid(f, tau0, sponge=0, h=None, forcing=0, collision=0):
     return out
 
 
-def stream_grid(C_, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC):
+def stream_grid(C_, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, u_wall=(0.0, 0.0)):
+    """Pull-streaming with the z wall rules; u_wall = x velocities of no-slip
+    bottom and top walls."""
     C_ = _f64(C_)
     nz, ny, nx, _ = C_.shape
     dims = np.array([nx, ny, nz], np.int32)
     out = np.zeros_like(C_)
-    lib().orc_stream_grid(_pi(dims), int(bc_lo), int(bc_hi), _pd(C_), _pd(out))
+    uw = _f64(u_wall)
+    lib().orc_stream_grid_w(_pi(dims), int(bc_lo), int(bc_hi), _pd(uw), _pd(C_), _pd(out))
     return out
 
 
@@ -310,6 +315,10 @@ class OracleSim:
         self.M = M
         self._keep = (dims, ip, dp, xb, nb, dS, bp)
         self._p = L.orc_sim_new(_pi(dims), _pi(ip), _pd(dp), M, _pd(xb), _pd(nb), _pd(dS), _pd(bp))
+        if case.get("u_wall_lo", 0.0) != 0.0 or case.get("u_wall_hi", 0.0) != 0.0:
+            uw = _f64([case.get("u_wall_lo", 0.0), case.get("u_wall_hi", 0.0)])
+            self._keep = self._keep + (uw,)
+            L.orc_sim_set_walls(self._p, _pd(uw))
         if body is not None and body.get("torque") is not None:
             tq = _f64(body["torque"])
             self._keep = self._keep + (tq,)

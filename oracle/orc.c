@@ -321,6 +321,7 @@ typedef struct {
     int bc_lo, bc_hi, sponge;
     int forcing;    /* 0: forced rule as printed; 1: momentum-exact variant */
     int collision;  /* 0: recursive regularized (the paper's); 1: BGK */
+    double uw_lo, uw_hi;   /* x velocity of a no-slip bottom / top wall */
 } dom_t;
 
 /* Relaxation time at height z.  Sponge reading (Sec. 2.5): tau rises linearly
@@ -364,7 +365,9 @@ static void collide_grid(const dom_t *D, const double *f, const double *h, doubl
  * periodic, free-slip (specular reflection, xi_z flipped), no-slip
  * (bounce-back, whole xi reversed) or constant pressure (the Sec. 3 domain
  * top, density rho0 = 1 at the halfway plane; reading: anti-bounce-back
- * f_i = -C_opp(i) + 2 w_i rho0, the O(u^2) wall-velocity terms dropped). */
+ * f_i = -C_opp(i) + 2 w_i rho0, the O(u^2) wall-velocity terms dropped).
+ * A no-slip wall moving in x at u_w (the shear flow of the rotation case):
+ * bounce-back plus the wall's momentum, f_i = C_opp(i) + 2 w_i rho0 xi_i.u_w / cs^2. */
 static void stream_grid(const dom_t *D, const double *C, double *f)
 {
     #pragma omp parallel for schedule(static)
@@ -387,7 +390,8 @@ static void stream_grid(const dom_t *D, const double *C, double *f)
                     } else if (bc == BC_PRESSURE) {
                         f[Q * c + i] = -C[Q * c + (Q - 1 - i)] + 2.0 * g_w[i] * RHO0;
                     } else {
-                        f[Q * c + i] = C[Q * c + (Q - 1 - i)];
+                        const double uw = sz < 0 ? D->uw_lo : D->uw_hi;
+                        f[Q * c + i] = C[Q * c + (Q - 1 - i)] + 2.0 * g_w[i] * RHO0 * g_xi[i][0] * uw / CS2;
                     }
                 }
             }
@@ -417,6 +421,16 @@ void orc_stream_grid(const int32_t *dims, int32_t bc_lo, int32_t bc_hi, const do
 {
     orc_init();
     dom_t D = {dims[0], dims[1], dims[2], 1.0, bc_lo, bc_hi, 0};
+    stream_grid(&D, C, f);
+}
+
+/* The same with no-slip walls moving in x at uw[0] (bottom) and uw[1] (top). */
+void orc_stream_grid_w(const int32_t *dims, int32_t bc_lo, int32_t bc_hi, const double *uw, const double *C, double *f)
+{
+    orc_init();
+    dom_t D = {dims[0], dims[1], dims[2], 1.0, bc_lo, bc_hi, 0};
+    D.uw_lo = uw[0];
+    D.uw_hi = uw[1];
     stream_grid(&D, C, f);
 }
 
@@ -668,6 +682,13 @@ orc_sim *orc_sim_new(const int32_t *dims, const int32_t *ip, const double *dp, i
 void orc_sim_set_torque(orc_sim *S, const double *T)
 {
     for (int a = 0; a < 3; a++) S->B.Text[a] = T[a];
+}
+
+/* x velocities of the bottom and top walls (no-slip walls only). */
+void orc_sim_set_walls(orc_sim *S, const double *uw)
+{
+    S->D.uw_lo = uw[0];
+    S->D.uw_hi = uw[1];
 }
 
 void orc_sim_set_force_surface(orc_sim *S, double delta, const double *dSo)

@@ -53,6 +53,11 @@ std::string check_case(const lbm_case &c, const lbm_body *b)
         if (bc < LBM_BC_PERIODIC || bc > LBM_BC_PRESSURE) return "unknown z boundary code";
     if ((c.bc_zlo == LBM_BC_PERIODIC) != (c.bc_zhi == LBM_BC_PERIODIC)) return "periodic z needs both walls periodic";
     if (c.h_end > 0.0 && std::lround(c.h_ini - c.h_end) >= c.nz) return "window shift exceeds the box height";
+    for (int w = 0; w < 2; w++) {
+        if (!(std::fabs(c.u_wall[w]) <= 0.2)) return "u_wall must be finite with |u_wall| <= 0.2";
+        if (c.u_wall[w] != 0.0 && (w == 0 ? c.bc_zlo : c.bc_zhi) != LBM_BC_NOSLIP)
+            return "a moving wall (u_wall != 0) must be a no-slip wall";
+    }
     if (b && b->n_markers > 0) {
         if (!b->x_body || !b->n_body || !b->dS) return "marker arrays must not be NULL";
         if (!(b->kappa > 0) || !(b->volume > 0)) return "kappa and volume must be > 0";
@@ -240,6 +245,8 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         pop += P.planes * d.plane;
         d.M = b ? std::max(0, b->n_markers) : 0;
         d.force_offset = (b && d.M > 0) ? b->force_offset : 0.0;
+        d.uw_lo = (float)k.u_wall[0];
+        d.uw_hi = (float)k.u_wall[1];
         if (d.force_offset > 0.0) P.force_surface = 1;
         d.marker_off = moff;
         d.tile_off = (int)P.mtiles.size();

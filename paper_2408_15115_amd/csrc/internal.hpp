@@ -22,6 +22,7 @@ struct CaseDev {
     int forcing;            // 0: forced rule as printed; 1: momentum-exact variant
     double h_ini, h_end;
     double force_offset;    // 0: stress integral at the markers; > 0: on the parallel surface
+    float uw_lo, uw_hi;     // x velocity of a no-slip bottom / top wall
 };
 
 // Dynamic FP64 rigid-body state of one case plus the ring origin and region

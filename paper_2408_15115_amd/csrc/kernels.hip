@@ -161,7 +161,8 @@ __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs 
     }
     const int gx = wrapi(B.org[0] + a, cd.nx), gy = wrapi(B.org[1] + b, cd.ny);
     float g[Q];
-    pull<CD>(src + cd.pop_off, cd.plane, cd.nx, cd.ny, cd.nz, B.z0, cd.bc_lo, cd.bc_hi, gx, gy, gz, g);
+    pull<CD>(src + cd.pop_off, cd.plane, cd.nx, cd.ny, cd.nz, B.z0, cd.bc_lo, cd.bc_hi, cd.uw_lo, cd.uw_hi, gx, gy, gz,
+             g);
     const Macro M = macro(raw_moments(g));
     const float tau = tau_at(cd.tau0, cd.nz, cd.sponge, gz);
     const float fac = 0.5f / tau - 1.0f;

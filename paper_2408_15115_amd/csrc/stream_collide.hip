@@ -40,7 +40,7 @@ __device__ __forceinline__ void stream_collide_tile(const typename CD::T *__rest
     const int y = t2 % ny;
     const int z = t2 / ny;
     float g[Q];
-    pull<CD>(src + cd.pop_off, cd.plane, nx, ny, nz, z0, cd.bc_lo, cd.bc_hi, x, y, z, g);
+    pull<CD>(src + cd.pop_off, cd.plane, nx, ny, nz, z0, cd.bc_lo, cd.bc_hi, cd.uw_lo, cd.uw_hi, x, y, z, g);
     const Macro M = macro(raw_moments(g));
     const float u2 = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
     const bool bad = !(fabsf(M.r1) < 1.0f) || !(u2 < 0.25f);

@@ -28,7 +28,8 @@ ERRNAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4:
 class lbm_case(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc_zlo", C.c_int32),
                 ("bc_zhi", C.c_int32), ("sponge_cells", C.c_int32), ("tau", C.c_double),
-                ("gravity", C.c_double), ("h_ini", C.c_double), ("h_end", C.c_double)]
+                ("gravity", C.c_double), ("h_ini", C.c_double), ("h_end", C.c_double),
+                ("u_wall", C.c_double * 2)]
 
 
 class lbm_body(C.Structure):
@@ -115,9 +116,11 @@ def _dptr(a):
 
 
 def make_case(d: dict) -> lbm_case:
-    return lbm_case(int(d["nx"]), int(d["ny"]), int(d["nz"]), int(d.get("bc_zlo", 0)), int(d.get("bc_zhi", 0)),
-                    int(d.get("sponge", 0)), float(d["tau"]), float(d.get("gravity", 0.0)),
-                    float(d.get("h_ini", 0.0)), float(d.get("h_end", 0.0)))
+    c = lbm_case(int(d["nx"]), int(d["ny"]), int(d["nz"]), int(d.get("bc_zlo", 0)), int(d.get("bc_zhi", 0)),
+                 int(d.get("sponge", 0)), float(d["tau"]), float(d.get("gravity", 0.0)),
+                 float(d.get("h_ini", 0.0)), float(d.get("h_end", 0.0)))
+    c.u_wall[0], c.u_wall[1] = float(d.get("u_wall_lo", 0.0)), float(d.get("u_wall_hi", 0.0))
+    return c
 
 
 def make_body(d: dict | None, keep: list) -> lbm_body:

@@ -236,10 +236,11 @@ def lattice_scaling(d_eq, re, kappa, v_t=V_TERMINAL_LU):
 
 # ---------------------------------------------------------------- cases
 def make_case(nx, ny, nz, tau, bc_zlo=BC_FREESLIP, bc_zhi=BC_FREESLIP, sponge=0, gravity=0.0,
-              h_ini=0.0, h_end=0.0, ibm_cycles=4):
+              h_ini=0.0, h_end=0.0, ibm_cycles=4, u_wall=(0.0, 0.0)):
     return {"nx": int(nx), "ny": int(ny), "nz": int(nz), "tau": float(tau), "bc_zlo": int(bc_zlo),
             "bc_zhi": int(bc_zhi), "sponge": int(sponge), "gravity": float(gravity),
-            "h_ini": float(h_ini), "h_end": float(h_end), "ibm_cycles": int(ibm_cycles)}
+            "h_ini": float(h_ini), "h_end": float(h_end), "ibm_cycles": int(ibm_cycles),
+            "u_wall_lo": float(u_wall[0]), "u_wall_hi": float(u_wall[1])}
 
 
 def case_sphere48(n=48, markers=400, R=4.0, tau=0.6, kappa=2.0, gravity=1e-5):
@@ -382,6 +383,18 @@ def taylor_green_populations(n, U0):
     xu = u @ xi.T
     uu = (u * u).sum(-1, keepdims=True)
     return D3Q27_W * (1.0 + 3.0 * xu + 4.5 * xu * xu - 1.5 * uu)
+
+
+def couette_populations(nx, ny, nz, U):
+    """Plane Couette flow between no-slip walls halfway outside the first and
+    last rows moving at -U and +U in x: u_x(z) = U (2 (z + 1/2) / nz - 1),
+    density 1, populations from the second-order Maxwellian expansion.
+    Layout (27, nz, ny, nx)."""
+    ux = U * (2.0 * (np.arange(nz) + 0.5) / nz - 1.0)
+    xi_x = np.array([i % 3 - 1 for i in range(27)], np.float64)
+    f = D3Q27_W[:, None] * (1.0 + 3.0 * xi_x[:, None] * ux[None, :] + 4.5 * (xi_x[:, None] * ux[None, :]) ** 2
+                            - 1.5 * ux[None, :] ** 2)
+    return np.ascontiguousarray(np.broadcast_to(f[:, :, None, None], (27, nz, ny, nx)))
 
 
 def taylor_green_populations19(n, U0):

@@ -187,3 +187,14 @@ def test_moment_storage_option():
     with pytest.raises(T.TurretError) as e:
         T.required_bytes([sc], [sb], storage="mom")
     assert "fluid-only" in str(e.value)
+
+
+def test_moving_wall_checks():
+    from paper_2408_15115_amd import turret as T
+    case = W.make_case(16, 16, 16, 0.7, W.BC_NOSLIP, W.BC_NOSLIP, 0, u_wall=(-0.05, 0.05))
+    T.required_bytes([case], None)
+    for bad, needle in ((dict(case, bc_zhi=W.BC_FREESLIP), "no-slip"), (dict(case, u_wall_lo=0.3), "0.2"),
+                        (dict(case, u_wall_hi=float("nan")), "finite")):
+        with pytest.raises(T.TurretError) as e:
+            T.required_bytes([bad], None)
+        assert needle in str(e.value)

@@ -35,9 +35,10 @@ CASES = [
 ]
 
 
-def run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed, storage="f32", amp=0.05, collision=0):
+def run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed, storage="f32", amp=0.05, collision=0,
+             u_wall=(0.0, 0.0)):
     lo, hi = bc if isinstance(bc, tuple) else (bc, bc)
-    case = W.make_case(nx, ny, nz, tau, lo, hi, sponge)
+    case = W.make_case(nx, ny, nz, tau, lo, hi, sponge, u_wall=u_wall)
     f0 = W.random_populations(seed, nx, ny, nz, amp=amp)
     say(f"lattice parity nx={nx} ny={ny} nz={nz} tau={tau} bc={bc} sponge={sponge} steps={steps} {storage} "
         f"collision={collision}")
@@ -48,11 +49,11 @@ def run_pair(T, orc, nx, ny, nz, tau, bc, sponge, steps, seed, storage="f32", am
     gpu = S.populations()
     # the library keeps post-collision states: its input is C_0, so the
     # oracle streams it first, then alternates collide/stream
-    f = orc.stream_grid(f0, lo, hi)
+    f = orc.stream_grid(f0, lo, hi, u_wall)
     for s in range(steps):
         C = orc.collide_grid(f, tau, sponge, collision=collision)
         if s + 1 < steps:
-            f = orc.stream_grid(C, lo, hi)
+            f = orc.stream_grid(C, lo, hi, u_wall)
     S.close()
     return gpu, oracle_to_soa(C)
 
@@ -115,3 +116,11 @@ def test_schedules_are_bitwise_identical(T, block, schedule):
         outs.append(S.populations())
         S.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("steps,storage,tol", [(1, "f32", TOL_F32), (20, "f32", TOL_F32), (20, "f16", 2e-3)])
+def test_moving_walls_match_oracle(T, orc, steps, storage, tol):
+    """No-slip walls moving in x (the shear flow of the rotation case)."""
+    gpu, ref = run_pair(T, orc, 16, 12, 11, 0.7, W.BC_NOSLIP, 0, steps, seed=13, amp=0.02, storage=storage,
+                        u_wall=(-0.03, 0.05))
+    assert max_rel(gpu, ref) < tol
