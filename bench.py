@@ -449,7 +449,8 @@ def settling_table3(T, W, torch, D, res=TABLE3_RE, kappa=2.7):
         Fd = float(np.mean(F))
         row = {"re_target": re, "D": D, "box": [case["nx"], case["ny"], case["nz"]], "tau": round(case["tau"], 5),
                "steps": steps, "v_T_lattice": round(vT, 6), "re_simulated": round(re_sim, 3),
-               "vT_over_clift_gauvin": round(vT / v_cg, 4), "v_inf_over_clift_gauvin": round(v_inf / v_cg, 4),
+               "vT_over_clift_gauvin": round(vT / v_cg, 4),
+               "v_inf_over_clift_gauvin": round(v_inf / v_cg, 4) if re < 1 else None,
                "vT_over_stokes": round(vT / (Fg / (3.0 * math.pi * nu * D)), 4) if re < 1 else None,
                "delta_vT_paper_measure": round((vT - v_ref) / vT, 4),
                "delta_F": round((Fg - Fd) / Fg, 4), "p_star": round(float(np.mean(Fp)) / Fd, 4),
@@ -560,6 +561,8 @@ def main():
     ap.add_argument("--settling-sweep", type=str, default=None,
                     help="comma-separated sphere diameters: run only the terminal-velocity resolution sweep")
     ap.add_argument("--no-stability", action="store_true")
+    ap.add_argument("--lattice-rates", action="store_true",
+                    help="run only the fluid-only lattice kernel comparison (D3Q27, D3Q19, moment storage)")
     ap.add_argument("--table3", type=str, default=None,
                     help="D[:Re1,Re2,...]: run only the terminal-velocity comparison of Table 3 at diameter D cells")
     ap.add_argument("--coupling", default="auto", choices=["auto", "serial", "beside"],
@@ -578,6 +581,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.lattice_rates:
+        print(json.dumps({"metric": "fluid-only lattice kernel rates", "data": "synthetic",
+                          "rows": lattice_rate_run(T, W, torch, steps=args.steps)}))
+        return
     if args.table3:
         d, _, rl = args.table3.partition(":")
         res = [float(r) for r in rl.split(",")] if rl else TABLE3_RE

@@ -221,11 +221,8 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
             if (k.bc_zlo != LBM_BC_PERIODIC || k.bc_zhi != LBM_BC_PERIODIC || k.sponge_cells != 0)
                 return "case " + std::to_string(c) + ": the D3Q19 lattice needs periodic z and no sponge";
         }
-        if (mom) {
-            if (b && b->n_markers > 0) return "case " + std::to_string(c) + ": moment storage is fluid-only (no markers)";
-            if (k.bc_zlo != LBM_BC_PERIODIC || k.bc_zhi != LBM_BC_PERIODIC)
-                return "case " + std::to_string(c) + ": moment storage needs periodic z";
-        }
+        if (mom && b && b->n_markers > 0)
+            return "case " + std::to_string(c) + ": moment storage is fluid-only (no markers)";
         CaseDev &d = P.cd[c];
         d.nx = k.nx;
         d.ny = k.ny;

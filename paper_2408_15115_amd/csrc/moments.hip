@@ -5,7 +5,9 @@
 // given by ten numbers.  Stored per cell (FP32, SoA [10][nz][ny][nx]):
 //   m0 = rho - 1,  m1..3 = rho u,  m4..9 = (1 - 1/tau) P1 as xx, yy, zz, xy, xz, yz.
 // The step reads 40 bytes and writes 40 bytes per cell instead of 27 + 27
-// populations.  Fluid-only, periodic in x, y and z.
+// populations.  Fluid-only, periodic in x and y; z periodic or bounded by the
+// walls of the lattice kernel (free-slip, no-slip at rest or moving in x,
+// constant pressure).
 //
 // The step marches in z.  A workgroup owns a column of MX x MY cells and a
 // chunk of LZ output planes.  For each plane it expands the stored moments of
@@ -108,6 +110,50 @@ __device__ __forceinline__ void add_group(const float (*L)[NH], int ix, int iy, 
         acc[9] += CZ > 0 ? sy : -sy;
     }
 }
+// The nine populations with xi_z = CZ that a z wall supplies to its boundary
+// row (CZ = +1 at the bottom, -1 at the top), from the plane of that row:
+// free-slip, the mirrored direction (xi_z reversed) of the lateral
+// neighbour; no-slip, the opposite direction of the cell itself plus the
+// moving wall's momentum 6 w_i xi_x u_w; constant pressure, the opposite
+// direction of the cell itself with its sign reversed (deviation form).
+template <int CZ>
+__device__ __forceinline__ void add_wall(const float (*L)[NH], int bc, float uw, int ix, int iy, float acc[10])
+{
+    float s0 = 0.0f, sx = 0.0f, sy = 0.0f, sxx = 0.0f, syy = 0.0f, sxy = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const int ex = k % 3 - 1, ey = k / 3 - 1;
+        const int i = 9 * (CZ + 1) + k;
+        float v;
+        if (bc == BC_FREESLIP) {
+            v = L[9 * (1 - CZ) + k][(iy + 1 - ey) * HX + (ix + 1 - ex)];
+        } else {
+            v = L[Q - 1 - i][(iy + 1) * HX + (ix + 1)];
+            if (bc == BC_PRESSURE) v = -v;
+            else if (ex != 0) v += (float)(6.0 * wq(i) * ex) * uw;
+        }
+        s0 += v;
+        if (ex != 0) {
+            sx += ex > 0 ? v : -v;
+            sxx += v;
+        }
+        if (ey != 0) {
+            sy += ey > 0 ? v : -v;
+            syy += v;
+        }
+        if (ex * ey != 0) sxy += ex * ey > 0 ? v : -v;
+    }
+    acc[0] += s0;
+    acc[1] += sx;
+    acc[2] += sy;
+    acc[4] += sxx;
+    acc[5] += syy;
+    acc[7] += sxy;
+    acc[3] += CZ > 0 ? s0 : -s0;
+    acc[6] += s0;
+    acc[8] += CZ > 0 ? sx : -sx;
+    acc[9] += CZ > 0 ? sy : -sy;
+}
 }  // namespace mom
 
 // Tile t of a case: x fastest, then y, then the z chunk.  Workgroups are
@@ -151,9 +197,15 @@ __global__ void __launch_bounds__(mom::kBlock) k_moment_step(const float *__rest
     const int ix = t % MX, iy = t / MX;
     const bool out = t < MX * MY && x0 + ix < nx && y0 + iy < ny;
 
+    // z walls: planes -1 and nz exist only when z is periodic; physical
+    // plane z is stored in ring slot (z + z0) mod nz
+    const bool wlo = cd.bc_lo != BC_PERIODIC, whi = cd.bc_hi != BC_PERIODIC;
+    const int z0 = body[tl.c].z0;
+    auto exists = [&](int z) { return (z >= 0 || !wlo) && (z < nz || !whi); };
+    auto slot = [&](int z) { return wrap1(wrap1(z, nz) + z0, nz); };
     float m[10];
-    if (halo) {
-        const float *sp = s + (long long)wrap1(zs - 1, nz) * ny * nx + hoff;
+    if (halo && exists(zs - 1)) {
+        const float *sp = s + (long long)slot(zs - 1) * ny * nx + hoff;
 #pragma unroll
         for (int c = 0; c < 10; c++) m[c] = sp[c * plane];
     }
@@ -161,22 +213,27 @@ __global__ void __launch_bounds__(mom::kBlock) k_moment_step(const float *__rest
 #pragma unroll
     for (int c = 0; c < 10; c++) a[c] = bq[c] = cq[c] = 0.0f;
     for (int z = zs - 1; z <= ze; z++) {
-        if (halo) {
+        const bool have = exists(z);   // the same for the whole workgroup
+        if (halo && have) {
             float c[Q];
             expand(m, c);
 #pragma unroll
             for (int i = 0; i < Q; i++) L[i][t] = c[i];
-            if (z < ze) {   // prefetch plane z + 1
-                const float *sp = s + (long long)wrap1(z + 1, nz) * ny * nx + hoff;
+        }
+        if (halo && z < ze && exists(z + 1)) {   // prefetch plane z + 1
+            const float *sp = s + (long long)slot(z + 1) * ny * nx + hoff;
 #pragma unroll
-                for (int c2 = 0; c2 < 10; c2++) m[c2] = sp[c2 * plane];
-            }
+            for (int c2 = 0; c2 < 10; c2++) m[c2] = sp[c2 * plane];
         }
         __syncthreads();
         if (out) {
-            add_group<-1>(L, ix, iy, a);
-            add_group<0>(L, ix, iy, bq);
-            add_group<1>(L, ix, iy, cq);
+            if (have) {
+                add_group<-1>(L, ix, iy, a);
+                add_group<0>(L, ix, iy, bq);
+                add_group<1>(L, ix, iy, cq);
+                if (z == 0 && wlo) add_wall<1>(L, cd.bc_lo, cd.uw_lo, ix, iy, bq);
+                if (z == nz - 1 && whi) add_wall<-1>(L, cd.bc_hi, cd.uw_hi, ix, iy, bq);
+            }
             if (z - 1 >= zs) {   // plane z - 1 is complete
                 const int zo = z - 1;
                 Moments rm;
@@ -197,7 +254,7 @@ __global__ void __launch_bounds__(mom::kBlock) k_moment_step(const float *__rest
                 const unsigned long long bm = __ballot(bad);
                 if (bm != 0ull && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)bm) - 1)
                     atomicOr(&body[tl.c].err, 4);
-                float *dp = d + ((long long)zo * ny + (y0 + iy)) * nx + (x0 + ix);
+                float *dp = d + ((long long)slot(zo) * ny + (y0 + iy)) * nx + (x0 + ix);
 #pragma unroll
                 for (int c = 0; c < 10; c++) __builtin_nontemporal_store(mo[c], &dp[c * plane]);
             }

@@ -166,7 +166,7 @@ def test_d3q19_lattice_option():
 
 def test_moment_storage_option():
     """Moment storage: 10 FP32 planes per case; D3Q27 regularized,
-    fluid-only, periodic z, schedule 0 only."""
+    fluid-only, schedule 0 only, any z walls."""
     from paper_2408_15115_amd import turret as T
     case = W.make_case(24, 20, 40, 0.6, W.BC_PERIODIC, W.BC_PERIODIC, 0)
     cells = 24 * 20 * 40
@@ -179,9 +179,7 @@ def test_moment_storage_option():
         with pytest.raises(T.TurretError) as e:
             T.required_bytes([case], None, **dict({"storage": "mom"}, **kw))
         assert needle in str(e.value)
-    with pytest.raises(T.TurretError) as e:
-        T.required_bytes([dict(case, bc_zlo=W.BC_NOSLIP, bc_zhi=W.BC_PRESSURE)], None, storage="mom")
-    assert "periodic z" in str(e.value)
+    T.required_bytes([dict(case, bc_zlo=W.BC_NOSLIP, bc_zhi=W.BC_PRESSURE)], None, storage="mom")
     sc, sb = W.case_sphere48()
     sc = dict(sc, bc_zlo=W.BC_PERIODIC, bc_zhi=W.BC_PERIODIC)
     with pytest.raises(T.TurretError) as e:

@@ -1,8 +1,10 @@
 """GPU parity of the moment-storage form of the D3Q27 recursive-regularized
 step (App. A: the collided state is a function of rho, u and P1 only)
 against the FP64 oracle, element by element on the reconstructed
-populations: FP32, periodic boxes with ragged column tiles and several z
-chunks, with and without a sponge, after one and after many steps; the
+populations: FP32, boxes with ragged column tiles and several z chunks,
+periodic or between free-slip, no-slip (resting or moving) and
+constant-pressure walls, with and without a sponge, after one and after
+many steps; the
 round trip of a regularized state through the ten stored moments; agreement
 with population storage on the same state; the rest state; and mass and
 momentum conservation."""
@@ -31,10 +33,12 @@ def regularized_state(orc, seed, nx, ny, nz, tau, sponge, amp):
     return orc.collide_grid(W.random_populations(seed, nx, ny, nz, amp=amp), tau, sponge)
 
 
-def run_pair(T, orc, nx, ny, nz, tau, sponge, steps, seed, amp=0.05):
-    case = W.make_case(nx, ny, nz, tau, W.BC_PERIODIC, W.BC_PERIODIC, sponge)
+def run_pair(T, orc, nx, ny, nz, tau, sponge, steps, seed, amp=0.05, bc=(W.BC_PERIODIC, W.BC_PERIODIC),
+             u_wall=(0.0, 0.0)):
+    case = W.make_case(nx, ny, nz, tau, bc[0], bc[1], sponge, u_wall=u_wall)
     C0 = regularized_state(orc, seed, nx, ny, nz, tau, sponge, amp)
-    say(f"moment storage parity nx={nx} ny={ny} nz={nz} tau={tau} sponge={sponge} steps={steps}")
+    say(f"moment storage parity nx={nx} ny={ny} nz={nz} tau={tau} sponge={sponge} steps={steps} bc={bc} "
+        f"u_wall={u_wall}")
     S = T.Solver([case], storage="mom")
     S.set_populations(oracle_to_soa(C0))
     for _ in range(steps):
@@ -45,7 +49,7 @@ def run_pair(T, orc, nx, ny, nz, tau, sponge, steps, seed, amp=0.05):
     assert err == 0
     C = C0
     for _ in range(steps):
-        C = orc.collide_grid(orc.stream_grid(C), tau, sponge)
+        C = orc.collide_grid(orc.stream_grid(C, bc[0], bc[1], u_wall), tau, sponge)
     return gpu, oracle_to_soa(C), C0
 
 
@@ -68,6 +72,22 @@ def test_one_step_matches_oracle(T, orc, nx, ny, nz, tau, sponge):
 @pytest.mark.parametrize("nx,ny,nz,tau,sponge", [CASES[1], CASES[2], CASES[4]])
 def test_many_steps_match_oracle(T, orc, nx, ny, nz, tau, sponge):
     gpu, ref, _ = run_pair(T, orc, nx, ny, nz, tau, sponge, 25, seed=nx + ny, amp=0.02)
+    assert max_rel(gpu, ref) < TOL_F32
+
+
+WALLS = [
+    # nx, ny, nz, tau, sponge, (bottom, top), u_wall
+    (20, 14, 40, 0.8, 6, (W.BC_FREESLIP, W.BC_FREESLIP), (0.0, 0.0)),
+    (33, 12, 37, 0.6, 0, (W.BC_NOSLIP, W.BC_NOSLIP), (-0.03, 0.05)),
+    (24, 13, 48, 0.7, 9, (W.BC_NOSLIP, W.BC_PRESSURE), (0.0, 0.0)),   # the paper's domain
+    (16, 10, 12, 0.9, 0, (W.BC_PRESSURE, W.BC_FREESLIP), (0.0, 0.0)),
+]
+
+
+@pytest.mark.parametrize("steps", [1, 20])
+@pytest.mark.parametrize("nx,ny,nz,tau,sponge,bc,u_wall", WALLS)
+def test_walls_match_oracle(T, orc, nx, ny, nz, tau, sponge, bc, u_wall, steps):
+    gpu, ref, _ = run_pair(T, orc, nx, ny, nz, tau, sponge, steps, seed=nx + nz, amp=0.02, bc=bc, u_wall=u_wall)
     assert max_rel(gpu, ref) < TOL_F32
 
 
