@@ -648,7 +648,7 @@ def main():
         del S
         torch.cuda.empty_cache()
         eb = T.ELEM_BYTES[T.STORAGE[storage]]
-        kbytes = 2 * 27 * eb * cells
+        kbytes = 2 * (10 if storage == "mom" else 27) * eb * cells   # stored values read and written
         return {"ms_per_step": total_ms / steps, "mlups": cells * steps / (total_ms * 1e-3) / 1e6,
                 "k1_ms": k1_ms, "k1_gbps": kbytes / (k1_ms * 1e-3) / 1e9, "k1_bytes": kbytes,
                 "graph_ms_per_step": gms, "F": st["F"].tolist(), "v": st["v"].tolist(), "steps": st["steps"],
@@ -678,6 +678,18 @@ def main():
             log(f"  {sto}: {r['mlups']:.0f} MLUPS, kernel {r['k1_gbps']:.0f} GB/s, drag diff vs f32 "
                 f"{variants[sto]['drag_rel_diff_vs_f32']:.2e}")
         variants["f32_same_steps"] = {"mlups": round(ref["mlups"], 1), "k1_gbps": round(ref["k1_gbps"], 1)}
+        # moment storage: the same coupled step, ten moments per cell (plus the
+        # forcing shifts of the particle region); graph-replayed like the value
+        r = run_storage("mom", args.variant_steps, 5, True)
+        gm = r["graph_ms_per_step"]
+        variants["moments"] = {"mlups_graph": round(cells / (gm * 1e-3) / 1e6, 1), "graph_ms_per_step": round(gm, 4),
+                               "mlups_eager": round(r["mlups"], 1), "lattice_kernel_ms": round(r["k1_ms"], 4),
+                               "lattice_kernel_gbps": round(r["k1_gbps"], 1),
+                               "drag_rel_diff_vs_f32": abs(r["F"][2] - ref["F"][2]) / abs(ref["F"][2]),
+                               "vz_rel_diff_vs_f32": abs(r["v"][2] - ref["v"][2]) / abs(ref["v"][2]),
+                               "after_steps": args.variant_steps}
+        log(f"  moment storage: {variants['moments']['mlups_graph']:.0f} MLUPS (graph), lattice kernel "
+            f"{r['k1_ms']:.3f} ms, drag diff vs f32 {variants['moments']['drag_rel_diff_vs_f32']:.2e}")
 
     if not args.no_variants and not args.no_batch:
         b = batch_run(T, W, torch, args.batch_steps, args.storage)

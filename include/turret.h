@@ -125,8 +125,10 @@ typedef struct {
  *               (1 - 1/tau) P1 (xx, yy, zz, xy, xz, yz), layout
  *               [10][nz][ny][nx] per case.  The step reconstructs the
  *               populations it pulls and gives the same result as LBM_F32 up to
- *               rounding.  Fluid-only cases (any z walls), lattice 27,
- *               collision 0 and schedule 0 only.  lbm_get_populations returns
+ *               rounding.  A forced cell (Sec. 2.2) keeps its equilibrium
+ *               shift tau h beside the moments for the next step, in a box over
+ *               the particle region.  Lattice 27, collision 0 and schedule 0
+ *               only.  lbm_get_populations returns
  *               the reconstructed populations; lbm_set_populations keeps the
  *               regularized part of what it is given (exact for a
  *               post-collision state of this collision)

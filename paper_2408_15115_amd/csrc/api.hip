@@ -38,7 +38,7 @@ struct Plan {
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
         off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox,
-        off_mark, off_wt, aux_bytes;
+        off_mark, off_wt, off_dsh, aux_bytes;
     int block = 256;
 };
 
@@ -221,8 +221,6 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
             if (k.bc_zlo != LBM_BC_PERIODIC || k.bc_zhi != LBM_BC_PERIODIC || k.sponge_cells != 0)
                 return "case " + std::to_string(c) + ": the D3Q19 lattice needs periodic z and no sponge";
         }
-        if (mom && b && b->n_markers > 0)
-            return "case " + std::to_string(c) + ": moment storage is fluid-only (no markers)";
         CaseDev &d = P.cd[c];
         d.nx = k.nx;
         d.ny = k.ny;
@@ -305,6 +303,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_hs = take(sizeof(double) * M);
     P.off_dSo = take(sizeof(double) * M);
     P.off_wt = take(sizeof(double) * 12 * M);
+    P.off_dsh = take(sizeof(float) * 4 * std::max<long long>(reg, 1));
     P.off_mtiles = take(sizeof(MarkerTile) * NT);
     P.off_tbox = take(sizeof(TileBox) * NT);
     P.aux_bytes = o;
@@ -444,6 +443,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.hstride = 3 * std::max<long long>(P.reg_cells, 1);
     p.mark = (unsigned char *)(a + P.off_mark);
     p.wt = (double *)(a + P.off_wt);
+    p.dsh = (float *)(a + P.off_dsh);
     p.mtiles = (MarkerTile *)(a + P.off_mtiles);
     p.feat = (float *)(a + P.off_feat);
     p.h0 = (double *)(a + P.off_h0);
@@ -789,7 +789,7 @@ int32_t lbm_get_populations(lbm_ctx *ctx, int32_t c, double *out)
     if (mom) {   // reconstruct the populations on the device
         float *tmp = nullptr;
         HIPCHK(ctx, hipMalloc(&tmp, raw.size()), "allocate population buffer");
-        hipError_t he = launch_moments_expand((const float *)src, tmp, d.plane, d.cells, ctx->stream);
+        hipError_t he = launch_moments_expand((const float *)src, tmp, ctx->p, c, ctx->stream);
         if (he == hipSuccess) he = hipMemcpyAsync(raw.data(), tmp, raw.size(), hipMemcpyDeviceToHost, ctx->stream);
         if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
         (void)hipFree(tmp);
@@ -836,6 +836,10 @@ int32_t lbm_set_populations(lbm_ctx *ctx, int32_t c, const double *in)
         HIPCHK(ctx, hipMalloc(&tmp, raw.size()), "allocate population buffer");
         hipError_t he = hipMemcpyAsync(tmp, raw.data(), raw.size(), hipMemcpyHostToDevice, ctx->stream);
         if (he == hipSuccess) he = launch_moments_project(tmp, (float *)dst, d.plane, d.cells, ctx->stream);
+        // the forcing shifts of the last correction no longer apply
+        const int zero = 0;
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(&ctx->p.body[c].dvalid, &zero, sizeof zero, hipMemcpyHostToDevice, ctx->stream);
         if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
         (void)hipFree(tmp);
         HIPCHK(ctx, he, "project populations");
@@ -875,10 +879,14 @@ int32_t lbm_save(lbm_ctx *ctx, const char *path)
     if (!ctx || !path) return LBM_EINVAL;
     if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "save between lbm_step and ibm_couple");
     const int eb = elem_bytes(ctx->opt.storage);
+    // moment storage also keeps the forcing shifts of the last correction
+    const size_t extra = ctx->opt.storage == LBM_MOM ? sizeof(float) * 4 * (size_t)std::max<long long>(ctx->plan.reg_cells, 1) : 0;
     const size_t popb = (size_t)ctx->plan.pop_elems * eb;
-    std::vector<char> pop(popb);
+    std::vector<char> pop(popb + extra);
     std::vector<BodyDev> bd(ctx->n);
     HIPCHK(ctx, hipMemcpyAsync(pop.data(), ctx->pop[ctx->cur], popb, hipMemcpyDeviceToHost, ctx->stream), "save");
+    if (extra)
+        HIPCHK(ctx, hipMemcpyAsync(pop.data() + popb, ctx->p.dsh, extra, hipMemcpyDeviceToHost, ctx->stream), "save");
     HIPCHK(ctx, hipMemcpyAsync(bd.data(), ctx->p.body, sizeof(BodyDev) * ctx->n, hipMemcpyDeviceToHost, ctx->stream), "save");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     FILE *f = std::fopen(path, "wb");
@@ -886,7 +894,7 @@ int32_t lbm_save(lbm_ctx *ctx, const char *path)
     const int64_t hdr[4] = {ctx->n, ctx->opt.storage, (int64_t)popb, (int64_t)sizeof(BodyDev)};
     bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
               std::fwrite(bd.data(), sizeof(BodyDev), ctx->n, f) == (size_t)ctx->n &&
-              std::fwrite(pop.data(), 1, popb, f) == popb;
+              std::fwrite(pop.data(), 1, popb + extra, f) == popb + extra;
     ok = (std::fclose(f) == 0) && ok;
     return ok ? LBM_OK : fail(ctx, LBM_EINVAL, "write failed");
 }
@@ -900,17 +908,20 @@ int32_t lbm_load(lbm_ctx *ctx, const char *path)
     char magic[8];
     int64_t hdr[4];
     const int eb = elem_bytes(ctx->opt.storage);
+    const size_t extra = ctx->opt.storage == LBM_MOM ? sizeof(float) * 4 * (size_t)std::max<long long>(ctx->plan.reg_cells, 1) : 0;
     const size_t popb = (size_t)ctx->plan.pop_elems * eb;
     bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
               std::fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == ctx->n && hdr[1] == ctx->opt.storage &&
               hdr[2] == (int64_t)popb && hdr[3] == (int64_t)sizeof(BodyDev);
     std::vector<BodyDev> bd(ctx->n);
-    std::vector<char> pop(ok ? popb : 0);
+    std::vector<char> pop(ok ? popb + extra : 0);
     ok = ok && std::fread(bd.data(), sizeof(BodyDev), ctx->n, f) == (size_t)ctx->n &&
-         std::fread(pop.data(), 1, popb, f) == popb;
+         std::fread(pop.data(), 1, popb + extra, f) == popb + extra;
     std::fclose(f);
     if (!ok) return fail(ctx, LBM_EINVAL, "checkpoint does not match this context");
     HIPCHK(ctx, hipMemcpyAsync(ctx->pop[ctx->cur], pop.data(), popb, hipMemcpyHostToDevice, ctx->stream), "load");
+    if (extra)
+        HIPCHK(ctx, hipMemcpyAsync(ctx->p.dsh, pop.data() + popb, extra, hipMemcpyHostToDevice, ctx->stream), "load");
     HIPCHK(ctx, hipMemcpyAsync(ctx->p.body, bd.data(), sizeof(BodyDev) * ctx->n, hipMemcpyHostToDevice, ctx->stream), "load");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     return LBM_OK;

@@ -40,6 +40,8 @@ struct BodyDev {
     int accepts, rejects;       // learned-start decisions so far
     int fallback;               // 1 if the last step fell back to the plain start
     int active;                 // 1 while the case still runs cycles of the current sequence
+    int dorg[3];                // moment storage: forcing-box origin (x, y, ring slot) of the last correction
+    int dvalid;                 // moment storage: 1 once a correction has written the forcing box
     int warm_cyc_sum;           // cycles used by the accepted learned starts, summed
     int org[3];      // IBM region origin (physical cell coordinates, x/y unwrapped)
     int err;         // 1: a marker stencil left the box in z; 2: non-finite or huge IBM value;
@@ -111,6 +113,7 @@ struct DevPtrs {
     double *hs;      // per-marker scale of the warm-start features, |h0| + |h(t-1)|
     double *dSo;     // per-marker areas of the parallel force surface (cases with force_offset > 0)
     TileBox *tbox;   // per-tile box, computed each step by k_markers
+    float *dsh;      // moment storage: per region cell the forcing shift (Delta_x, Delta_y, Delta_z, lambda)
 };
 
 // ---------------------------------------------------------------- launchers
@@ -120,12 +123,12 @@ hipError_t launch_stream_collide(int storage, const void *src, void *dst, const 
 // The D3Q19 comparison lattice (fluid only, FP32, periodic, plain schedule).
 hipError_t launch_stream_collide19(const void *src, void *dst, const DevPtrs &p, int ntiles, int block,
                                    int collision, hipStream_t s);
-// Moment storage (fluid only, FP32, periodic): the z-marching step over the
-// moment tile table, and per-case conversions between moments and
-// population deviations ([10][plane] <-> [27][plane]).
+// Moment storage (FP32): the z-marching step over the moment tile table, and
+// per-case conversions between moments (with the forcing shifts of the last
+// correction) and population deviations ([10][plane] <-> [27][plane]).
 int moment_tiles(int nx, int ny, int nz);
 hipError_t launch_moment_step(const void *src, void *dst, const DevPtrs &p, int ntiles, hipStream_t s);
-hipError_t launch_moments_expand(const float *src, float *dst, long long plane, long long cells, hipStream_t s);
+hipError_t launch_moments_expand(const float *src, float *dst, const DevPtrs &p, int c, hipStream_t s);
 hipError_t launch_moments_project(const float *src, float *dst, long long plane, long long cells, hipStream_t s);
 hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
 // IBM coupling.  With a warm start (warm_mode 1: the previous step's final

@@ -25,6 +25,8 @@
 #include "lattice.hpp"
 #include "pull.hpp"
 #include "mlp.hpp"
+#include "moments.hpp"
+#include <type_traits>
 
 namespace turret {
 
@@ -127,6 +129,55 @@ __device__ inline BodyView body_view(const BodyDev &B)
     return v;
 }
 
+// Moment storage: the tag that selects the moment forms of the region gather,
+// the correction and the window reset.
+struct CodecMom {
+    using T = float;
+};
+
+// The pull of pull() on moment storage: population dir of each source cell,
+// evaluated from that cell's stored state (and its forcing shift), with the
+// same z wall rules.
+__device__ inline void pull_mom(const float *__restrict__ src, const CaseDev &cd, const mom::ShiftBox &sb, int z0,
+                                int x, int y, int z, float g[Q])
+{
+    const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
+#pragma unroll 1
+    for (int i = 0; i < Q; i++) {
+        const int ex = cx(i), ey = cy(i), ez = cz(i);
+        int sx = x - ex, sy = y - ey, sz = z - ez;
+        sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+        sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+        int dir = i;
+        float sign = 1.0f, add = 0.0f;
+        const bool out_lo = sz < 0, out_hi = sz >= nz;
+        const int bc = out_lo ? cd.bc_lo : (out_hi ? cd.bc_hi : BC_PERIODIC);
+        if ((out_lo || out_hi) && bc != BC_PERIODIC) {
+            sz = z;
+            if (bc == BC_FREESLIP) {
+                dir = 9 * (-ez + 1) + 3 * (ey + 1) + (ex + 1);
+            } else {
+                dir = Q - 1 - i;
+                sx = x;
+                sy = y;
+                if (bc == BC_PRESSURE) sign = -1.0f;
+                else add = (float)(6.0 * wq(i) * ex) * (out_lo ? cd.uw_lo : cd.uw_hi);
+            }
+        } else {
+            sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
+        }
+        int slot = sz + z0;
+        if (slot >= nz) slot -= nz;
+        const float *sp = src + ((long long)slot * ny + sy) * nx + sx;
+        float m[10], sh[4], A[Q];
+#pragma unroll
+        for (int c = 0; c < 10; c++) m[c] = sp[c * cd.plane];
+        (void)mom::shift_at(sb, nx, ny, nz, sx, sy, slot, sh);
+        mom::state_coeffs(m, sh, A);
+        g[i] = sign * mom::population(A, dir) + add;
+    }
+}
+
 // ------------------------------------------------------------ region fields
 // For every cell of the particle region: pull f(t+1) from the buffer the
 // lattice kernel read, then rho - 1, u* = sum xi f / sum f and the stress
@@ -161,8 +212,11 @@ __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs 
     }
     const int gx = wrapi(B.org[0] + a, cd.nx), gy = wrapi(B.org[1] + b, cd.ny);
     float g[Q];
-    pull<CD>(src + cd.pop_off, cd.plane, cd.nx, cd.ny, cd.nz, B.z0, cd.bc_lo, cd.bc_hi, cd.uw_lo, cd.uw_hi, gx, gy, gz,
-             g);
+    if constexpr (std::is_same<CD, CodecMom>::value)
+        pull_mom(src + cd.pop_off, cd, mom::shift_box(p, cd, p.body[c]), B.z0, gx, gy, gz, g);
+    else
+        pull<CD>(src + cd.pop_off, cd.plane, cd.nx, cd.ny, cd.nz, B.z0, cd.bc_lo, cd.bc_hi, cd.uw_lo, cd.uw_hi, gx, gy,
+                 gz, g);
     const Macro M = macro(raw_moments(g));
     const float tau = tau_at(cd.tau0, cd.nz, cd.sponge, gz);
     const float fac = 0.5f / tau - 1.0f;
@@ -1105,6 +1159,52 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
     });
 }
 
+// The forced correction on moment storage: the stored moments stay the
+// regularized state; the shift of every cell of the particle region goes to
+// the case's forcing box, (tau h, lambda) on forced cells and zero elsewhere,
+// with lambda = 1, or 1 / tau in the momentum-exact variant (the first-order
+// term then carries rho h).  The box's origin is recorded in ring-slot
+// coordinates, which a window shift leaves in place.  Marks are cleared.
+__global__ void k_correct_mom(DevPtrs p)
+{
+    const int c = blockIdx.y;
+    const CaseDev cd = p.cases[c];
+    const BodyView B = body_view(p.body[c]);
+    if (cd.M == 0 || B.err != 0) return;
+    const int L = cd.L, L3 = L * L * L;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) {
+        BodyDev &Bw = p.body[c];
+        Bw.dorg[0] = wrapi(B.org[0], cd.nx);
+        Bw.dorg[1] = wrapi(B.org[1], cd.ny);
+        Bw.dorg[2] = wrapi(B.org[2] + B.z0, cd.nz);
+        Bw.dvalid = 1;
+    }
+    if (q >= L3) return;
+    float *D = p.dsh + cd.reg_off * 4;
+    float sh[4] = {0.0f, 0.0f, 0.0f, 1.0f};
+    unsigned char &mk = p.mark[cd.reg_off + q];
+    const int gz = B.org[2] + q / (L * L);
+    if (mk && gz >= 0 && gz < cd.nz) {
+        const long long *H = p.H + cd.reg_off * 3;
+        long long h0 = 0, h1 = 0, h2 = 0;
+#pragma unroll
+        for (int j = 0; j < kHBufs; j++) {
+            h0 += H[j * p.hstride + q];
+            h1 += H[j * p.hstride + L3 + q];
+            h2 += H[j * p.hstride + 2 * L3 + q];
+        }
+        const float tau = tau_at(cd.tau0, cd.nz, cd.sponge, gz);
+        sh[0] = tau * (float)((double)h0 * kFixInv);
+        sh[1] = tau * (float)((double)h1 * kFixInv);
+        sh[2] = tau * (float)((double)h2 * kFixInv);
+        if (cd.forcing == 1) sh[3] = 1.0f / tau;
+    }
+    if (mk) mk = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) D[k * (long long)L3 + q] = sh[k];
+}
+
 // ----------------------------------------------------------------- window
 // Sec. 2.5: below h_end the content and the body move up by dz rows.  With
 // the ring layout the move is the origin change z0 -> z0 - dz; the dz rows
@@ -1137,10 +1237,15 @@ __global__ void k_window_reset(typename CD::T *__restrict__ cur, DevPtrs p)
         int zc = zrow + B.z0;
         if (zc >= cd.nz) zc -= cd.nz;
         typename CD::T *dst = cur + cd.pop_off + (long long)zc * slab + rem;
-        Unroll<0, Q>::run([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            dst[(long long)i * cd.plane] = CD::template enc<i>(0.0f);
-        });
+        if constexpr (std::is_same<CD, CodecMom>::value) {
+#pragma unroll
+            for (int k = 0; k < 10; k++) dst[(long long)k * cd.plane] = 0.0f;   // the rest state's moments
+        } else {
+            Unroll<0, Q>::run([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                dst[(long long)i * cd.plane] = CD::template enc<i>(0.0f);
+            });
+        }
     }
 }
 
@@ -1235,6 +1340,9 @@ hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases,
 {
     if (Mtot == 0) return hipSuccess;
     switch (storage) {
+    case ST_MOM:
+        hipLaunchKernelGGL(k_correct_mom, dim3((maxL3 + 255) / 256, n_cases), dim3(256), 0, s, p);
+        return hipGetLastError();
     case ST_F16: return correct_impl<CodecF16>(cur, p, n_cases, maxL3, s);
     case ST_BF16: return correct_impl<CodecBF16>(cur, p, n_cases, maxL3, s);
     default: return correct_impl<CodecF32>(cur, p, n_cases, maxL3, s);
@@ -1247,6 +1355,9 @@ hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p
 {
     if (Mtot == 0) return hipSuccess;
     switch (storage) {
+    case ST_MOM:
+        return ibm_impl<CodecMom>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16, warm_cycles,
+                                  diag, force_surface, s);
     case ST_F16:
         return ibm_impl<CodecF16>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16, warm_cycles,
                                   diag, force_surface, s);
@@ -1280,6 +1391,7 @@ static hipError_t window_impl(void *cur, const DevPtrs &p, int n_cases, int max_
 hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s)
 {
     switch (storage) {
+    case ST_MOM: return window_impl<CodecMom>(cur, p, n_cases, max_slab, s);
     case ST_F16: return window_impl<CodecF16>(cur, p, n_cases, max_slab, s);
     case ST_BF16: return window_impl<CodecBF16>(cur, p, n_cases, max_slab, s);
     default: return window_impl<CodecF32>(cur, p, n_cases, max_slab, s);

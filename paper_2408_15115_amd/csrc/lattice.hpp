@@ -49,7 +49,7 @@ constexpr double kScaleBase = 4096.0;
 __host__ __device__ constexpr double store_scale(int i) { return kScaleBase / wq(i); }
 
 enum { BC_PERIODIC = 0, BC_FREESLIP = 1, BC_NOSLIP = 2, BC_PRESSURE = 3 };
-enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_MOM = 3 };
 
 // ------------------------------------------------------------------ codecs
 struct CodecF32 {

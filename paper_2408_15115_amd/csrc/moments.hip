@@ -18,6 +18,7 @@
 // moments are loaded before the gather so that the HBM reads overlap it.
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "moments.hpp"
 
 namespace turret {
 
@@ -35,45 +36,6 @@ static_assert(NH <= kBlock && MX * MY <= kBlock, "tile does not fit the workgrou
 __device__ __forceinline__ int wrap1(int v, int n)
 {
     return v < 0 ? v + n : (v >= n ? v - n : v);
-}
-
-// Deviations C - w of the collided populations from the stored moments.
-__device__ __forceinline__ void expand(const float m[10], float out[Q])
-{
-    Macro M;
-    M.r1 = m[0];
-    M.rho = 1.0f + m[0];
-    const float inv = 1.0f / M.rho;
-    M.u[0] = m[1] * inv;
-    M.u[1] = m[2] * inv;
-    M.u[2] = m[3] * inv;
-    M.P[0][0] = m[4];
-    M.P[1][1] = m[5];
-    M.P[2][2] = m[6];
-    M.P[0][1] = M.P[1][0] = m[7];
-    M.P[0][2] = M.P[2][0] = m[8];
-    M.P[1][2] = M.P[2][1] = m[9];
-    float A[Q];
-    post_collision_coeffs(M, M.u, 1.0f, A);
-    hermite_to_populations(A, out);
-}
-
-// Collide: raw moments of the pulled deviations -> the stored post-collision state.
-__device__ __forceinline__ void collide_to_moments(const Moments &rm, float om, float m[10], bool &bad)
-{
-    const Macro M = macro(rm);
-    const float u2 = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
-    bad = !(fabsf(M.r1) < 1.0f) || !(u2 < 0.25f);
-    m[0] = M.r1;
-    m[1] = rm.j[0];
-    m[2] = rm.j[1];
-    m[3] = rm.j[2];
-    m[4] = om * M.P[0][0];
-    m[5] = om * M.P[1][1];
-    m[6] = om * M.P[2][2];
-    m[7] = om * M.P[0][1];
-    m[8] = om * M.P[0][2];
-    m[9] = om * M.P[1][2];
 }
 
 // Partial raw moments of the nine pulled populations with xi_z = CZ (from
@@ -168,11 +130,12 @@ __device__ __forceinline__ void add_wall(const float (*L)[NH], int bc, float uw,
 // keeps partial moment sums for planes z - 1, z and z + 1 in registers and
 // only the newest expanded plane is held in LDS.
 __global__ void __launch_bounds__(mom::kBlock) k_moment_step(const float *__restrict__ src, float *__restrict__ dst,
-                                                             const CaseDev *__restrict__ cases,
-                                                             BodyDev *__restrict__ body,
-                                                             const Tile *__restrict__ tiles, int ntiles)
+                                                             DevPtrs p, int ntiles)
 {
     using namespace mom;
+    const CaseDev *__restrict__ cases = p.cases;
+    BodyDev *__restrict__ body = p.body;
+    const Tile *__restrict__ tiles = p.tiles;
     const int b = blockIdx.x;
     const int ti = (b & 7) * ((ntiles + 7) >> 3) + (b >> 3);
     if (ti >= ntiles) return;
@@ -203,6 +166,7 @@ __global__ void __launch_bounds__(mom::kBlock) k_moment_step(const float *__rest
     const int z0 = body[tl.c].z0;
     auto exists = [&](int z) { return (z >= 0 || !wlo) && (z < nz || !whi); };
     auto slot = [&](int z) { return wrap1(wrap1(z, nz) + z0, nz); };
+    const ShiftBox sb = shift_box(p, cd, body[tl.c]);   // forcing shifts of the last correction
     float m[10];
     if (halo && exists(zs - 1)) {
         const float *sp = s + (long long)slot(zs - 1) * ny * nx + hoff;
@@ -215,8 +179,9 @@ __global__ void __launch_bounds__(mom::kBlock) k_moment_step(const float *__rest
     for (int z = zs - 1; z <= ze; z++) {
         const bool have = exists(z);   // the same for the whole workgroup
         if (halo && have) {
-            float c[Q];
-            expand(m, c);
+            float c[Q], sh[4];
+            (void)shift_at(sb, nx, ny, nz, gx, gy, slot(z), sh);
+            expand(m, sh, c);
 #pragma unroll
             for (int i = 0; i < Q; i++) L[i][t] = c[i];
         }
@@ -269,18 +234,24 @@ __global__ void __launch_bounds__(mom::kBlock) k_moment_step(const float *__rest
     }
 }
 
-// Moments -> population deviations of one case, layout [27][plane].
+// Moments (and forcing shifts) -> population deviations of case c, layout
+// [27][plane] in the ring order of the storage.
 __global__ void __launch_bounds__(256) k_moments_expand(const float *__restrict__ src, float *__restrict__ dst,
-                                                        long long plane, long long cells)
+                                                        DevPtrs p, int c)
 {
+    const CaseDev cd = p.cases[c];
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i >= cells) return;
-    float m[10], c[Q];
+    if (i >= cd.cells) return;
+    const long long plane = cd.plane;
+    const int x = (int)(i % cd.nx), y = (int)((i / cd.nx) % cd.ny), zs = (int)(i / ((long long)cd.nx * cd.ny));
+    const mom::ShiftBox sb = mom::shift_box(p, cd, p.body[c]);
+    float m[10], sh[4], out[Q];
 #pragma unroll
     for (int k = 0; k < 10; k++) m[k] = src[k * plane + i];
-    mom::expand(m, c);
+    (void)mom::shift_at(sb, cd.nx, cd.ny, cd.nz, x, y, zs, sh);
+    mom::expand(m, sh, out);
 #pragma unroll
-    for (int k = 0; k < Q; k++) dst[k * plane + i] = c[k];
+    for (int k = 0; k < Q; k++) dst[k * plane + i] = out[k];
 }
 
 // Population deviations of post-collision states -> stored moments: rho - 1,
@@ -308,15 +279,17 @@ int moment_tiles(int nx, int ny, int nz)
 hipError_t launch_moment_step(const void *src, void *dst, const DevPtrs &p, int ntiles, hipStream_t s)
 {
     const int grid = (ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_moment_step, dim3(grid), dim3(mom::kBlock), 0, s, (const float *)src, (float *)dst, p.cases,
-                       p.body, p.tiles, ntiles);
+    hipLaunchKernelGGL(k_moment_step, dim3(grid), dim3(mom::kBlock), 0, s, (const float *)src, (float *)dst, p, ntiles);
     return hipGetLastError();
 }
 
-hipError_t launch_moments_expand(const float *src, float *dst, long long plane, long long cells, hipStream_t s)
+hipError_t launch_moments_expand(const float *src, float *dst, const DevPtrs &p, int c, hipStream_t s)
 {
-    const long long grid = (cells + 255) / 256;
-    hipLaunchKernelGGL(k_moments_expand, dim3((unsigned)grid), dim3(256), 0, s, src, dst, plane, cells);
+    CaseDev cd;
+    hipError_t e = hipMemcpy(&cd, p.cases + c, sizeof cd, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    const long long grid = (cd.cells + 255) / 256;
+    hipLaunchKernelGGL(k_moments_expand, dim3((unsigned)grid), dim3(256), 0, s, src, dst, p, c);
     return hipGetLastError();
 }
 

@@ -166,7 +166,7 @@ def test_d3q19_lattice_option():
 
 def test_moment_storage_option():
     """Moment storage: 10 FP32 planes per case; D3Q27 regularized,
-    fluid-only, schedule 0 only, any z walls."""
+    schedule 0 only, any z walls, with or without a particle."""
     from paper_2408_15115_amd import turret as T
     case = W.make_case(24, 20, 40, 0.6, W.BC_PERIODIC, W.BC_PERIODIC, 0)
     cells = 24 * 20 * 40
@@ -181,10 +181,9 @@ def test_moment_storage_option():
         assert needle in str(e.value)
     T.required_bytes([dict(case, bc_zlo=W.BC_NOSLIP, bc_zhi=W.BC_PRESSURE)], None, storage="mom")
     sc, sb = W.case_sphere48()
-    sc = dict(sc, bc_zlo=W.BC_PERIODIC, bc_zhi=W.BC_PERIODIC)
-    with pytest.raises(T.TurretError) as e:
-        T.required_bytes([sc], [sb], storage="mom")
-    assert "fluid-only" in str(e.value)
+    a_mom, _, aux_mom = T.required_bytes([sc], [sb], storage="mom")
+    a_pop, _, aux_pop = T.required_bytes([sc], [sb])
+    assert a_mom < a_pop / 2 and aux_mom == aux_pop   # the forcing box is part of every auxiliary buffer
 
 
 def test_moving_wall_checks():
