@@ -380,13 +380,15 @@ def settling_sweep(T, W, torch, diameters, re=5.0, offsets=(0.0, 3.0), domain="p
 TABLE3_RE = (0.58, 1.39, 4.49, 6.18, 28.3, 127.88)
 
 
-def settling_table3(T, W, torch, D, res=TABLE3_RE, kappa=2.7):
+def settling_table3(T, W, torch, D, res=TABLE3_RE, kappa=2.7, storage="f32"):
     """The terminal-velocity comparison of Table 3 (Sec. 3.2) at one
     resolution: a sphere of diameter D cells settling from rest in the
     paper's box (w* = 10, h* = 30, no-slip bottom, constant-pressure top;
-    h_ini* = 27 below Re 20 and 23 above, h_end* = 3, sponge 2.4 D), force on
+    h_ini* = 27 below Re 20, 23 up to Re 1000 and 20 above, h_end* = 3,
+    sponge 2.4 D), force on
     the parallel surface 3 cells out, max(500 D, 8 drag-law relaxation
-    times, 3 Oseen times nu / v^2) steps: at low Re the history force
+    times (6 above Re 1000, where the quadratic drag relaxes twice as fast),
+    3 Oseen times nu / v^2) steps: at low Re the history force
     approaches the terminal speed as t^(-1/2) until the Oseen time, so the
     speed is also extrapolated by a fit v = v_inf - c t^(-1/2) over the
     second half of the run.  Per Re: the terminal speed over the Clift-Gauvin value
@@ -399,14 +401,17 @@ def settling_table3(T, W, torch, D, res=TABLE3_RE, kappa=2.7):
     import numpy as np
     rows = []
     for re in res:
-        h_ini = 27.0 if re < 20 else 23.0
+        h_ini = 27.0 if re < 20 else (23.0 if re < 1000 else 20.0)
         case, body, v_t = W.case_sphere_settling(float(D), re, kappa, force_offset=3.0, domain="paper",
                                                  h_ini_d=h_ini, h_end_d=3.0, sponge_d=2.4)
         nu, g = (case["tau"] - 0.5) / 3.0, case["gravity"]
         t_relax = v_t / g * (kappa + 0.5) / kappa
         chunk = 250
-        steps = int(max(500 * D, 8 * t_relax, 3 * nu / v_t ** 2)) // chunk * chunk + chunk
-        S = T.Solver([case], [body], stream=torch.cuda.Stream())
+        # a drag quadratic in v (Re above 1000) relaxes twice as fast near the
+        # terminal speed: 6 t_relax are 12 of its time constants
+        relax = 8 if re < 1000 else 6
+        steps = int(max(500 * D, relax * t_relax, 3 * nu / v_t ** 2)) // chunk * chunk + chunk
+        S = T.Solver([case], [body], stream=torch.cuda.Stream(), storage=storage)
         nch = steps // chunk
         tail = max(8, nch // 4)
         v, F, Fp, hist = [], [], [], []
@@ -447,7 +452,8 @@ def settling_table3(T, W, torch, D, res=TABLE3_RE, kappa=2.7):
         cd_sim = 24.0 / re_sim if re < 1 else W.clift_gauvin_cd(re_sim)
         v_ref = math.sqrt(8.0 * Fg / (math.pi * D * D * cd_sim))
         Fd = float(np.mean(F))
-        row = {"re_target": re, "D": D, "box": [case["nx"], case["ny"], case["nz"]], "tau": round(case["tau"], 5),
+        row = {"re_target": re, "D": D, "storage": storage, "box": [case["nx"], case["ny"], case["nz"]],
+               "tau": round(case["tau"], 5),
                "steps": steps, "v_T_lattice": round(vT, 6), "re_simulated": round(re_sim, 3),
                "vT_over_clift_gauvin": round(vT / v_cg, 4),
                "v_inf_over_clift_gauvin": round(v_inf / v_cg, 4) if re < 1 else None,
@@ -546,7 +552,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "mom"])
     ap.add_argument("--variant-steps", type=int, default=400)
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-variants", action="store_true")
@@ -588,7 +594,7 @@ def main():
     if args.table3:
         d, _, rl = args.table3.partition(":")
         res = [float(r) for r in rl.split(",")] if rl else TABLE3_RE
-        rows = settling_table3(T, W, torch, int(d), res)
+        rows = settling_table3(T, W, torch, int(d), res, storage=args.storage)
         print(json.dumps({"metric": "sphere terminal velocity against Clift-Gauvin / Stokes across Re (Table 3)",
                           "data": "synthetic", "rows": rows}))
         return
