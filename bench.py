@@ -130,9 +130,12 @@ def batch_run(T, W, torch, steps, storage):
     batch = W.batch_cases(64)
     cases = [c for c, _ in batch]
     bodies = [b for _, b in batch]
-    tuned = autotune.tune_step(cases, bodies, storage=storage)
-    log(f"batch: schedule {tuned['best']} ({'cached' if tuned['cached'] else 'tuned'} on whole steps, "
-        f"{tuned['ms']:.3f} ms per step, lattice kernel alone {tuned['lattice_ms']:.3f} ms)")
+    if storage == "mom":   # moment storage has one schedule: the z-marching column tiles
+        tuned = {"best": {}, "cached": False}
+    else:
+        tuned = autotune.tune_step(cases, bodies, storage=storage)
+        log(f"batch: schedule {tuned['best']} ({'cached' if tuned['cached'] else 'tuned'} on whole steps, "
+            f"{tuned['ms']:.3f} ms per step, lattice kernel alone {tuned['lattice_ms']:.3f} ms)")
     S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), **tuned["best"])
     total_ms, k1_ms = timed_steps(S, torch, steps, 3)
     errs = [S.body_state(c, check=False)["err"] for c in range(len(cases))]
@@ -145,7 +148,7 @@ def batch_run(T, W, torch, steps, storage):
     torch.cuda.empty_cache()
     cells = sum(c["nx"] * c["ny"] * c["nz"] for c in cases)
     eb = T.ELEM_BYTES[T.STORAGE[storage]]
-    k1_gbps = 54 * eb * cells / (k1_ms * 1e-3) / 1e9
+    k1_gbps = 2 * (10 if storage == "mom" else 27) * eb * cells / (k1_ms * 1e-3) / 1e9
     return {"cases": len(cases), "cells": cells, "markers": int(sum(b["x_body"].shape[0] for b in bodies)),
             "steps": steps, "mlups": round(cells * steps / (total_ms * 1e-3) / 1e6, 1),
             "ms_per_step": round(total_ms / steps, 4), "k1_gbps": round(k1_gbps, 1),
@@ -702,6 +705,11 @@ def main():
         variants["batch64"] = b
         log(f"  batch: {b['mlups']:.0f} MLUPS, {b['ms_per_step']:.2f} ms/step, kernel {b['k1_gbps']:.0f} GB/s, "
             f"masked {b['masked_cases']}")
+        if args.storage == "f32":
+            bm = batch_run(T, W, torch, args.batch_steps, "mom")
+            variants["batch64_moments"] = bm
+            log(f"  batch, moment storage: {bm['mlups']:.0f} MLUPS, {bm['ms_per_step']:.2f} ms/step, "
+                f"masked {bm['masked_cases']}")
 
     if not args.no_variants and not args.no_learned:
         lr = learned_run(T, W, torch, args.storage)

@@ -6,7 +6,8 @@ reconstructed forced states) within 1e-5 relative, force and torque within
 momentum-exact variant, the force surface, and the paper's no-slip bottom
 with a constant-pressure top.  Also: agreement with population storage on
 the 48^3 sphere, the coupling beside the lattice kernel equal to the serial
-order, and checkpoint resume, both bitwise."""
+order, checkpoint resume, and several cases in one context equal to each
+case alone, all bitwise."""
 import os
 
 import numpy as np
@@ -116,3 +117,23 @@ def test_checkpoint_resume_is_bitwise(T, tmp_path):
     B.run(6)
     assert np.array_equal(A.populations(), B.populations())
     assert np.array_equal(A.body_state()["F"], B.body_state()["F"])
+
+
+def test_cases_in_one_context_equal_each_case_alone(T):
+    """Two cases of different sizes in one context (one with a particle and
+    the falling-frame window, one fluid-only between moving walls) give
+    bitwise the results of each case run alone: the moment tile table, the
+    forcing boxes and the ring offsets are per case."""
+    a_case, a_body = small_sphere(h_end=19.5 - 1e-6, h_ini=25.5, sponge=5)
+    b_case = W.make_case(40, 16, 36, 0.6, W.BC_NOSLIP, W.BC_NOSLIP, 0, u_wall=(-0.02, 0.03))
+    both = T.Solver([a_case, b_case], [a_body, None], storage="mom")
+    one_a = T.Solver([a_case], [a_body], storage="mom")
+    one_b = T.Solver([b_case], None, storage="mom")
+    for S in (both, one_a, one_b):
+        S.run(25)
+    assert np.array_equal(both.populations(0), one_a.populations(0))
+    assert np.array_equal(both.populations(1), one_b.populations(0))
+    sa, sb = both.body_state(0), one_a.body_state(0)
+    assert sa["shifts"] >= 1
+    for k in ("F", "T", "r", "v"):
+        assert np.array_equal(sa[k], sb[k]), k
