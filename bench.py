@@ -579,7 +579,7 @@ def main():
                          "beside it on a second stream")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(each case runs on a single MI355X); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

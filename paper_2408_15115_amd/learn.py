@@ -1,4 +1,4 @@
-"""Training driver of the learned warm start (orchestration only).
+"""Training loop of the learned warm start (orchestration only).
 
 Samples come from the solver's own plain runs (lbm_ibm_samples); the network
 is trained by the library's forward/backward kernels and Adam.  Features and
