@@ -455,7 +455,7 @@ def settling_table3(T, W, torch, D, res=TABLE3_RE, kappa=2.7, storage="f32"):
         cd_sim = 24.0 / re_sim if re < 1 else W.clift_gauvin_cd(re_sim)
         v_ref = math.sqrt(8.0 * Fg / (math.pi * D * D * cd_sim))
         Fd = float(np.mean(F))
-        row = {"re_target": re, "D": D, "storage": storage, "box": [case["nx"], case["ny"], case["nz"]],
+        row = {"re_target": re, "D": D, "kappa": kappa, "storage": storage, "box": [case["nx"], case["ny"], case["nz"]],
                "tau": round(case["tau"], 5),
                "steps": steps, "v_T_lattice": round(vT, 6), "re_simulated": round(re_sim, 3),
                "vT_over_clift_gauvin": round(vT / v_cg, 4),
@@ -570,6 +570,7 @@ def main():
     ap.add_argument("--settling-sweep", type=str, default=None,
                     help="comma-separated sphere diameters: run only the terminal-velocity resolution sweep")
     ap.add_argument("--no-stability", action="store_true")
+    ap.add_argument("--kappa", type=float, default=2.7, help="density ratio of the --table3 spheres")
     ap.add_argument("--lattice-rates", action="store_true",
                     help="run only the fluid-only lattice kernel comparison (D3Q27, D3Q19, moment storage)")
     ap.add_argument("--table3", type=str, default=None,
@@ -597,7 +598,7 @@ def main():
     if args.table3:
         d, _, rl = args.table3.partition(":")
         res = [float(r) for r in rl.split(",")] if rl else TABLE3_RE
-        rows = settling_table3(T, W, torch, int(d), res, storage=args.storage)
+        rows = settling_table3(T, W, torch, int(d), res, kappa=args.kappa, storage=args.storage)
         print(json.dumps({"metric": "sphere terminal velocity against Clift-Gauvin / Stokes across Re (Table 3)",
                           "data": "synthetic", "rows": rows}))
         return
