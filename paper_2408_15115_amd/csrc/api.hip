@@ -38,7 +38,8 @@ struct Plan {
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
         off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox,
-        off_mark, off_wt, off_dsh, aux_bytes;
+        off_mark, off_wt, off_dsh, off_rpop, aux_bytes;
+    long long xreg_cells = 0;   // moment storage: cells of all expanded regions (edge L + 2)
     int block = 256;
 };
 
@@ -261,6 +262,8 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         }
         d.reg_off = reg;
         reg += (long long)d.L * d.L * d.L;
+        d.xreg_off = P.xreg_cells;
+        if (d.M > 0) P.xreg_cells += (long long)(d.L + 2) * (d.L + 2) * (d.L + 2);
         P.maxL3 = std::max(P.maxL3, d.L * d.L * d.L);
         if (d.M > 0) P.max_slab = std::max(P.max_slab, d.dz * k.nx * k.ny);
         P.max_tiles += (d.cells + 63) / 64;
@@ -304,6 +307,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_dSo = take(sizeof(double) * M);
     P.off_wt = take(sizeof(double) * 12 * M);
     P.off_dsh = take(sizeof(float) * 4 * std::max<long long>(reg, 1));
+    P.off_rpop = take(sizeof(float) * Q * std::max<long long>(mom ? P.xreg_cells : 0, 1));
     P.off_mtiles = take(sizeof(MarkerTile) * NT);
     P.off_tbox = take(sizeof(TileBox) * NT);
     P.aux_bytes = o;
@@ -444,6 +448,8 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.mark = (unsigned char *)(a + P.off_mark);
     p.wt = (double *)(a + P.off_wt);
     p.dsh = (float *)(a + P.off_dsh);
+    p.rpop = (float *)(a + P.off_rpop);
+    p.xstride = std::max<long long>(P.xreg_cells, 1);
     p.mtiles = (MarkerTile *)(a + P.off_mtiles);
     p.feat = (float *)(a + P.off_feat);
     p.h0 = (double *)(a + P.off_h0);

@@ -23,6 +23,7 @@ struct CaseDev {
     double h_ini, h_end;
     double force_offset;    // 0: stress integral at the markers; > 0: on the parallel surface
     float uw_lo, uw_hi;     // x velocity of a no-slip bottom / top wall
+    long long xreg_off;     // moment storage: cell offset of the case's expanded region (edge L + 2)
 };
 
 // Dynamic FP64 rigid-body state of one case plus the ring origin and region
@@ -114,6 +115,8 @@ struct DevPtrs {
     double *dSo;     // per-marker areas of the parallel force surface (cases with force_offset > 0)
     TileBox *tbox;   // per-tile box, computed each step by k_markers
     float *dsh;      // moment storage: per region cell the forcing shift (Delta_x, Delta_y, Delta_z, lambda)
+    float *rpop;     // moment storage: collided populations of the region and a one-cell rim, [27][xstride]
+    long long xstride;
 };
 
 // ---------------------------------------------------------------- launchers

@@ -135,47 +135,69 @@ struct CodecMom {
     using T = float;
 };
 
-// The pull of pull() on moment storage: population dir of each source cell,
-// evaluated from that cell's stored state (and its forcing shift), with the
-// same z wall rules.
-__device__ inline void pull_mom(const float *__restrict__ src, const CaseDev &cd, const mom::ShiftBox &sb, int z0,
-                                int x, int y, int z, float g[Q])
+// Moment storage, first pass of the region gather: the collided populations
+// (forcing shifts included) of every cell of the particle region and a
+// one-cell rim, edge E = L + 2, into rpop.  Rim planes beyond a z wall are
+// never pulled and are left alone.
+__global__ void k_region_expand_mom(const float *__restrict__ src, DevPtrs p)
 {
-    const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
-#pragma unroll 1
-    for (int i = 0; i < Q; i++) {
-        const int ex = cx(i), ey = cy(i), ez = cz(i);
-        int sx = x - ex, sy = y - ey, sz = z - ez;
-        sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
-        sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+    const int c = blockIdx.y;
+    const CaseDev cd = p.cases[c];
+    const BodyView B = body_view(p.body[c]);
+    if (cd.M == 0 || B.err != 0) return;
+    const int E = cd.L + 2, E3 = E * E * E;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= E3) return;
+    const int a = q % E, b = (q / E) % E, cc = q / (E * E);
+    int z = B.org[2] - 1 + cc;
+    if (z < 0 || z >= cd.nz) {
+        if (cd.bc_lo != BC_PERIODIC) return;
+        z = wrapi(z, cd.nz);
+    }
+    const int x = wrapi(B.org[0] - 1 + a, cd.nx), y = wrapi(B.org[1] - 1 + b, cd.ny);
+    int slot = z + B.z0;
+    if (slot >= cd.nz) slot -= cd.nz;
+    const float *sp = src + cd.pop_off + ((long long)slot * cd.ny + y) * cd.nx + x;
+    float m[10], sh[4], out[Q];
+#pragma unroll
+    for (int k = 0; k < 10; k++) m[k] = sp[k * cd.plane];
+    (void)mom::shift_at(mom::shift_box(p, cd, p.body[c]), cd.nx, cd.ny, cd.nz, x, y, slot, sh);
+    mom::expand(m, sh, out);
+    float *dst = p.rpop + cd.xreg_off + q;
+#pragma unroll
+    for (int i = 0; i < Q; i++) dst[i * p.xstride] = out[i];
+}
+
+// Second pass: the pull of pull() from the expanded region, for region cell
+// (a, b, cc) at physical height z, with the same z wall rules.
+__device__ inline void pull_region(const DevPtrs &p, const CaseDev &cd, int a, int b, int cc, int z, float g[Q])
+{
+    const int E = cd.L + 2;
+    const float *R = p.rpop + cd.xreg_off;
+    const int wlo = z == 0 && cd.bc_lo != BC_PERIODIC, whi = z == cd.nz - 1 && cd.bc_hi != BC_PERIODIC;
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        int sa = a + 1 - cx(i), sb = b + 1 - cy(i), sc = cc + 1 - cz(i);
         int dir = i;
         float sign = 1.0f, add = 0.0f;
-        const bool out_lo = sz < 0, out_hi = sz >= nz;
-        const int bc = out_lo ? cd.bc_lo : (out_hi ? cd.bc_hi : BC_PERIODIC);
-        if ((out_lo || out_hi) && bc != BC_PERIODIC) {
-            sz = z;
-            if (bc == BC_FREESLIP) {
-                dir = 9 * (-ez + 1) + 3 * (ey + 1) + (ex + 1);
-            } else {
-                dir = Q - 1 - i;
-                sx = x;
-                sy = y;
-                if (bc == BC_PRESSURE) sign = -1.0f;
-                else add = (float)(6.0 * wq(i) * ex) * (out_lo ? cd.uw_lo : cd.uw_hi);
+        if constexpr (cz(i) != 0) {
+            const bool wall = cz(i) == 1 ? wlo : whi;
+            const int bc = cz(i) == 1 ? cd.bc_lo : cd.bc_hi;
+            if (wall) {
+                sc = cc + 1;
+                if (bc == BC_FREESLIP) {
+                    dir = mirror_z(i);
+                } else {
+                    dir = opposite(i);
+                    sa = a + 1;
+                    sb = b + 1;
+                    if (bc == BC_PRESSURE) sign = -1.0f;
+                    else if constexpr (cx(i) != 0) add = (float)(6.0 * wq(i) * cx(i)) * (cz(i) == 1 ? cd.uw_lo : cd.uw_hi);
+                }
             }
-        } else {
-            sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
         }
-        int slot = sz + z0;
-        if (slot >= nz) slot -= nz;
-        const float *sp = src + ((long long)slot * ny + sy) * nx + sx;
-        float m[10], sh[4], A[Q];
-#pragma unroll
-        for (int c = 0; c < 10; c++) m[c] = sp[c * cd.plane];
-        (void)mom::shift_at(sb, nx, ny, nz, sx, sy, slot, sh);
-        mom::state_coeffs(m, sh, A);
-        g[i] = sign * mom::population(A, dir) + add;
-    }
+        g[i] = sign * R[dir * p.xstride + ((long long)sc * E + sb) * E + sa] + add;
+    });
 }
 
 // ------------------------------------------------------------ region fields
@@ -213,7 +235,7 @@ __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs 
     const int gx = wrapi(B.org[0] + a, cd.nx), gy = wrapi(B.org[1] + b, cd.ny);
     float g[Q];
     if constexpr (std::is_same<CD, CodecMom>::value)
-        pull_mom(src + cd.pop_off, cd, mom::shift_box(p, cd, p.body[c]), B.z0, gx, gy, gz, g);
+        pull_region(p, cd, a, b, cc, gz, g);
     else
         pull<CD>(src + cd.pop_off, cd.plane, cd.nx, cd.ny, cd.nz, B.z0, cd.bc_lo, cd.bc_hi, cd.uw_lo, cd.uw_hi, gx, gy,
                  gz, g);
@@ -1267,6 +1289,12 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     const dim3 tile_grid((n_mtiles + 7) / 8 * 8);
     const dim3 mark_grid((Mtot + 255) / 256);
     hipLaunchKernelGGL(k_markers, tile_grid, dim3(64), 0, s, p, n_mtiles);
+    if constexpr (std::is_same<CD, CodecMom>::value) {
+        int L = 1;
+        while ((long long)L * L * L < maxL3) L++;
+        const long long E3 = (long long)(L + 2) * (L + 2) * (L + 2);
+        hipLaunchKernelGGL(k_region_expand_mom, dim3((unsigned)((E3 + 255) / 256), n_cases), blk, 0, s, (const T *)prev, p);
+    }
     hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
     // plain start with at most kHBufs cycles: each cycle's spread rides on
     // the pass before it (force + spread 1, update c + spread c + 1)

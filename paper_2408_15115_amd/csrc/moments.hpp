@@ -50,26 +50,6 @@ __device__ __forceinline__ void expand(const float m[10], const float sh[4], flo
     hermite_to_populations(A, out);
 }
 
-// One population, direction i (runtime), from the coefficients: the product
-// of the three one-dimensional factors e0 = 1, e1(-1,0,1) = (-3, 0, 3),
-// e2(-1,0,1) = (3, -1.5, 3), times w_i.
-__device__ __forceinline__ float population(const float A[Q], int i)
-{
-    const int c[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
-    float e[3][3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        e[d][0] = 1.0f;
-        e[d][1] = 3.0f * (float)c[d];
-        e[d][2] = c[d] == 0 ? -1.5f : 3.0f;
-    }
-    float s = 0.0f;
-#pragma unroll
-    for (int m = 0; m < Q; m++) s += A[m] * e[0][m % 3] * e[1][(m / 3) % 3] * e[2][m / 9];
-    const float w1[3] = {1.0f / 6.0f, 2.0f / 3.0f, 1.0f / 6.0f};
-    return s * w1[c[0] + 1] * w1[c[1] + 1] * w1[c[2] + 1];
-}
-
 // Collide: raw moments of the pulled deviations -> the stored post-collision state.
 __device__ __forceinline__ void collide_to_moments(const Moments &rm, float om, float m[10], bool &bad)
 {
