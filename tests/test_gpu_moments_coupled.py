@@ -7,7 +7,8 @@ momentum-exact variant, the force surface, and the paper's no-slip bottom
 with a constant-pressure top.  Also: agreement with population storage on
 the 48^3 sphere, the coupling beside the lattice kernel equal to the serial
 order, checkpoint resume, and several cases in one context equal to each
-case alone, all bitwise."""
+case alone, all bitwise; and the benchmark's full-size case against
+population storage."""
 import os
 
 import numpy as np
@@ -137,3 +138,29 @@ def test_cases_in_one_context_equal_each_case_alone(T):
     assert sa["shifts"] >= 1
     for k in ("F", "T", "r", "v"):
         assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_full_size_case_matches_population_storage(T):
+    """The benchmark's case at full size (256 x 256 x 768, 12,252 markers,
+    free-slip walls, sponge), 60 coupled steps in the bench's launch
+    configuration: force, torque and body velocity of moment storage against
+    population storage (itself checked against the oracle at full size)."""
+    import torch
+    case, body = W.case_ellipsoid_tall()
+    st = {}
+    for storage in ("f32", "mom"):
+        say(f"full-size ellipsoid case, 60 steps, {storage}")
+        S = T.Solver([case], [body], storage=storage, stream=torch.cuda.Stream())
+        S.run(60)
+        st[storage] = S.body_state()
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+    a, b = st["mom"], st["f32"]
+    Fs, Ts = np.linalg.norm(b["F"]), np.linalg.norm(b["T"])
+    say(f"  force {np.max(np.abs(a['F'] - b['F'])) / Fs:.3e}, torque {np.max(np.abs(a['T'] - b['T'])) / Ts:.3e}, "
+        f"v {np.max(np.abs(a['v'] - b['v'])) / np.linalg.norm(b['v']):.3e}")
+    assert np.max(np.abs(a["F"] - b["F"])) < 1e-4 * Fs
+    assert np.max(np.abs(a["T"] - b["T"])) < 1e-4 * max(Ts, 16.0 * Fs)   # torque arm: the semi-axis
+    assert np.max(np.abs(a["v"] - b["v"])) < 1e-5 * np.linalg.norm(b["v"])
+    assert a["err"] == 0 and b["err"] == 0
