@@ -5,9 +5,10 @@
 // given by ten numbers.  Stored per cell (FP32, SoA [10][nz][ny][nx]):
 //   m0 = rho - 1,  m1..3 = rho u,  m4..9 = (1 - 1/tau) P1 as xx, yy, zz, xy, xz, yz.
 // The step reads 40 bytes and writes 40 bytes per cell instead of 27 + 27
-// populations.  Fluid-only, periodic in x and y; z periodic or bounded by the
-// walls of the lattice kernel (free-slip, no-slip at rest or moving in x,
-// constant pressure).
+// populations.  Periodic in x and y; z periodic or bounded by the walls of the
+// lattice kernel (free-slip, no-slip at rest or moving in x, constant
+// pressure).  Cells forced in the last step carry their equilibrium shift in
+// the forcing box of their case (moments.hpp); the expansion applies it.
 //
 // The step marches in z.  A workgroup owns a column of MX x MY cells and a
 // chunk of LZ output planes.  For each plane it expands the stored moments of
