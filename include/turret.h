@@ -187,8 +187,11 @@ typedef struct {
 } lbm_options;
 
 /* Caller-owned device buffers (byte sizes from lbm_required_bytes):
- *   pop_a, pop_b  the two population buffers (ping-pong)
- *   aux           descriptors, body states, markers, IBM region fields */
+ *   pop_a, pop_b  the two population buffers (ping-pong); with LBM_MOM they hold
+ *                 the ten moment planes per case instead
+ *   aux           descriptors, body states, markers, IBM region fields; with
+ *                 LBM_MOM also the forcing shifts of the particle region and its
+ *                 collided populations (region plus a one-cell rim) */
 typedef struct {
     void *pop_a;
     void *pop_b;
