@@ -338,7 +338,7 @@ def settling_run(T, W, torch, steps=8000):
     return out
 
 
-def settling_sweep(T, W, torch, diameters, re=5.0, offsets=(0.0, 3.0), domain="paper"):
+def settling_sweep(T, W, torch, diameters, re=5.0, offsets=(0.0, 3.0), domain="paper", storage="f32"):
     """Sphere terminal velocity over the Clift-Gauvin value against resolution:
     spheres of diameter D cells (kappa 2.7, Re `re`) settling from rest in the
     w* = 10, h* = 30 box of the paper's low-Re cases (no-slip bottom,
@@ -351,7 +351,7 @@ def settling_sweep(T, W, torch, diameters, re=5.0, offsets=(0.0, 3.0), domain="p
         steps = int(500 * D)
         for off in offsets:
             case, body, v_t = W.case_sphere_settling(float(D), re, 2.7, force_offset=off, domain=domain)
-            S = T.Solver([case], [body], stream=torch.cuda.Stream())
+            S = T.Solver([case], [body], stream=torch.cuda.Stream(), storage=storage)
             chunk = 250
             nch = steps // chunk
             tail = max(8, nch // 4)
@@ -371,7 +371,8 @@ def settling_sweep(T, W, torch, diameters, re=5.0, offsets=(0.0, 3.0), domain="p
             del S
             torch.cuda.empty_cache()
             cells = case["nx"] * case["ny"] * case["nz"]
-            row = {"D": D, "re": re, "force_offset": off, "domain": domain, "box": [case["nx"], case["ny"], case["nz"]],
+            row = {"D": D, "re": re, "force_offset": off, "domain": domain, "storage": storage,
+                   "box": [case["nx"], case["ny"], case["nz"]],
                    "markers": int(body["x_body"].shape[0]), "steps": steps, "tau": round(case["tau"], 5),
                    "vT_over_clift_gauvin": round(float(np.mean(v)), 4), "drift": round(float(np.ptp(v)), 4),
                    "window_shifts": int(st["shifts"]), "mlups": round(cells * steps / dt / 1e6, 1)}
@@ -569,6 +570,8 @@ def main():
     ap.add_argument("--no-settling", action="store_true")
     ap.add_argument("--settling-sweep", type=str, default=None,
                     help="comma-separated sphere diameters: run only the terminal-velocity resolution sweep")
+    ap.add_argument("--sweep-offsets", type=str, default="0,3",
+                    help="force-surface offsets of the --settling-sweep runs")
     ap.add_argument("--no-stability", action="store_true")
     ap.add_argument("--kappa", type=float, default=2.7, help="density ratio of the --table3 spheres")
     ap.add_argument("--lattice-rates", action="store_true",
@@ -603,7 +606,8 @@ def main():
                           "data": "synthetic", "rows": rows}))
         return
     if args.settling_sweep:
-        rows = settling_sweep(T, W, torch, [int(d) for d in args.settling_sweep.split(",")])
+        rows = settling_sweep(T, W, torch, [int(d) for d in args.settling_sweep.split(",")],
+                              offsets=tuple(float(o) for o in args.sweep_offsets.split(",")), storage=args.storage)
         print(json.dumps({"metric": "sphere terminal velocity / Clift-Gauvin against resolution",
                           "data": "synthetic", "rows": rows}))
         return
