@@ -128,7 +128,9 @@ typedef struct {
  *               rounding.  A forced cell (Sec. 2.2) keeps its equilibrium
  *               shift tau h beside the moments for the next step, in a box over
  *               the particle region.  Lattice 27, collision 0 and schedule 0
- *               only.  lbm_get_populations returns
+ *               only.  lbm_get_populations / lbm_set_populations then allocate
+ *               a temporary device buffer of one case's 27 planes for the call
+ *               (the step calls allocate nothing).  lbm_get_populations returns
  *               the reconstructed populations; lbm_set_populations keeps the
  *               regularized part of what it is given (exact for a
  *               post-collision state of this collision)
