@@ -595,7 +595,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.lattice_rates:
-        print(json.dumps({"metric": "fluid-only lattice kernel rates", "data": "synthetic",
+        # the plain copy in the same run calibrates counter-based traffic figures
+        copy = None if args.no_copy else round(copy_bandwidth(T, torch), 1)
+        print(json.dumps({"metric": "fluid-only lattice kernel rates", "data": "synthetic", "copy_GBps": copy,
                           "rows": lattice_rate_run(T, W, torch, steps=args.steps)}))
         return
     if args.table3:
