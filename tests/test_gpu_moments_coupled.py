@@ -7,8 +7,8 @@ momentum-exact variant, the force surface, and the paper's no-slip bottom
 with a constant-pressure top.  Also: agreement with population storage on
 the 48^3 sphere, the coupling beside the lattice kernel equal to the serial
 order, checkpoint resume, and several cases in one context equal to each
-case alone, all bitwise; and the benchmark's full-size case against
-population storage."""
+case alone, and graph replay against eager steps, all bitwise; the gated
+warm start and the benchmark's full-size case against population storage."""
 import os
 
 import numpy as np
@@ -187,3 +187,29 @@ def test_warm_started_coupling_matches_population_storage(T):
         f"force {np.max(np.abs(bm['F'] - bf['F'])) / Fs:.3e}")
     assert max_rel(pm, pf) < 1e-5
     assert np.max(np.abs(bm["F"] - bf["F"])) < 1e-4 * Fs
+
+
+def test_graph_replay_equals_eager(T):
+    """Moment storage under captured graphs (the benchmark's launch form): every
+    replay equals the eager steps bitwise, with eager work and a
+    synchronization between replays (the forcing box is written by kernels,
+    never by memset nodes)."""
+    import torch
+    case, body = small_sphere(h_end=19.5 - 1e-6, h_ini=25.5, sponge=5)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        A = T.Solver([case], [body], storage="mom", stream=stream)
+        B = T.Solver([case], [body], storage="mom", stream=stream)
+        A.run(2)
+        B.graph_capture(2)
+        B.graph_launch()
+        stream.synchronize()
+        assert np.array_equal(A.populations(), B.populations())
+        for _ in range(4):
+            A.run(2)
+            B.graph_launch()
+            _ = torch.zeros(1000, device="cuda").sum().item()
+            assert np.array_equal(A.populations(), B.populations())
+            sa, sb = A.body_state(), B.body_state()
+            assert np.array_equal(sa["F"], sb["F"]) and np.array_equal(sa["r"], sb["r"])
+        assert A.body_state()["shifts"] >= 1
