@@ -51,9 +51,11 @@ def heavy_sphere_transient(T, D, relax=4.0, every=500, tag=None):
     steps = int(relax * t_relax) // every * every
     S = T.Solver([case], [body])
     v = [0.0]
-    for _ in range(steps // every):
+    for k in range(steps // every):
         S.run(every)
         v.append(-S.body_state()["v"][2])
+        if (k + 1) % 100 == 0:
+            say(f"  heavy sphere D {D}: step {(k + 1) * every} of {steps}, v_z {v[-1]:.5f}")
     S.close()
     t = np.arange(0, steps + 1, every, dtype=float)
     v = np.array(v)
