@@ -80,6 +80,7 @@ def lib():
         L.orc_sim_free.argtypes = [C.c_void_p]
         L.orc_sim_set_force_surface.argtypes = [C.c_void_p, d, pd]
         L.orc_sim_set_torque.argtypes = [C.c_void_p, pd]
+        L.orc_sim_set_fluid_force.argtypes = [C.c_void_p, pd]
         L.orc19_lattice.argtypes = [pi, pd]
         L.orc19_feq.argtypes = [d, pd, pd]
         L.orc19_f1.argtypes = [pd, pd, pd]
@@ -327,6 +328,13 @@ class OracleSim:
             dSo = _f64(body["dS_offset"])
             self._keep = self._keep + (dSo,)
             L.orc_sim_set_force_surface(self._p, float(body["force_offset"]), _pd(dSo))
+
+    def set_fluid_force(self, g):
+        """A uniform force per unit mass on the whole fluid, added to the
+        immersed force in every collision."""
+        gf = _f64(g)
+        self._keep = self._keep + (gf,)
+        lib().orc_sim_set_fluid_force(self._p, _pd(gf))
 
     def __del__(self):
         if getattr(self, "_p", None):

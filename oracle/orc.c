@@ -616,6 +616,8 @@ typedef struct {
     double force_offset;           /* 0: stress integral at the markers; > 0: on the parallel
                                       surface X_k + force_offset n_k, areas dSo */
     double *dSo;
+    double gf[3];                  /* uniform fluid force added to h_imm in the collision */
+    double *htot;                  /* h_imm + gf when gf is set */
     int64_t shifts, steps;
     int err;
 } orc_sim;
@@ -702,13 +704,34 @@ void orc_sim_set_force_surface(orc_sim *S, double delta, const double *dSo)
     }
 }
 
+/* A uniform force per unit mass on the fluid (a mean pressure gradient in a
+ * periodic box).  It enters the forced rule of Sec. 2.2 exactly like the
+ * immersed force: the collision evaluates f^(0) at u + tau (h_imm + gf). */
+void orc_sim_set_fluid_force(orc_sim *S, const double *gf)
+{
+    size_t n = (size_t)S->D.nx * S->D.ny * S->D.nz;
+    for (int a = 0; a < 3; a++) S->gf[a] = gf[a];
+    if (!S->htot) S->htot = (double *)malloc(3 * n * sizeof(double));
+}
+
 void orc_sim_free(orc_sim *S)
 {
     if (!S) return;
     free(S->f); free(S->C); free(S->h); free(S->sig); free(S->uu); free(S->need);
     free(S->xb); free(S->nb); free(S->dS); free(S->X); free(S->N); free(S->U);
-    free(S->hk); free(S->tmp); free(S->dSo);
+    free(S->hk); free(S->tmp); free(S->dSo); free(S->htot);
     free(S);
+}
+
+/* The force field the collision applies: h_imm, plus the uniform fluid force
+ * when one is set. */
+static const double *forcing_field(orc_sim *S)
+{
+    if (!S->htot) return S->h;
+    size_t n = (size_t)S->D.nx * S->D.ny * S->D.nz;
+    for (size_t c = 0; c < n; c++)
+        for (int a = 0; a < 3; a++) S->htot[3 * c + a] = S->h[3 * c + a] + S->gf[a];
+    return S->htot;
 }
 
 void orc_sim_set_f(orc_sim *S, const double *f)
@@ -756,7 +779,7 @@ static void shift_post_collision(orc_sim *S, double *C)
  * steps. */
 void orc_sim_get_post_collision(orc_sim *S, double *C)
 {
-    collide_grid(&S->D, S->f, S->h, C);
+    collide_grid(&S->D, S->f, forcing_field(S), C);
     if (S->pending) {
         int keep = S->pending;
         shift_post_collision(S, C);
@@ -899,7 +922,7 @@ static void ibm(orc_sim *S)
 int32_t orc_sim_step(orc_sim *S, int32_t nsteps)
 {
     for (int s = 0; s < nsteps; s++) {
-        collide_grid(&S->D, S->f, S->h, S->C);
+        collide_grid(&S->D, S->f, forcing_field(S), S->C);
         if (S->pending) shift_post_collision(S, S->C);
         stream_grid(&S->D, S->C, S->f);
         body_advance(&S->B, S->F, S->T);
