@@ -21,6 +21,7 @@ SRC19_PATH = os.path.join(_HERE, "orc19.c")     # the D3Q19 comparison lattice
 _OVERRIDE = os.environ.get("ORACLE_LIB_OVERRIDE")
 
 BC_PERIODIC, BC_FREESLIP, BC_NOSLIP, BC_PRESSURE = 0, 1, 2, 3
+STORAGE = {"f64": 0, "f32": 0, "f16": 1, "bf16": 2}   # stored-state precision of the oracle (f32: not modelled)
 
 
 def build(force: bool = False) -> str:
@@ -81,6 +82,10 @@ def lib():
         L.orc_sim_set_force_surface.argtypes = [C.c_void_p, d, pd]
         L.orc_sim_set_torque.argtypes = [C.c_void_p, pd]
         L.orc_sim_set_fluid_force.argtypes = [C.c_void_p, pd]
+        L.orc_sim_set_storage.argtypes = [C.c_void_p, i32, d]
+        L.orc_round_format.argtypes = [d, i32]
+        L.orc_round_format.restype = d
+        L.orc_quantize.argtypes = [i32, C.c_int64, pd]
         L.orc19_lattice.argtypes = [pi, pd]
         L.orc19_feq.argtypes = [d, pd, pd]
         L.orc19_f1.argtypes = [pd, pd, pd]
@@ -170,6 +175,19 @@ def phi(r):
 
 def tau_at(nz, tau0, sponge, z):
     return lib().orc_tau_at(int(nz), float(tau0), int(sponge), int(z))
+
+
+def round_format(x, storage):
+    """x rounded to the nearest binary16 / bfloat16 value (ties to even)."""
+    return lib().orc_round_format(float(x), STORAGE[storage])
+
+
+def quantize(f, storage):
+    """Populations (..., 27) as the reduced-precision store holds them:
+    w_i + q(s_i (f_i - w_i)) / s_i with s_i = 4096 / w_i."""
+    f = np.array(f, np.float64, order="C")
+    lib().orc_quantize(STORAGE[storage], f.size // 27, _pd(f))
+    return f
 
 
 # ------------------------------------------------------------- grid ops
@@ -328,6 +346,12 @@ class OracleSim:
             dSo = _f64(body["dS_offset"])
             self._keep = self._keep + (dSo,)
             L.orc_sim_set_force_surface(self._p, float(body["force_offset"]), _pd(dSo))
+
+    def set_storage(self, storage, keep_box=0.0):
+        """Store the post-collision state in "f16" or "bf16" (the build's
+        precision form); keep_box > 0 leaves the cells within that max-norm
+        distance of the body centre in FP64."""
+        lib().orc_sim_set_storage(self._p, STORAGE[storage], float(keep_box))
 
     def set_fluid_force(self, g):
         """A uniform force per unit mass on the whole fluid, added to the

@@ -311,6 +311,56 @@ double orc_phi(double r)
     return 0.0;
 }
 
+/* ------------------------------------------- storage quantization (build)
+ * The precision form of the build stores each population as s_i (f_i - w_i),
+ * s_i = 4096 / w_i, in IEEE binary16 or in bfloat16, rounded to nearest with
+ * ties to even.  The paper has no reduced-precision storage; this models the
+ * stored state so that the GPU's reduced-precision path can be compared
+ * element by element.  A value of a binary format with p significand bits
+ * (the leading one included), smallest normal exponent emin and largest
+ * finite value vmax is an integer multiple of 2^(E - p + 1), where E is the
+ * exponent of its leading bit, clamped at emin below (subnormals); rounding
+ * to that grid with nearbyint under the default rounding mode rounds ties to
+ * even, and a rounded magnitude above vmax overflows to infinity. */
+static double round_to_format(double x, int p, int emin, double vmax)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    (void)frexp(fabs(x), &e);          /* |x| in [2^(e-1), 2^e) */
+    int E = e - 1;
+    if (E < emin) E = emin;
+    const double ulp = ldexp(1.0, E - (p - 1));
+    const double r = nearbyint(x / ulp) * ulp;
+    if (fabs(r) > vmax) return copysign(INFINITY, x);
+    return r;
+}
+
+enum { STORE_F64 = 0, STORE_F16 = 1, STORE_BF16 = 2 };
+
+double orc_round_format(double x, int32_t storage)
+{
+    if (storage == STORE_F16) return round_to_format(x, 11, -14, 65504.0);
+    if (storage == STORE_BF16) return round_to_format(x, 8, -126, ldexp(255.0, 120));
+    return x;
+}
+
+/* One population as the stored state keeps it: w_i + q(s_i (f_i - w_i)) / s_i. */
+static double quantize_pop(double f, int i, int32_t storage)
+{
+    const double s = 4096.0 / g_w[i];
+    return g_w[i] + orc_round_format(s * (f - g_w[i]), storage) / s;
+}
+
+/* The same on a whole field of n cells (layout cell*27 + i). */
+void orc_quantize(int32_t storage, int64_t n, double *f)
+{
+    orc_init();
+    if (storage == STORE_F64) return;
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; c++)
+        for (int i = 0; i < Q; i++) f[Q * c + i] = quantize_pop(f[Q * c + i], i, storage);
+}
+
 /* ------------------------------------------------------------- domain */
 
 enum { BC_PERIODIC = 0, BC_FREESLIP = 1, BC_NOSLIP = 2, BC_PRESSURE = 3 };
@@ -617,6 +667,8 @@ typedef struct {
                                       surface X_k + force_offset n_k, areas dSo */
     double *dSo;
     double gf[3];                  /* uniform fluid force added to h_imm in the collision */
+    int storage;                   /* STORE_*: precision of the stored post-collision state */
+    double keep_box;               /* > 0: cells within this distance (max norm) of r keep FP64 */
     double *htot;                  /* h_imm + gf when gf is set */
     int64_t shifts, steps;
     int err;
@@ -714,6 +766,42 @@ void orc_sim_set_fluid_force(orc_sim *S, const double *gf)
     if (!S->htot) S->htot = (double *)malloc(3 * n * sizeof(double));
 }
 
+/* Reduced-precision storage of the post-collision state (the build's
+ * precision form): after each collision every population is replaced by the
+ * value the stored format holds.  keep_box > 0 exempts the cells within that
+ * max-norm distance of the body's centre, which then stay FP64. */
+void orc_sim_set_storage(orc_sim *S, int32_t storage, double keep_box)
+{
+    S->storage = storage;
+    S->keep_box = keep_box;
+}
+
+static void quantize_state(orc_sim *S, double *C)
+{
+    if (S->storage == STORE_F64) return;
+    const dom_t *D = &S->D;
+    #pragma omp parallel for schedule(static)
+    for (int z = 0; z < D->nz; z++)
+        for (int y = 0; y < D->ny; y++)
+            for (int x = 0; x < D->nx; x++) {
+                if (S->keep_box > 0.0) {
+                    const double p[3] = {x, y, z};
+                    double dmax = 0.0;
+                    for (int a = 0; a < 3; a++) {
+                        double d = fabs(p[a] - S->B.r[a]);
+                        if (a < 2) {
+                            const double n = a == 0 ? D->nx : D->ny;
+                            if (n - d < d) d = n - d;    /* periodic distance */
+                        }
+                        if (d > dmax) dmax = d;
+                    }
+                    if (dmax <= S->keep_box) continue;
+                }
+                const size_t c = cell(D, x, y, z);
+                for (int i = 0; i < Q; i++) C[Q * c + i] = quantize_pop(C[Q * c + i], i, S->storage);
+            }
+}
+
 void orc_sim_free(orc_sim *S)
 {
     if (!S) return;
@@ -780,6 +868,7 @@ static void shift_post_collision(orc_sim *S, double *C)
 void orc_sim_get_post_collision(orc_sim *S, double *C)
 {
     collide_grid(&S->D, S->f, forcing_field(S), C);
+    quantize_state(S, C);
     if (S->pending) {
         int keep = S->pending;
         shift_post_collision(S, C);
@@ -923,6 +1012,7 @@ int32_t orc_sim_step(orc_sim *S, int32_t nsteps)
 {
     for (int s = 0; s < nsteps; s++) {
         collide_grid(&S->D, S->f, forcing_field(S), S->C);
+        quantize_state(S, S->C);
         if (S->pending) shift_post_collision(S, S->C);
         stream_grid(&S->D, S->C, S->f);
         body_advance(&S->B, S->F, S->T);
