@@ -14,7 +14,8 @@
  *     [27][nz][ny][nx] starts at element offset pop_offset(c) of each of the
  *     two population buffers.  The z index is a ring: physical row z lives at
  *     slot (z + z0) mod nz, z0 being moved by window_shift.  FP16/BF16 storage
- *     keeps s_i * g_i with s_i = 4096 / w_i.
+ *     keeps s_i * g_i with s_i = 2^(14 + 2 |xi_i|^2) (the first power of two
+ *     at or above 4096 / w_i), rounded to nearest even.
  *   - Every call returns LBM_OK (0) or a negative LBM_E* code; no C++
  *     exception crosses the boundary.  lbm_last_error() gives the message.
  *   - Ownership: the caller allocates all device memory (sizes from

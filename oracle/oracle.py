@@ -184,7 +184,7 @@ def round_format(x, storage):
 
 def quantize(f, storage):
     """Populations (..., 27) as the reduced-precision store holds them:
-    w_i + q(s_i (f_i - w_i)) / s_i with s_i = 4096 / w_i."""
+    w_i + q(s_i (f_i - w_i)) / s_i with s_i = 2^(14 + 2 |xi_i|^2)."""
     f = np.array(f, np.float64, order="C")
     lib().orc_quantize(STORAGE[storage], f.size // 27, _pd(f))
     return f

@@ -312,9 +312,10 @@ double orc_phi(double r)
 }
 
 /* ------------------------------------------- storage quantization (build)
- * The precision form of the build stores each population as s_i (f_i - w_i),
- * s_i = 4096 / w_i, in IEEE binary16 or in bfloat16, rounded to nearest with
- * ties to even.  The paper has no reduced-precision storage; this models the
+ * The precision form of the build stores each population as s_i (f_i - w_i)
+ * in IEEE binary16 or in bfloat16, rounded to nearest with ties to even;
+ * s_i = 2^(14 + 2 |xi_i|^2), the first power of two at or above 4096 / w_i,
+ * so that scaling by it is exact.  The paper has no reduced-precision storage; this models the
  * stored state so that the GPU's reduced-precision path can be compared
  * element by element.  A value of a binary format with p significand bits
  * (the leading one included), smallest normal exponent emin and largest
@@ -347,7 +348,8 @@ double orc_round_format(double x, int32_t storage)
 /* One population as the stored state keeps it: w_i + q(s_i (f_i - w_i)) / s_i. */
 static double quantize_pop(double f, int i, int32_t storage)
 {
-    const double s = 4096.0 / g_w[i];
+    const int n2 = g_xi[i][0] * g_xi[i][0] + g_xi[i][1] * g_xi[i][1] + g_xi[i][2] * g_xi[i][2];
+    const double s = ldexp(1.0, 14 + 2 * n2);
     return g_w[i] + orc_round_format(s * (f - g_w[i]), storage) / s;
 }
 

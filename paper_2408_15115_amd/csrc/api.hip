@@ -746,7 +746,7 @@ static double lattice_weight(int q, int i)
 
 static float host_dec(int storage, const void *raw, size_t idx, int i)
 {
-    const double inv = wq(i) / kScaleBase;
+    const double inv = 1.0 / store_scale(i);
     if (storage == LBM_F32) return ((const float *)raw)[idx];
     if (storage == LBM_F16) return (float)((const _Float16 *)raw)[idx] * (float)inv;
     uint32_t u = (uint32_t)((const uint16_t *)raw)[idx] << 16;

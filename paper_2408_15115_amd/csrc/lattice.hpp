@@ -41,12 +41,15 @@ __host__ __device__ constexpr double wq(int i) { return w1d(cx(i)) * w1d(cy(i)) 
 __host__ __device__ constexpr int mirror_z(int i) { return 9 * (-cz(i) + 1) + 3 * (cy(i) + 1) + (cx(i) + 1); }
 __host__ __device__ constexpr int opposite(int i) { return 26 - i; }
 
-// FP16/BF16 storage keeps s_i * g_i with s_i = 4096 / w_i: g_i / w_i is
-// O(|u|), so stored magnitudes sit well inside the FP16 normal range and the
-// rest state is exactly 0.  Mirror and opposite directions share w_i, so
-// wall rules never change the scale.
-constexpr double kScaleBase = 4096.0;
-__host__ __device__ constexpr double store_scale(int i) { return kScaleBase / wq(i); }
+// FP16/BF16 storage keeps s_i * g_i with the power of two
+// s_i = 2^(14 + 2 |xi_i|^2), the first power of two at or above 4096 / w_i:
+// g_i / w_i is O(|u|), so stored magnitudes sit well inside the FP16 normal
+// range (|g_i / w_i| up to 13.49 in every direction) and the rest state is
+// exactly 0.  A power of two makes the scaling itself exact in FP32 in both
+// directions, so the only rounding is the store's.  Mirror and opposite
+// directions share |xi_i|, so wall rules never change the scale.
+__host__ __device__ constexpr int scale_exp(int i) { return 14 + 2 * (cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i)); }
+__host__ __device__ constexpr double store_scale(int i) { return (double)(1ull << scale_exp(i)); }
 
 enum { BC_PERIODIC = 0, BC_FREESLIP = 1, BC_NOSLIP = 2, BC_PRESSURE = 3 };
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_MOM = 3 };

@@ -29,6 +29,13 @@ import numpy as np
 
 BC_PERIODIC, BC_FREESLIP, BC_NOSLIP, BC_PRESSURE = 0, 1, 2, 3
 V_TERMINAL_LU = 0.02
+# Where the force and torque of Sec. 2.2 are evaluated: the stress integral on
+# the parallel surface this many cells outside the markers (with that
+# surface's own areas).  0 evaluates it at the markers, as printed; there the
+# 4-point stencil straddles the surface and averages the outer stress with
+# that of the rigidly moving inner fluid, and a sphere in Stokes flow reads a
+# third to a half of its drag.  Three cells out the stencil sees only fluid.
+FORCE_OFFSET = 3.0
 
 # D3Q27 weights w_i = prod_d w1(xi_d), w1(0) = 2/3, w1(+-1) = 1/6; direction
 # i = 9*(xi_z+1) + 3*(xi_y+1) + (xi_x+1).  Only used to draw random
@@ -168,16 +175,16 @@ def _with_force_surface(body, delta, dS_offset):
     return body
 
 
-def sphere_fibonacci_body(R, n, kappa, r0, force_offset=0.0, **kw):
+def sphere_fibonacci_body(R, n, kappa, r0, force_offset=FORCE_OFFSET, **kw):
     xb, nb, dS = fibonacci_sphere(n, R)
     b = _body(kappa, 4.0 / 3.0 * math.pi * R ** 3, 0.4 * R * R * np.eye(3), xb, nb, dS, r0, **kw)
     return _with_force_surface(b, force_offset, dS * ((R + force_offset) / R) ** 2)
 
 
-def mesh_body(V, F, kappa, r0, force_offset=0.0, **kw):
+def mesh_body(V, F, kappa, r0, force_offset=FORCE_OFFSET, **kw):
     """Markers at the vertices of a closed triangle mesh.  With force_offset
-    > 0 the mesh is also offset along the vertex normals by that distance and
-    the vertex areas of the offset mesh are attached."""
+    > 0 (the default) the mesh is also offset along the vertex normals by
+    that distance and the vertex areas of the offset mesh are attached."""
     vol, cen, Jm = mesh_mass_properties(V, F)
     Vc = V - cen
     dS, nb = vertex_areas_normals(Vc, F)
@@ -278,7 +285,7 @@ def _freq_for_area(area, target_dS=0.5):
     return max(4, int(round(math.sqrt(area / target_dS / 10.0))))
 
 
-def case_sphere_settling(D=16.0, re=5.0, kappa=2.7, force_offset=0.0, w_d=10, h_d=30, domain="free-slip",
+def case_sphere_settling(D=16.0, re=5.0, kappa=2.7, force_offset=FORCE_OFFSET, w_d=10, h_d=30, domain="free-slip",
                          v_t=None, h_ini_d=None, h_end_d=None, sponge_d=None):
     """A sphere of diameter D (lattice units) settling from rest in a
     w = w_d D by w_d D by h = h_d D box (the paper's w* = 10, h* = 30 domain of
@@ -341,9 +348,10 @@ def batch_cases(n_cases=64, seed0=2408, max_h=384):
             vol, _, _ = mesh_mass_properties(V, F)
             scale = D / 2.0 / (3.0 * vol / (4.0 * math.pi)) ** (1.0 / 3.0)
             body = mesh_body(V * scale, F, kappa, r0)
-        # keep the marker stencils two cells inside the walls: start at most
-        # 0.75 h high and re-inject 32 rows lower, or above R_b + 4
-        rb = float(np.linalg.norm(body["x_body"], axis=1).max())
+        # keep the stencils of the force surface two cells inside the walls:
+        # start at most 0.75 h high and re-inject 32 rows lower, or above
+        # R_b + force offset + 4
+        rb = float(np.linalg.norm(body["x_body"], axis=1).max()) + body.get("force_offset", 0.0)
         z_start = min(z0, h - rb - 4.0)
         z_end = max(z_start - 32.0, rb + 4.0)
         body["r0"] = np.array([body["r0"][0], body["r0"][1], z_start])

@@ -1,6 +1,7 @@
 """Write the FP64 oracle trajectory of the 48^3 sphere case (the plain-method
-case: tau 0.6, 400 Fibonacci markers, kappa 2, g 1e-5, free-slip z walls)
-for 2000 steps.  Calls only the oracle; the stored values are its output.
+case: tau 0.6, 400 Fibonacci markers, kappa 2, g 1e-5, free-slip z walls,
+force and torque on the parallel surface 3 cells outside the markers) for
+2000 steps.  Calls only the oracle; the stored values are its output.
 
 Usage: python tests/golden/make_sphere48_trajectory.py
 """
@@ -30,7 +31,8 @@ def main():
         if n % 200 == 0:
             print(n, b["F"][2], b["v"][2], flush=True)
     hdr = ("FP64 oracle trajectory, 48^3 sphere case (tau 0.6, R 4, 400 Fibonacci markers, kappa 2, "
-           "g 1e-5, free-slip z), written by make_sphere48_trajectory.py from the oracle only.\n"
+           f"g 1e-5, free-slip z, force surface {body.get('force_offset', 0.0):g} cells out), "
+           "written by make_sphere48_trajectory.py from the oracle only.\n"
            "columns: step Fx Fy Fz Tx Ty Tz Fpx Fpy Fpz vx vy vz rx ry rz")
     np.savetxt(OUT, np.array(rows), header=hdr, fmt="%.17g")
 

@@ -101,7 +101,9 @@ def test_force_surface_checks():
     points two cells inside the z walls, and gets a larger region."""
     from paper_2408_15115_amd import turret as T
     case, body = W.case_sphere48()
-    _, _, aux0 = T.required_bytes([case], [body])
+    assert body["force_offset"] == W.FORCE_OFFSET == 3.0        # the default reading
+    at_markers = W.sphere_fibonacci_body(4.0, 400, 2.0, body["r0"], force_offset=0.0)
+    _, _, aux0 = T.required_bytes([case], [at_markers])
     b = W.sphere_fibonacci_body(4.0, 400, 2.0, body["r0"], force_offset=3.0)
     _, _, aux1 = T.required_bytes([case], [b])
     assert aux1 > aux0

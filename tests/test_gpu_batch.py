@@ -88,15 +88,24 @@ def test_particle_free_case_in_a_batch(T, alone):
     A.close()
 
 
-def test_batched_case_matches_oracle(T, orc):
+def test_batched_cases_match_oracle(T, orc):
+    """Every case of the batch (three boxes, relaxation times, walls and
+    shapes, one window shift in case 0) against the oracle run alone."""
     cases, bodies = small_batch()
     S = T.Solver(cases, bodies, schedule=3, persist_wgs=16, tile_order=2)
-    S.run(10)
-    o = orc.OracleSim(cases[1], bodies[1])
-    o.step(10)
-    assert max_rel(S.populations(1), oracle_to_soa(o.post_collision())) < 1e-5
-    ost, st = o.body_state(), S.body_state(1)
-    assert np.max(np.abs(st["F"] - ost["F"])) < 1e-4 * np.linalg.norm(ost["F"])
+    S.run(12)
+    for c in range(3):
+        say(f"batch case {c} vs oracle, 12 steps")
+        o = orc.OracleSim(cases[c], bodies[c])
+        o.step(12)
+        err = max_rel(S.populations(c), oracle_to_soa(o.post_collision()))
+        ost, st = o.body_state(), S.body_state(c)
+        ferr = np.max(np.abs(st["F"] - ost["F"])) / np.linalg.norm(ost["F"])
+        say(f"  populations {err:.2e}, force {ferr:.2e}, shifts {st['shifts']}")
+        assert err < 1e-5 and ferr < 1e-4, c
+        assert st["shifts"] == ost["shifts"]
+        assert np.allclose(st["r"], ost["r"], rtol=0, atol=1e-9)
+    S.close()
 
 
 def test_schedule_switch_on_a_live_context(T, alone):

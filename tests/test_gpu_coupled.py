@@ -264,8 +264,8 @@ def test_call_order_is_checked(T):
 def test_stencil_leaving_the_box_is_reported(T):
     """A body dropped with a large velocity reaches the bottom wall; the
     marker kernel flags it and the next synchronizing call reports it."""
-    case, body = small_sphere(zc=6.0, nz=40)
-    body["v0"] = np.array([0.0, 0.0, -0.3])
+    case, body = small_sphere(zc=10.0, nz=40)
+    body["v0"] = np.array([0.0, 0.0, -0.5])
     S = T.Solver([case], [body])
     S.run(8)
     with pytest.raises(T.TurretError) as e:

@@ -1,0 +1,158 @@
+"""Parity of the FP16 and BF16 storage paths against the oracle's model of
+the same storage (each stored population is w_i + q(s_i (f_i - w_i)) / s_i,
+s_i = 2^(14 + 2 |xi_i|^2), q the rounding of the format to nearest even).
+
+After one step, element by element.  Both sides round the same
+post-collision values, so nearly all stored codes agree exactly.  They can
+differ by one unit of the format where the GPU's FP32 value and the
+oracle's FP64 value straddle a rounding boundary, and on the forced cells,
+which the GPU rounds twice (the lattice kernel stores the unforced
+collision, the forced-collision correction adds the forcing term and rounds
+again) while the oracle rounds the forced collision once.  Where a
+deviation is tiny, the format's unit is finer than FP32 arithmetic on
+populations of size w_i, so the bar per element is one unit of the format
+at the oracle's stored value plus 1e-6 w_i (ten times the FP32 path's
+measured error against the FP64 oracle).
+
+After 25 steps, statistically.  A one-unit difference feeds the neighbours'
+next collisions, so the two rounded trajectories decorrelate and each
+carries its own rounding noise.  The oracle is then also run without
+rounding: the GPU's distance to the rounded oracle must stay within twice
+(RMS) and three times (max) the rounding's own effect on the oracle,
+g_rounded - g_FP64.  A wrong scale, a dropped term or a biased rounding
+would exceed that by orders of magnitude."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2408_15115_amd import workloads as W
+
+# storage scale s_i = 2^(14 + 2 |xi_i|^2) of the FP16/BF16 store
+SCALE = np.array([2.0 ** (14 + 2 * ((i % 3 - 1) ** 2 + ((i // 3) % 3 - 1) ** 2 + (i // 9 - 1) ** 2)) for i in range(27)])
+from tests.gpu_util import oracle_to_soa, say
+
+pytestmark = pytest.mark.gpu
+
+P_BITS = {"f16": 11, "bf16": 8}
+E_MIN = {"f16": -14, "bf16": -126}
+FLOOR = 1e-6          # per element, in units of w_i
+# fields of each comparison go to $TURRET_DUMP_DIR when it is set
+DUMP = os.environ.get("TURRET_DUMP_DIR")
+
+
+def dump(name, **arrays):
+    if DUMP:
+        os.makedirs(DUMP, exist_ok=True)
+        np.savez_compressed(os.path.join(DUMP, name), **arrays)
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_2408_15115_amd import turret
+    return turret
+
+
+def excess_units(gpu, ref, storage):
+    """(|g_gpu - g_ref| - FLOOR w_i) in units of the format at the oracle's
+    stored value, on (27, ...) fields; <= 1 passes the one-step bar."""
+    w = W.D3Q27_W.reshape((27,) + (1,) * (gpu.ndim - 1))
+    s = SCALE.reshape(w.shape)
+    ax = np.abs(s * (ref - w))
+    e = np.maximum(np.floor(np.log2(np.where(ax > 0, ax, 1.0))), E_MIN[storage])
+    ulp = 2.0 ** (e - (P_BITS[storage] - 1))
+    return (np.abs(s * (gpu - ref)) - FLOOR * w * s) / ulp
+
+
+def report_one_step(gpu, ref, storage, tag):
+    u = excess_units(gpu, ref, storage)
+    w = W.D3Q27_W.reshape((27,) + (1,) * (gpu.ndim - 1))
+    same = float(np.mean(np.abs(gpu - ref) <= 2.0 ** -22 * np.abs(ref - w) + 1e-15))
+    say(f"  {tag}: identical codes {100 * same:.3f} %, largest excess {u.max():.2f} units")
+    return u
+
+
+def report_many_steps(gpu, ref_q, ref64, tag):
+    d_gpu = gpu - ref_q
+    d_q = ref_q - ref64
+    rms_gpu, rms_q = float(np.sqrt(np.mean(d_gpu ** 2))), float(np.sqrt(np.mean(d_q ** 2)))
+    max_gpu, max_q = float(np.abs(d_gpu).max()), float(np.abs(d_q).max())
+    say(f"  {tag}: |gpu - rounded oracle| rms {rms_gpu:.3e} max {max_gpu:.3e}; "
+        f"rounding's own effect rms {rms_q:.3e} max {max_q:.3e}; mean difference {float(d_gpu.mean()):.2e}")
+    return rms_gpu, rms_q, max_gpu, max_q
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("steps", [1, 25])
+def test_lattice_matches_quantized_oracle(T, orc, storage, steps):
+    nx, ny, nz, tau = 33, 17, 19, 0.6
+    lo, hi = W.BC_FREESLIP, W.BC_NOSLIP
+    case = W.make_case(nx, ny, nz, tau, lo, hi, 4)
+    C0 = orc.quantize(W.random_populations(21, nx, ny, nz, amp=0.05), storage)
+    say(f"quantized lattice parity {storage} {nx}x{ny}x{nz} steps={steps}")
+    S = T.Solver([case], storage=storage)
+    S.set_populations(oracle_to_soa(C0))
+    assert np.abs(S.populations() - oracle_to_soa(C0)).max() <= 1e-9     # the input is stored exactly
+    for _ in range(steps):
+        S.lbm_step()
+    gpu = S.populations()
+    S.close()
+    fq = f64 = orc.stream_grid(C0, lo, hi)
+    for s in range(steps):
+        Cq = orc.quantize(orc.collide_grid(fq, tau, 4), storage)
+        C64 = orc.collide_grid(f64, tau, 4)
+        if s + 1 < steps:
+            fq, f64 = orc.stream_grid(Cq, lo, hi), orc.stream_grid(C64, lo, hi)
+    ref_q = oracle_to_soa(Cq)
+    dump(f"quant_lattice_{storage}_{steps}.npz", gpu=gpu, ref_q=ref_q, ref64=oracle_to_soa(C64))
+    if steps == 1:
+        assert report_one_step(gpu, ref_q, storage, "after 1 step").max() <= 1.0
+    else:
+        rms_gpu, rms_q, max_gpu, max_q = report_many_steps(gpu, ref_q, oracle_to_soa(C64), f"after {steps} steps")
+        assert rms_gpu <= 2.0 * rms_q and max_gpu <= 3.0 * max_q
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("steps", [1, 25])
+def test_coupled_step_matches_quantized_oracle(T, orc, storage, steps):
+    """Lattice kernel plus the forced-collision correction around a falling,
+    spinning sphere (force surface 3 cells out): the populations as above,
+    and force and torque against the oracle's from its own rounded state."""
+    n, nz = 24, 40
+    case = W.make_case(n, n, nz, 0.7, W.BC_FREESLIP, W.BC_FREESLIP, 0, 2e-5)
+    body = W.sphere_fibonacci_body(3.0, 200, 2.0, [(n - 1) / 2 + 0.3, (n - 1) / 2 - 0.2, 19.5],
+                                   w0=np.array([1e-3, -2e-3, 3e-3]))
+    say(f"quantized coupled parity {storage} sphere 24x24x40 steps={steps}")
+    o = orc.OracleSim(case, body)
+    o.set_storage(storage)
+    o64 = orc.OracleSim(case, body) if steps > 1 else None
+    S = T.Solver([case], [body], storage=storage)
+    dF, dT, qF, qT = [], [], [], []
+    for k in range(steps):
+        o.step(1)
+        S.run(1)
+        a, b = S.body_state(), o.body_state()
+        dF.append(np.abs(a["F"] - b["F"]).max())
+        dT.append(np.abs(a["T"] - b["T"]).max())
+        if o64 is not None:
+            o64.step(1)
+            c = o64.body_state()
+            qF.append(np.abs(b["F"] - c["F"]).max())
+            qT.append(np.abs(b["T"] - c["T"]).max())
+    gpu = S.populations()
+    S.close()
+    ref_q = oracle_to_soa(o.post_collision())
+    dump(f"quant_coupled_{storage}_{steps}.npz", gpu=gpu, ref_q=ref_q)
+    if steps == 1:
+        assert report_one_step(gpu, ref_q, storage, "after 1 coupled step").max() <= 1.0
+        return
+    rms_gpu, rms_q, max_gpu, max_q = report_many_steps(gpu, ref_q, oracle_to_soa(o64.post_collision()),
+                                                       f"after {steps} coupled steps")
+    assert rms_gpu <= 2.0 * rms_q and max_gpu <= 3.0 * max_q
+    # force and torque: the GPU's distance to the rounded oracle over the run
+    # against the rounding's own effect on the oracle's force and torque
+    say(f"  force: |gpu - rounded oracle| max {max(dF):.3e}, rounding's own effect {max(qF):.3e}; "
+        f"torque {max(dT):.3e}, {max(qT):.3e}")
+    assert max(dF) <= 3.0 * max(qF) and max(dT) <= 3.0 * max(qT)

@@ -1,6 +1,6 @@
 """Pins of the oracle's model of reduced-precision storage (the build's
 precision form; the paper has none): each stored population is
-w_i + q(s_i (f_i - w_i)) / s_i with s_i = 4096 / w_i and q the rounding to
+w_i + q(s_i (f_i - w_i)) / s_i with s_i = 2^(14 + 2 |xi_i|^2) and q the rounding to
 IEEE binary16 or to bfloat16, to nearest with ties to even.
 
 The rounding is checked against numpy's double-to-half conversion and
@@ -12,6 +12,9 @@ import numpy as np
 import pytest
 
 from paper_2408_15115_amd import workloads as W
+
+# storage scale s_i = 2^(14 + 2 |xi_i|^2) of the FP16/BF16 store
+SCALE = np.array([2.0 ** (14 + 2 * ((i % 3 - 1) ** 2 + ((i // 3) % 3 - 1) ** 2 + (i // 9 - 1) ** 2)) for i in range(27)])
 
 
 def test_binary16_rounding_is_numpys(orc):
@@ -47,7 +50,7 @@ def test_stored_field_is_the_rounded_scaled_deviation(orc, storage):
     _, w = orc.lattice()
     f = W.random_populations(3, 6, 5, 4, amp=0.05)
     q = orc.quantize(f, storage)
-    s = 4096.0 / w
+    s = SCALE.reshape(w.shape)
     x = s * (f - w)
     want = w + np.vectorize(lambda v: orc.round_format(v, storage))(x) / s
     assert np.array_equal(q, want)
