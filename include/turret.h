@@ -20,7 +20,10 @@
  *     exception crosses the boundary.  lbm_last_error() gives the message.
  *   - Ownership: the caller allocates all device memory (sizes from
  *     lbm_required_bytes) and keeps it alive until lbm_destroy; the library
- *     never allocates or frees device memory.  Host arrays passed to lbm_init
+ *     allocates no device memory on the step path.  With moment storage,
+ *     lbm_get_populations and lbm_set_populations allocate a temporary buffer
+ *     of one case's populations for the duration of the call;
+ *     lbm_get_populations_noalloc allocates nothing.  Host arrays passed to lbm_init
  *     are copied.  The stream is the caller's; every call is asynchronous on
  *     it except lbm_get_populations, lbm_set_populations, body_get_state,
  *     lbm_save and lbm_load, which synchronize it.  A context must not be
@@ -278,6 +281,20 @@ int32_t lbm_graph_launch(lbm_ctx *ctx);
  * of case case_id. */
 int32_t lbm_get_populations(lbm_ctx *ctx, int32_t case_id, double *host_out);
 int32_t lbm_set_populations(lbm_ctx *ctx, int32_t case_id, const double *host_in);
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): the populations
+ * of lbm_get_populations, written as f = w + g in FP64, layout
+ * [q][nz][ny][nx] in physical z order, into the caller's DEVICE buffer
+ * dev_out (q * nx * ny * nz doubles), asynchronously on the context's stream,
+ * with no allocation and no synchronization.  The values equal
+ * lbm_get_populations's bit for bit.  Moment storage rebuilds the
+ * populations in a fixed device scratch of 64 MiB that the library holds on
+ * each GPU until the process ends: cases whose q * plane * 4 bytes exceed it
+ * (about 600k cells) return LBM_EINVAL with a message.  Calls that overlap
+ * on one GPU (from two threads or streams) share that scratch and race.  The
+ * unstable flag is not reported here (body_get_state reports it). */
+int32_t lbm_get_populations_noalloc(lbm_ctx *ctx, int32_t case_id, double *dev_out);
 
 /* Body state of a case (synchronizing), out[32]:
  *   r(3) d(9) v(3) w(3) F(3) T(3) F_pressure(3) ibm_residual steps shifts

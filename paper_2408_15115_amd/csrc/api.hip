@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -377,6 +378,72 @@ static int32_t hip_fail(lbm_ctx *ctx, hipError_t e, const char *where)
         hipError_t e_ = (expr);                        \
         if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
     } while (0)
+
+// ------------------------------------------ population read without allocation
+// lbm_get_populations_noalloc keeps its staging in `scratch`, a file-scope
+// device array of kNoAllocScratchBytes that every GPU the library runs on
+// holds until the process ends.  Host code never passes the array's name to
+// a kernel or a copy: it takes the array's device address once per device
+// with hipGetSymbolAddress and uses that address.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) float scratch[kNoAllocScratchBytes / sizeof(float)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this device's scratch (looked up on its first use).
+static int32_t scratch_address(lbm_ctx *ctx, float **out)
+{
+    int dev = -1;
+    HIPCHK(ctx, hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(ctx, LBM_EHIP, "device ordinal out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(ctx, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(ctx, LBM_EHIP, "hipGetSymbolAddress(scratch) returned no address");
+        g_scratch_ptr[dev] = (float *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
+struct DecodeTable {
+    double w[27];    // lattice weight of each direction
+    float inv[27];   // 1 / s_i of the reduced-precision codecs
+};
+
+// Stored values of case c -> populations f = w_i + g_i in the caller's FP64
+// layout [q][nz][ny][nx] (physical z, the ring origin undone), with the
+// same FP32 decode arithmetic as the host copy of lbm_get_populations.
+template <int ST>
+__global__ void __launch_bounds__(256) k_decode_populations(const void *__restrict__ raw, long long plane, int q,
+                                                            int nx, int ny, int nz, const BodyDev *__restrict__ body,
+                                                            DecodeTable tab, double *__restrict__ out)
+{
+    const long long slab = (long long)nx * ny;
+    const long long n = (long long)q * nz * slab;
+    const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int i = (int)(idx / (nz * slab));
+    const long long rem = idx - (long long)i * nz * slab;
+    const int z = (int)(rem / slab);
+    const long long k = rem - (long long)z * slab;
+    const int zc = (z + body->z0) % nz;
+    const long long src = (long long)i * plane + (long long)zc * slab + k;
+    float g;
+    if constexpr (ST == LBM_F16) {
+        g = (float)((const _Float16 *)raw)[src] * tab.inv[i];
+    } else if constexpr (ST == LBM_BF16) {
+        g = __uint_as_float((uint32_t)((const uint16_t *)raw)[src] << 16) * tab.inv[i];
+    } else {
+        g = ((const float *)raw)[src];
+    }
+    out[idx] = tab.w[i] + (double)g;
+}
 
 static thread_local std::string g_init_error;
 
@@ -853,6 +920,54 @@ int32_t lbm_set_populations(lbm_ctx *ctx, int32_t c, const double *in)
         HIPCHK(ctx, hipMemcpyAsync(dst, raw.data(), raw.size(), hipMemcpyHostToDevice, ctx->stream), "copy populations");
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     }
+    return LBM_OK;
+}
+
+int32_t lbm_get_populations_noalloc(lbm_ctx *ctx, int32_t c, double *dev_out)
+{
+    if (!ctx || !dev_out || c < 0 || c >= ctx->n) return fail(ctx, LBM_EINVAL, "bad case or NULL output");
+    if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "population read between lbm_step and ibm_couple");
+    const CaseDev &d = ctx->plan.cd[c];
+    const bool mom = ctx->opt.storage == LBM_MOM;
+    const int st = mom ? LBM_F32 : ctx->opt.storage;
+    const int q = ctx->plan.q;
+    const size_t staged = (size_t)q * (size_t)d.plane * sizeof(float);
+    if (mom && staged > kNoAllocScratchBytes)
+        return fail(ctx, LBM_EINVAL,
+                    "case too large for the no-allocation read: moment storage stages " + std::to_string(staged) +
+                        " bytes, the scratch holds " + std::to_string(kNoAllocScratchBytes));
+    DecodeTable tab{};
+    for (int i = 0; i < q; i++) {
+        tab.w[i] = lattice_weight(q, i);
+        tab.inv[i] = (float)(1.0 / store_scale(i));
+    }
+    const void *raw = (const char *)ctx->pop[ctx->cur] + (size_t)d.pop_off * elem_bytes(st);
+    if (mom) {
+        float *sp = nullptr;
+        int32_t r = scratch_address(ctx, &sp);
+        if (r) return r;
+        HIPCHK(ctx, launch_moments_expand_n((const float *)raw, sp, ctx->p, c, d.cells, ctx->stream),
+               "reconstruct populations in the scratch");
+        raw = sp;
+    }
+    const long long n = (long long)q * d.cells;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    const BodyDev *body = ctx->p.body + c;
+    switch (st) {
+    case LBM_F16:
+        hipLaunchKernelGGL(k_decode_populations<LBM_F16>, grid, dim3(256), 0, ctx->stream, raw, d.plane, q, d.nx, d.ny,
+                           d.nz, body, tab, dev_out);
+        break;
+    case LBM_BF16:
+        hipLaunchKernelGGL(k_decode_populations<LBM_BF16>, grid, dim3(256), 0, ctx->stream, raw, d.plane, q, d.nx,
+                           d.ny, d.nz, body, tab, dev_out);
+        break;
+    default:
+        hipLaunchKernelGGL(k_decode_populations<LBM_F32>, grid, dim3(256), 0, ctx->stream, raw, d.plane, q, d.nx, d.ny,
+                           d.nz, body, tab, dev_out);
+        break;
+    }
+    HIPCHK(ctx, hipGetLastError(), "decode populations");
     return LBM_OK;
 }
 

@@ -132,6 +132,9 @@ hipError_t launch_stream_collide19(const void *src, void *dst, const DevPtrs &p,
 int moment_tiles(int nx, int ny, int nz);
 hipError_t launch_moment_step(const void *src, void *dst, const DevPtrs &p, int ntiles, hipStream_t s);
 hipError_t launch_moments_expand(const float *src, float *dst, const DevPtrs &p, int c, hipStream_t s);
+// the same with the case's cell count from the host plan (no synchronizing read)
+hipError_t launch_moments_expand_n(const float *src, float *dst, const DevPtrs &p, int c, long long cells,
+                                   hipStream_t s);
 hipError_t launch_moments_project(const float *src, float *dst, long long plane, long long cells, hipStream_t s);
 hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
 // IBM coupling.  With a warm start (warm_mode 1: the previous step's final

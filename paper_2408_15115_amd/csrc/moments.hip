@@ -294,6 +294,14 @@ hipError_t launch_moments_expand(const float *src, float *dst, const DevPtrs &p,
     return hipGetLastError();
 }
 
+hipError_t launch_moments_expand_n(const float *src, float *dst, const DevPtrs &p, int c, long long cells,
+                                   hipStream_t s)
+{
+    const long long grid = (cells + 255) / 256;
+    hipLaunchKernelGGL(k_moments_expand, dim3((unsigned)grid), dim3(256), 0, s, src, dst, p, c);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments_project(const float *src, float *dst, long long plane, long long cells, hipStream_t s)
 {
     const long long grid = (cells + 255) / 256;

@@ -71,6 +71,7 @@ _sig = {
     "lbm_graph_launch": (C.c_int32, [_ctx]),
     "lbm_get_populations": (C.c_int32, [_ctx, C.c_int32, _P(C.c_double)]),
     "lbm_set_populations": (C.c_int32, [_ctx, C.c_int32, _P(C.c_double)]),
+    "lbm_get_populations_noalloc": (C.c_int32, [_ctx, C.c_int32, C.c_void_p]),
     "body_get_state": (C.c_int32, [_ctx, C.c_int32, _P(C.c_double)]),
     "lbm_save": (C.c_int32, [_ctx, C.c_char_p]),
     "lbm_load": (C.c_int32, [_ctx, C.c_char_p]),
@@ -254,6 +255,14 @@ class Solver:
         out = np.empty((self.q, nz, ny, nx))
         self._chk("lbm_get_populations", lbm_get_populations(self._ctx, case, _dptr(out)))
         return out
+
+    def populations_noalloc(self, out, case=0):
+        """lbm_get_populations_noalloc into a device tensor ``out`` of
+        q * nx * ny * nz float64 values (asynchronous on the stream)."""
+        nx, ny, nz = self.dims[case]
+        assert out.dtype == self.torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() >= self.q * nx * ny * nz
+        self._chk("lbm_get_populations_noalloc", lbm_get_populations_noalloc(self._ctx, case, C.c_void_p(out.data_ptr())))
 
     def set_populations(self, f, case=0):
         nx, ny, nz = self.dims[case]
