@@ -177,7 +177,19 @@ typedef struct {
  *               H_zzx +- H_xyy; no fourth order).  Fluid-only contexts
  *               (no markers), FP32 storage, periodic z, no sponge,
  *               schedule 0; populations are then [19][nz][ny][nx] with
- *               the D3Q27 direction order, corners left out */
+ *               the D3Q27 direction order, corners left out
+ *   fine_box    FP16/BF16 storage only: 1 = keep a box around each body in
+ *               FP32 (the particle region of the coupling plus a one-cell
+ *               rim, at most the case's size per axis).  After the lattice
+ *               kernel, the box cells are stepped again from FP32 sources
+ *               wherever those lie in the previous step's box; the
+ *               reduced-precision store still holds the rounding of every
+ *               cell, and the forced-collision correction rounds the box
+ *               cells once.  The stress, the interpolations and the forcing
+ *               then see FP32 populations near the body, while the rest of
+ *               the lattice moves half the bytes.  0 = none (the default).
+ *               The boxes (two per case, one per population buffer) live in
+ *               aux; population copies and checkpoints include them. */
 typedef struct {
     int32_t storage;
     int32_t ibm_cycles;
@@ -190,6 +202,7 @@ typedef struct {
     int32_t serial_ibm;
     int32_t collision;
     int32_t lattice;
+    int32_t fine_box;
 } lbm_options;
 
 /* Caller-owned device buffers (byte sizes from lbm_required_bytes):

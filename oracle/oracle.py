@@ -82,7 +82,7 @@ def lib():
         L.orc_sim_set_force_surface.argtypes = [C.c_void_p, d, pd]
         L.orc_sim_set_torque.argtypes = [C.c_void_p, pd]
         L.orc_sim_set_fluid_force.argtypes = [C.c_void_p, pd]
-        L.orc_sim_set_storage.argtypes = [C.c_void_p, i32, d]
+        L.orc_sim_set_storage.argtypes = [C.c_void_p, i32, d, pi]
         L.orc_round_format.argtypes = [d, i32]
         L.orc_round_format.restype = d
         L.orc_quantize.argtypes = [i32, C.c_int64, pd]
@@ -102,6 +102,7 @@ def lib():
         L.orc_sim_get_body.argtypes = [C.c_void_p, pd]
         L.orc_sim_get_markers.argtypes = [C.c_void_p, pd, pd, pd, pd]
         L.orc_num_threads.restype = i32
+        L.orc_set_threads.argtypes = [i32]
         L.orc_init()
         _lib = L
     return _lib
@@ -347,11 +348,14 @@ class OracleSim:
             self._keep = self._keep + (dSo,)
             L.orc_sim_set_force_surface(self._p, float(body["force_offset"]), _pd(dSo))
 
-    def set_storage(self, storage, keep_box=0.0):
+    def set_storage(self, storage, box=None):
         """Store the post-collision state in "f16" or "bf16" (the build's
-        precision form); keep_box > 0 leaves the cells within that max-norm
-        distance of the body centre in FP64."""
-        lib().orc_sim_set_storage(self._p, STORAGE[storage], float(keep_box))
+        precision form).  box = (rb, (ex, ey, ez)) keeps the cells
+        floor(r_a - rb) - 3 ... + e_a - 1 around the body in FP64."""
+        rb, edges = box if box is not None else (0.0, (0, 0, 0))
+        e = np.array(edges, np.int32)
+        self._keep = self._keep + (e,)
+        lib().orc_sim_set_storage(self._p, STORAGE[storage], float(rb), _pi(e))
 
     def set_fluid_force(self, g):
         """A uniform force per unit mass on the whole fluid, added to the
@@ -410,3 +414,7 @@ class OracleSim:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))

@@ -670,7 +670,8 @@ typedef struct {
     double *dSo;
     double gf[3];                  /* uniform fluid force added to h_imm in the collision */
     int storage;                   /* STORE_*: precision of the stored post-collision state */
-    double keep_box;               /* > 0: cells within this distance (max norm) of r keep FP64 */
+    double box_rb;                 /* full-precision box around the body: reach and edges */
+    int box_edge[3];
     double *htot;                  /* h_imm + gf when gf is set */
     int64_t shifts, steps;
     int err;
@@ -770,34 +771,37 @@ void orc_sim_set_fluid_force(orc_sim *S, const double *gf)
 
 /* Reduced-precision storage of the post-collision state (the build's
  * precision form): after each collision every population is replaced by the
- * value the stored format holds.  keep_box > 0 exempts the cells within that
- * max-norm distance of the body's centre, which then stay FP64. */
-void orc_sim_set_storage(orc_sim *S, int32_t storage, double keep_box)
+ * value the stored format holds.  With box edges > 0 the cells of a box
+ * around the body keep full precision: per axis a the cells
+ * floor(r_a - box_rb) - 3 ... + box_edge[a] - 1 (x and y periodic, z not
+ * wrapped), r being the body position of the stored state. */
+void orc_sim_set_storage(orc_sim *S, int32_t storage, double box_rb, const int32_t *box_edge)
 {
     S->storage = storage;
-    S->keep_box = keep_box;
+    S->box_rb = box_rb;
+    for (int a = 0; a < 3; a++) S->box_edge[a] = box_edge ? box_edge[a] : 0;
 }
 
 static void quantize_state(orc_sim *S, double *C)
 {
     if (S->storage == STORE_F64) return;
     const dom_t *D = &S->D;
+    int lo[3] = {0, 0, 0};
+    const int *e = S->box_edge;
+    const int boxed = e[0] > 0 && e[1] > 0 && e[2] > 0;
+    if (boxed) {
+        /* a window shift still pending moves this state up later: its body
+         * position is r_z - pending until then */
+        const double r[3] = {S->B.r[0], S->B.r[1], S->B.r[2] - S->pending};
+        for (int a = 0; a < 3; a++) lo[a] = (int)floor(r[a] - S->box_rb) - 3;
+    }
     #pragma omp parallel for schedule(static)
     for (int z = 0; z < D->nz; z++)
         for (int y = 0; y < D->ny; y++)
             for (int x = 0; x < D->nx; x++) {
-                if (S->keep_box > 0.0) {
-                    const double p[3] = {x, y, z};
-                    double dmax = 0.0;
-                    for (int a = 0; a < 3; a++) {
-                        double d = fabs(p[a] - S->B.r[a]);
-                        if (a < 2) {
-                            const double n = a == 0 ? D->nx : D->ny;
-                            if (n - d < d) d = n - d;    /* periodic distance */
-                        }
-                        if (d > dmax) dmax = d;
-                    }
-                    if (dmax <= S->keep_box) continue;
+                if (boxed) {
+                    const int kx = wrap(x - lo[0], D->nx), ky = wrap(y - lo[1], D->ny), kz = z - lo[2];
+                    if (kx < e[0] && ky < e[1] && kz >= 0 && kz < e[2]) continue;
                 }
                 const size_t c = cell(D, x, y, z);
                 for (int i = 0; i < Q; i++) C[Q * c + i] = quantize_pop(C[Q * c + i], i, S->storage);
@@ -1062,6 +1066,16 @@ void orc_sim_get_markers(const orc_sim *S, double *X, double *N, double *U, doub
     if (N) memcpy(N, S->N, b);
     if (U) memcpy(U, S->U, b);
     if (hk) memcpy(hk, S->hk, b);
+}
+
+/* Threads of the OpenMP loops (for timing the oracle on one core). */
+void orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int32_t orc_num_threads(void)

@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libturret.so")
-SOURCES = ["stream_collide.hip", "stream_collide19.hip", "moments.hip", "kernels.hip", "mlp.hip", "api.hip"]
+SOURCES = ["stream_collide.hip", "stream_collide19.hip", "moments.hip", "fine.hip", "kernels.hip", "mlp.hip",
+           "api.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",

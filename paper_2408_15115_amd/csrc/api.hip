@@ -39,8 +39,10 @@ struct Plan {
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
         off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox,
-        off_mark, off_wt, off_dsh, off_rpop, aux_bytes;
+        off_mark, off_wt, off_dsh, off_rpop, off_fine0, off_fine1, aux_bytes;
     long long xreg_cells = 0;   // moment storage: cells of all expanded regions (edge L + 2)
+    long long fine_elems = 0;   // FP16/BF16 storage: floats of all full-precision boxes (per buffer)
+    long long max_box = 0;      // cells of the largest box
     int block = 256;
 };
 
@@ -105,6 +107,9 @@ std::string check_options(const lbm_options *o)
     if (o->serial_ibm < 0 || o->serial_ibm > 1) return "serial_ibm must be 0 or 1";
     if (o->collision < 0 || o->collision > 1) return "collision must be 0 or 1";
     if (o->lattice != 0 && o->lattice != 19 && o->lattice != 27) return "lattice must be 27 (or 0) or 19";
+    if (o->fine_box < 0 || o->fine_box > 1) return "fine_box must be 0 or 1";
+    if (o->fine_box && o->storage != LBM_F16 && o->storage != LBM_BF16)
+        return "fine_box applies to FP16 and BF16 storage only";
     return "";
 }
 
@@ -265,6 +270,16 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         reg += (long long)d.L * d.L * d.L;
         d.xreg_off = P.xreg_cells;
         if (d.M > 0) P.xreg_cells += (long long)(d.L + 2) * (d.L + 2) * (d.L + 2);
+        // full-precision box: the region and a one-cell rim, at most the box
+        if (opt && opt->fine_box && d.M > 0) {
+            d.LB[0] = std::min(d.L + 2, d.nx);
+            d.LB[1] = std::min(d.L + 2, d.ny);
+            d.LB[2] = std::min(d.L + 2, d.nz);
+            const long long cells = (long long)d.LB[0] * d.LB[1] * d.LB[2];
+            d.fine_off = P.fine_elems;
+            P.fine_elems += Q * ((cells + 63) / 64 * 64);
+            P.max_box = std::max(P.max_box, cells);
+        }
         P.maxL3 = std::max(P.maxL3, d.L * d.L * d.L);
         if (d.M > 0) P.max_slab = std::max(P.max_slab, d.dz * k.nx * k.ny);
         P.max_tiles += (d.cells + 63) / 64;
@@ -309,6 +324,8 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_wt = take(sizeof(double) * 12 * M);
     P.off_dsh = take(sizeof(float) * 4 * std::max<long long>(reg, 1));
     P.off_rpop = take(sizeof(float) * Q * std::max<long long>(mom ? P.xreg_cells : 0, 1));
+    P.off_fine0 = take(sizeof(float) * std::max<long long>(P.fine_elems, 1));
+    P.off_fine1 = take(sizeof(float) * std::max<long long>(P.fine_elems, 1));
     P.off_mtiles = take(sizeof(MarkerTile) * NT);
     P.off_tbox = take(sizeof(TileBox) * NT);
     P.aux_bytes = o;
@@ -445,6 +462,27 @@ __global__ void __launch_bounds__(256) k_decode_populations(const void *__restri
     out[idx] = tab.w[i] + (double)g;
 }
 
+// The cells of case c's full-precision box of buffer `cur` (when valid):
+// f = w_i + g in the caller's layout, over the values k_decode_populations
+// wrote from the store.
+__global__ void __launch_bounds__(256) k_decode_fine(DevPtrs p, int c, int cur, DecodeTable tab, double *__restrict__ out)
+{
+    const CaseDev cd = p.cases[c];
+    const BodyDev &B = p.body[c];
+    if (cd.LB[0] == 0 || !B.fvalid[cur]) return;
+    const long long fplane = (long long)cd.LB[0] * cd.LB[1] * cd.LB[2];
+    const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (idx >= Q * fplane) return;
+    const int i = (int)(idx / fplane);
+    const long long slot = idx - (long long)i * fplane;
+    const int kx = (int)(slot % cd.LB[0]), ky = (int)((slot / cd.LB[0]) % cd.LB[1]), kz = (int)(slot / (cd.LB[0] * cd.LB[1]));
+    const int z = B.fo[cur][2] + kz;
+    if (z < 0 || z >= cd.nz) return;
+    const int x = ((B.fo[cur][0] + kx) % cd.nx + cd.nx) % cd.nx, y = ((B.fo[cur][1] + ky) % cd.ny + cd.ny) % cd.ny;
+    const long long slab = (long long)cd.nx * cd.ny;
+    out[((long long)i * cd.nz + z) * slab + (long long)y * cd.nx + x] = tab.w[i] + (double)p.fine[cur][cd.fine_off + idx];
+}
+
 static thread_local std::string g_init_error;
 
 extern "C" {
@@ -523,6 +561,8 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.hs = (double *)(a + P.off_hs);
     p.dSo = (double *)(a + P.off_dSo);
     p.tbox = (TileBox *)(a + P.off_tbox);
+    p.fine[0] = (float *)(a + P.off_fine0);
+    p.fine[1] = (float *)(a + P.off_fine1);
 
     // host images of the descriptors, body states and markers
     std::vector<BodyDev> bd(n_cases);
@@ -630,6 +670,11 @@ static int32_t do_lbm_step(lbm_ctx *ctx)
                                      (int)ctx->plan.tiles.size(), ctx->opt.block, ctx->opt.schedule,
                                      ctx->opt.persist_wgs, ctx->opt.collision, ctx->stream),
                "lbm_step");
+    if (ctx->plan.max_box > 0)
+        HIPCHK(ctx,
+               launch_fine_step(ctx->opt.storage, ctx->pop[src], ctx->pop[dst], ctx->p, src, dst, ctx->n,
+                                ctx->plan.max_box, ctx->opt.collision, ctx->stream),
+               "full-precision box");
     ctx->cur = dst;
     ctx->needs_ibm = ctx->has_body;
     return LBM_OK;
@@ -644,14 +689,14 @@ static int32_t do_ibm(lbm_ctx *ctx)
     HIPCHK(ctx,
            launch_ibm(ctx->opt.storage, ctx->pop[1 - ctx->cur], ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.Mtot,
                       (int)ctx->plan.mtiles.size(), ctx->plan.maxL3, ctx->opt.ibm_cycles, ctx->warm_mode, ctx->mlp_th16, ctx->mlp_cycles,
-                      ctx->opt.ibm_diag, ctx->plan.force_surface, cs),
+                      ctx->opt.ibm_diag, ctx->plan.force_surface, 1 - ctx->cur, cs),
            "ibm_couple");
     if (!serial) {
         HIPCHK(ctx, hipEventRecord(ctx->join, ctx->side), "record join event");
         HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->join, 0), "stream waits for the coupling");
     }
     HIPCHK(ctx, launch_correct(ctx->opt.storage, ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.Mtot, ctx->plan.maxL3,
-                               ctx->stream),
+                               ctx->cur, ctx->stream),
            "forced correction");
     ctx->needs_ibm = false;
     return LBM_OK;
@@ -660,7 +705,8 @@ static int32_t do_ibm(lbm_ctx *ctx)
 static int32_t do_window(lbm_ctx *ctx)
 {
     if (!ctx->has_body) return LBM_OK;
-    HIPCHK(ctx, launch_window(ctx->opt.storage, ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.max_slab, ctx->stream),
+    HIPCHK(ctx, launch_window(ctx->opt.storage, ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.max_slab, ctx->cur,
+                              ctx->stream),
            "window_shift");
     return LBM_OK;
 }
@@ -720,8 +766,8 @@ int32_t lbm_set_schedule(lbm_ctx *ctx, const lbm_options *opt)
     if (!e.empty()) return fail(ctx, LBM_EINVAL, e);
     const int cyc = opt->ibm_cycles ? opt->ibm_cycles : 4;
     if (opt->storage != ctx->opt.storage || cyc != ctx->opt.ibm_cycles || opt->forcing != ctx->opt.forcing ||
-        (opt->lattice == 19) != (ctx->plan.q == 19))
-        return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage, ibm_cycles, forcing or lattice");
+        (opt->lattice == 19) != (ctx->plan.q == 19) || opt->fine_box != ctx->opt.fine_box)
+        return fail(ctx, LBM_EINVAL, "lbm_set_schedule cannot change storage, ibm_cycles, forcing, lattice or fine_box");
     if (ctx->plan.q == 19 && opt->schedule != 0) return fail(ctx, LBM_EINVAL, "the D3Q19 lattice runs with schedule 0");
     if (ctx->opt.storage == LBM_MOM && (opt->schedule != 0 || opt->collision != 0))
         return fail(ctx, LBM_EINVAL, "moment storage runs with schedule 0 and collision 0");
@@ -879,6 +925,27 @@ int32_t lbm_get_populations(lbm_ctx *ctx, int32_t c, double *out)
                 out[((size_t)i * d.nz + z) * slab + k] =
                     lattice_weight(q, i) + (double)host_dec(st, raw.data(), (size_t)i * d.plane + zc * slab + k, i);
         }
+    // cells of the full-precision box: their FP32 values
+    if (d.LB[0] > 0 && B.fvalid[ctx->cur]) {
+        const long long fplane = (long long)d.LB[0] * d.LB[1] * d.LB[2];
+        std::vector<float> fb((size_t)Q * fplane);
+        HIPCHK(ctx, hipMemcpyAsync(fb.data(), ctx->p.fine[ctx->cur] + d.fine_off, fb.size() * sizeof(float),
+                                   hipMemcpyDeviceToHost, ctx->stream), "copy the full-precision box");
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+        const int *fo = B.fo[ctx->cur];
+        for (int kz = 0; kz < d.LB[2]; kz++) {
+            const int z = fo[2] + kz;
+            if (z < 0 || z >= d.nz) continue;
+            for (int ky = 0; ky < d.LB[1]; ky++)
+                for (int kx = 0; kx < d.LB[0]; kx++) {
+                    const int x = ((fo[0] + kx) % d.nx + d.nx) % d.nx, y = ((fo[1] + ky) % d.ny + d.ny) % d.ny;
+                    const long long slot = ((long long)kz * d.LB[1] + ky) * d.LB[0] + kx;
+                    for (int i = 0; i < Q; i++)
+                        out[((size_t)i * d.nz + z) * slab + (size_t)y * d.nx + x] =
+                            lattice_weight(q, i) + (double)fb[(size_t)i * fplane + slot];
+                }
+        }
+    }
     return B.err ? fail(ctx, LBM_EUNSTABLE, "unstable: marker stencil left the box or non-finite IBM value") : LBM_OK;
 }
 
@@ -918,6 +985,11 @@ int32_t lbm_set_populations(lbm_ctx *ctx, int32_t c, const double *in)
         HIPCHK(ctx, he, "project populations");
     } else {
         HIPCHK(ctx, hipMemcpyAsync(dst, raw.data(), raw.size(), hipMemcpyHostToDevice, ctx->stream), "copy populations");
+        if (d.LB[0] > 0) {   // the full-precision box restarts from the rounded values
+            const int zero = 0;
+            HIPCHK(ctx, hipMemcpyAsync(&ctx->p.body[c].fvalid[ctx->cur], &zero, sizeof zero, hipMemcpyHostToDevice,
+                                       ctx->stream), "reset the full-precision box");
+        }
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     }
     return LBM_OK;
@@ -968,6 +1040,12 @@ int32_t lbm_get_populations_noalloc(lbm_ctx *ctx, int32_t c, double *dev_out)
         break;
     }
     HIPCHK(ctx, hipGetLastError(), "decode populations");
+    if (d.LB[0] > 0) {
+        const long long nf = (long long)Q * d.LB[0] * d.LB[1] * d.LB[2];
+        hipLaunchKernelGGL(k_decode_fine, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, ctx->stream, ctx->p, c,
+                           ctx->cur, tab, dev_out);
+        HIPCHK(ctx, hipGetLastError(), "decode the full-precision box");
+    }
     return LBM_OK;
 }
 
@@ -1000,16 +1078,25 @@ int32_t lbm_save(lbm_ctx *ctx, const char *path)
     if (!ctx || !path) return LBM_EINVAL;
     if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "save between lbm_step and ibm_couple");
     const int eb = elem_bytes(ctx->opt.storage);
-    // moment storage also keeps the forcing shifts of the last correction
-    const size_t extra = ctx->opt.storage == LBM_MOM ? sizeof(float) * 4 * (size_t)std::max<long long>(ctx->plan.reg_cells, 1) : 0;
+    // moment storage also keeps the forcing shifts of the last correction,
+    // FP16/BF16 storage the full-precision boxes of the current buffer
+    const size_t extra = ctx->opt.storage == LBM_MOM
+                             ? sizeof(float) * 4 * (size_t)std::max<long long>(ctx->plan.reg_cells, 1)
+                             : sizeof(float) * (size_t)ctx->plan.fine_elems;
+    const void *extra_src = ctx->opt.storage == LBM_MOM ? (const void *)ctx->p.dsh : (const void *)ctx->p.fine[ctx->cur];
     const size_t popb = (size_t)ctx->plan.pop_elems * eb;
     std::vector<char> pop(popb + extra);
     std::vector<BodyDev> bd(ctx->n);
     HIPCHK(ctx, hipMemcpyAsync(pop.data(), ctx->pop[ctx->cur], popb, hipMemcpyDeviceToHost, ctx->stream), "save");
     if (extra)
-        HIPCHK(ctx, hipMemcpyAsync(pop.data() + popb, ctx->p.dsh, extra, hipMemcpyDeviceToHost, ctx->stream), "save");
+        HIPCHK(ctx, hipMemcpyAsync(pop.data() + popb, extra_src, extra, hipMemcpyDeviceToHost, ctx->stream), "save");
     HIPCHK(ctx, hipMemcpyAsync(bd.data(), ctx->p.body, sizeof(BodyDev) * ctx->n, hipMemcpyDeviceToHost, ctx->stream), "save");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    for (BodyDev &b : bd) {   // the file keeps the current buffer's box in slot 0
+        if (ctx->cur == 1) std::memcpy(b.fo[0], b.fo[1], sizeof b.fo[0]);
+        b.fvalid[0] = b.fvalid[ctx->cur];
+        b.fvalid[1] = 0;
+    }
     FILE *f = std::fopen(path, "wb");
     if (!f) return fail(ctx, LBM_EINVAL, std::string("cannot open ") + path);
     const int64_t hdr[4] = {ctx->n, ctx->opt.storage, (int64_t)popb, (int64_t)sizeof(BodyDev)};
@@ -1029,7 +1116,10 @@ int32_t lbm_load(lbm_ctx *ctx, const char *path)
     char magic[8];
     int64_t hdr[4];
     const int eb = elem_bytes(ctx->opt.storage);
-    const size_t extra = ctx->opt.storage == LBM_MOM ? sizeof(float) * 4 * (size_t)std::max<long long>(ctx->plan.reg_cells, 1) : 0;
+    const size_t extra = ctx->opt.storage == LBM_MOM
+                             ? sizeof(float) * 4 * (size_t)std::max<long long>(ctx->plan.reg_cells, 1)
+                             : sizeof(float) * (size_t)ctx->plan.fine_elems;
+    void *extra_dst = ctx->opt.storage == LBM_MOM ? (void *)ctx->p.dsh : (void *)ctx->p.fine[ctx->cur];
     const size_t popb = (size_t)ctx->plan.pop_elems * eb;
     bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
               std::fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == ctx->n && hdr[1] == ctx->opt.storage &&
@@ -1040,9 +1130,14 @@ int32_t lbm_load(lbm_ctx *ctx, const char *path)
          std::fread(pop.data(), 1, popb + extra, f) == popb + extra;
     std::fclose(f);
     if (!ok) return fail(ctx, LBM_EINVAL, "checkpoint does not match this context");
+    for (BodyDev &b : bd) {   // slot 0 of the file is the current buffer's box
+        if (ctx->cur == 1) std::memcpy(b.fo[1], b.fo[0], sizeof b.fo[0]);
+        b.fvalid[ctx->cur] = b.fvalid[0];
+        b.fvalid[1 - ctx->cur] = 0;
+    }
     HIPCHK(ctx, hipMemcpyAsync(ctx->pop[ctx->cur], pop.data(), popb, hipMemcpyHostToDevice, ctx->stream), "load");
     if (extra)
-        HIPCHK(ctx, hipMemcpyAsync(ctx->p.dsh, pop.data() + popb, extra, hipMemcpyHostToDevice, ctx->stream), "load");
+        HIPCHK(ctx, hipMemcpyAsync(extra_dst, pop.data() + popb, extra, hipMemcpyHostToDevice, ctx->stream), "load");
     HIPCHK(ctx, hipMemcpyAsync(ctx->p.body, bd.data(), sizeof(BodyDev) * ctx->n, hipMemcpyHostToDevice, ctx->stream), "load");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
     return LBM_OK;

@@ -24,6 +24,8 @@ struct CaseDev {
     double force_offset;    // 0: stress integral at the markers; > 0: on the parallel surface
     float uw_lo, uw_hi;     // x velocity of a no-slip bottom / top wall
     long long xreg_off;     // moment storage: cell offset of the case's expanded region (edge L + 2)
+    int LB[3];              // FP16/BF16 storage: edges of the case's full-precision box (0: none)
+    long long fine_off;     // element offset of the case's box in each box buffer ([27][LBz][LBy][LBx])
 };
 
 // Dynamic FP64 rigid-body state of one case plus the ring origin and region
@@ -45,6 +47,8 @@ struct BodyDev {
     int dvalid;                 // moment storage: 1 once a correction has written the forcing box
     int warm_cyc_sum;           // cycles used by the accepted learned starts, summed
     int org[3];      // IBM region origin (physical cell coordinates, x/y unwrapped)
+    int fo[2][3];    // full-precision box origin of population buffer 0 / 1 (physical, x/y unwrapped)
+    int fvalid[2];   // 1 once a step has written that buffer's box
     int err;         // 1: a marker stencil left the box in z; 2: non-finite or huge IBM value;
                      // 4: non-finite density or |u| > 0.5.  Nonzero masks (freezes) the case.
 };
@@ -117,6 +121,7 @@ struct DevPtrs {
     float *dsh;      // moment storage: per region cell the forcing shift (Delta_x, Delta_y, Delta_z, lambda)
     float *rpop;     // moment storage: collided populations of the region and a one-cell rim, [27][xstride]
     long long xstride;
+    float *fine[2];  // FP16/BF16 storage: the full-precision boxes of population buffers 0 and 1
 };
 
 // ---------------------------------------------------------------- launchers
@@ -137,6 +142,11 @@ hipError_t launch_moments_expand_n(const float *src, float *dst, const DevPtrs &
                                    hipStream_t s);
 hipError_t launch_moments_project(const float *src, float *dst, long long plane, long long cells, hipStream_t s);
 hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
+// FP16/BF16 storage with full-precision boxes: after the lattice kernel,
+// step the box cells again from buffer sid's box into buffer did's box
+// (max_box = the largest box's cell count; 0 = no boxes).
+hipError_t launch_fine_step(int storage, const void *src, void *dst, const DevPtrs &p, int sid, int did, int n_cases,
+                            long long max_box, int collision, hipStream_t s);
 // IBM coupling.  With a warm start (warm_mode 1: the previous step's final
 // h_k; 2: the network th16) cycles run from that start until a case's
 // residual is at or below its gate, at most warm_cycles of them; cases that
@@ -146,12 +156,15 @@ hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s);
 // launch_ibm runs the coupling up to h(t+1) (it reads `prev`, the buffer the
 // lattice kernel reads, not the lattice kernel's output, so it may run
 // beside it); launch_correct then adds the forcing to `cur`.
+// prev_id / cur_id: the population buffer (0 or 1) of prev / cur, whose
+// full-precision box the kernels read / update.
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
                       int n_mtiles, int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles,
-                      int diag, int force_surface, hipStream_t s);
-hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3, hipStream_t s);
+                      int diag, int force_surface, int prev_id, hipStream_t s);
+hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3, int cur_id,
+                          hipStream_t s);
 hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s);
-hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s);
+hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, hipStream_t s);
 
 }  // namespace turret

@@ -23,6 +23,7 @@
 
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "fine.hpp"
 #include "pull.hpp"
 #include "mlp.hpp"
 #include "moments.hpp"
@@ -208,7 +209,7 @@ __device__ inline void pull_region(const DevPtrs &p, const CaseDev &cd, int a, i
 // by k_markers (inside some tile's stencil box) are visited; the others are
 // read by no interpolation and carry no force.
 template <class CD>
-__global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs p)
+__global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs p, int sid)
 {
     const int c = blockIdx.y;
     const CaseDev cd = p.cases[c];
@@ -234,11 +235,18 @@ __global__ void k_region_gather(const typename CD::T *__restrict__ src, DevPtrs 
     }
     const int gx = wrapi(B.org[0] + a, cd.nx), gy = wrapi(B.org[1] + b, cd.ny);
     float g[Q];
-    if constexpr (std::is_same<CD, CodecMom>::value)
+    if constexpr (std::is_same<CD, CodecMom>::value) {
         pull_region(p, cd, a, b, cc, gz, g);
-    else
+    } else if (cd.LB[0] > 0) {
+        // reduced-precision store with a full-precision box around the body
+        const BodyDev &Bd = p.body[c];
+        const int fo[3] = {Bd.fo[sid][0], Bd.fo[sid][1], Bd.fo[sid][2]};
+        pull_fine<CD>(src + cd.pop_off, Bd.fvalid[sid] ? p.fine[sid] + cd.fine_off : nullptr, cd, B.z0, fo, gx, gy, gz,
+                      g);
+    } else {
         pull<CD>(src + cd.pop_off, cd.plane, cd.nx, cd.ny, cd.nz, B.z0, cd.bc_lo, cd.bc_hi, cd.uw_lo, cd.uw_hi, gx, gy,
                  gz, g);
+    }
     const Macro M = macro(raw_moments(g));
     const float tau = tau_at(cd.tau0, cd.nz, cd.sponge, gz);
     const float fac = 0.5f / tau - 1.0f;
@@ -1123,7 +1131,7 @@ __global__ void k_targets(DevPtrs p, int Mtot, float *out)
 // the first-order term w_i xi_i . (tau - 1) rho h / cs^2).  Only cells
 // marked this step can carry a force; their marks are cleared here.
 template <class CD>
-__global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
+__global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p, int did)
 {
     const int c = blockIdx.y;
     const CaseDev cd = p.cases[c];
@@ -1155,11 +1163,28 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
     }
     const float rho = 1.0f + R[q];
     const float u[3] = {R[L3 + q], R[2 * L3 + q], R[3 * L3 + q]};
+    // a cell of the full-precision box is corrected there (FP32) and stored
+    // rounded once; elsewhere the stored value is decoded and re-rounded
+    int slot = -1;
+    float *F = nullptr;
+    long long fplane = 0;
+    if (cd.LB[0] > 0 && p.body[c].fvalid[did]) {
+        const BodyDev &Bd = p.body[c];
+        const int fo[3] = {Bd.fo[did][0], Bd.fo[did][1], Bd.fo[did][2]};
+        slot = fine_slot(cd, fo, gx, gy, gz);
+        F = p.fine[did] + cd.fine_off;
+        fplane = fine_plane(cd);
+    }
     float g[Q];
-    Unroll<0, Q>::run([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        g[i] = CD::template dec<i>(dst[(long long)i * cd.plane + off]);
-    });
+    if (slot >= 0) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) g[i] = F[(long long)i * fplane + slot];
+    } else {
+        Unroll<0, Q>::run([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            g[i] = CD::template dec<i>(dst[(long long)i * cd.plane + off]);
+        });
+    }
     if ((h0 | h1 | h2) == 0) return;
     const float tau = tau_at(cd.tau0, cd.nz, cd.sponge, gz);
     const float us[3] = {u[0] + tau * (float)((double)h0 * kFixInv), u[1] + tau * (float)((double)h1 * kFixInv),
@@ -1177,7 +1202,10 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p)
     hermite_to_populations(A, d);
     Unroll<0, Q>::run([&](auto I) {
         constexpr int i = decltype(I)::value;
-        dst[(long long)i * cd.plane + off] = CD::template enc<i>(g[i] + d[i]);
+        const float v = g[i] + d[i];
+        if constexpr (!std::is_same<CD, CodecF32>::value)
+            if (slot >= 0) F[(long long)i * fplane + slot] = v;
+        dst[(long long)i * cd.plane + off] = CD::template enc<i>(v);
     });
 }
 
@@ -1241,12 +1269,14 @@ __global__ void k_window_trigger(DevPtrs p, int n_cases)
     if (cd.M == 0 || B.err != 0 || cd.dz <= 0 || !(cd.h_end > 0.0) || !(B.r[2] < cd.h_end)) return;
     B.r[2] += (double)cd.dz;
     B.z0 = wrapi(B.z0 - cd.dz, cd.nz);
+    B.fo[0][2] += cd.dz;   // the full-precision boxes move with the content
+    B.fo[1][2] += cd.dz;
     B.shift_now = 1;
     B.shifts += 1;
 }
 
 template <class CD>
-__global__ void k_window_reset(typename CD::T *__restrict__ cur, DevPtrs p)
+__global__ void k_window_reset(typename CD::T *__restrict__ cur, DevPtrs p, int cid)
 {
     const int c = blockIdx.y;
     const CaseDev &cd = p.cases[c];
@@ -1267,6 +1297,15 @@ __global__ void k_window_reset(typename CD::T *__restrict__ cur, DevPtrs p)
                 constexpr int i = decltype(I)::value;
                 dst[(long long)i * cd.plane] = CD::template enc<i>(0.0f);
             });
+            if (cd.LB[0] > 0 && B.fvalid[cid]) {
+                const int slot = fine_slot(cd, B.fo[cid], rem % cd.nx, rem / cd.nx, zrow);
+                if (slot >= 0) {
+                    float *F = p.fine[cid] + cd.fine_off;
+                    const long long fplane = fine_plane(cd);
+#pragma unroll
+                    for (int i = 0; i < Q; i++) F[(long long)i * fplane + slot] = 0.0f;
+                }
+            }
         }
     }
 }
@@ -1281,7 +1320,7 @@ hipError_t launch_body_advance(const DevPtrs &p, int n_cases, hipStream_t s)
 template <class CD>
 static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot, int n_mtiles,
                            int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles, int diag,
-                           int force_surface, hipStream_t s)
+                           int force_surface, int prev_id, hipStream_t s)
 {
     using T = typename CD::T;
     const dim3 blk(256);
@@ -1295,7 +1334,7 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
         const long long E3 = (long long)(L + 2) * (L + 2) * (L + 2);
         hipLaunchKernelGGL(k_region_expand_mom, dim3((unsigned)((E3 + 255) / 256), n_cases), blk, 0, s, (const T *)prev, p);
     }
-    hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p);
+    hipLaunchKernelGGL(k_region_gather<CD>, reg_grid, blk, 0, s, (const T *)prev, p, prev_id);
     // plain start with at most kHBufs cycles: each cycle's spread rides on
     // the pass before it (force + spread 1, update c + spread c + 1)
     static_assert(kHBufs == 4, "the launch below instantiates 1..4 accumulators");
@@ -1357,44 +1396,45 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
 }
 
 template <class CD>
-static hipError_t correct_impl(void *cur, const DevPtrs &p, int n_cases, int maxL3, hipStream_t s)
+static hipError_t correct_impl(void *cur, const DevPtrs &p, int n_cases, int maxL3, int cur_id, hipStream_t s)
 {
     const dim3 reg_grid((maxL3 + 255) / 256, n_cases);
-    hipLaunchKernelGGL(k_correct<CD>, reg_grid, dim3(256), 0, s, (typename CD::T *)cur, p);
+    hipLaunchKernelGGL(k_correct<CD>, reg_grid, dim3(256), 0, s, (typename CD::T *)cur, p, cur_id);
     return hipGetLastError();
 }
 
-hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3, hipStream_t s)
+hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3, int cur_id,
+                          hipStream_t s)
 {
     if (Mtot == 0) return hipSuccess;
     switch (storage) {
     case ST_MOM:
         hipLaunchKernelGGL(k_correct_mom, dim3((maxL3 + 255) / 256, n_cases), dim3(256), 0, s, p);
         return hipGetLastError();
-    case ST_F16: return correct_impl<CodecF16>(cur, p, n_cases, maxL3, s);
-    case ST_BF16: return correct_impl<CodecBF16>(cur, p, n_cases, maxL3, s);
-    default: return correct_impl<CodecF32>(cur, p, n_cases, maxL3, s);
+    case ST_F16: return correct_impl<CodecF16>(cur, p, n_cases, maxL3, cur_id, s);
+    case ST_BF16: return correct_impl<CodecBF16>(cur, p, n_cases, maxL3, cur_id, s);
+    default: return correct_impl<CodecF32>(cur, p, n_cases, maxL3, cur_id, s);
     }
 }
 
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
                       int n_mtiles, int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles,
-                      int diag, int force_surface, hipStream_t s)
+                      int diag, int force_surface, int prev_id, hipStream_t s)
 {
     if (Mtot == 0) return hipSuccess;
     switch (storage) {
     case ST_MOM:
         return ibm_impl<CodecMom>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16, warm_cycles,
-                                  diag, force_surface, s);
+                                  diag, force_surface, prev_id, s);
     case ST_F16:
         return ibm_impl<CodecF16>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16, warm_cycles,
-                                  diag, force_surface, s);
+                                  diag, force_surface, prev_id, s);
     case ST_BF16:
         return ibm_impl<CodecBF16>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16,
-                                   warm_cycles, diag, force_surface, s);
+                                   warm_cycles, diag, force_surface, prev_id, s);
     default:
         return ibm_impl<CodecF32>(prev, cur, p, n_cases, Mtot, n_mtiles, maxL3, cycles, warm_mode, th16, warm_cycles,
-                                  diag, force_surface, s);
+                                  diag, force_surface, prev_id, s);
     }
 }
 
@@ -1405,24 +1445,25 @@ hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s)
 }
 
 template <class CD>
-static hipError_t window_impl(void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s)
+static hipError_t window_impl(void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, hipStream_t s)
 {
     hipLaunchKernelGGL(k_window_trigger, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
     if (max_slab > 0) {
         // about 2048 workgroups in all, at least 8 per case
         const int per_case = std::max(8, std::min((max_slab + 255) / 256, 2048 / n_cases));
-        hipLaunchKernelGGL(k_window_reset<CD>, dim3(per_case, n_cases), dim3(256), 0, s, (typename CD::T *)cur, p);
+        hipLaunchKernelGGL(k_window_reset<CD>, dim3(per_case, n_cases), dim3(256), 0, s, (typename CD::T *)cur, p,
+                           cur_id);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, hipStream_t s)
+hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, hipStream_t s)
 {
     switch (storage) {
-    case ST_MOM: return window_impl<CodecMom>(cur, p, n_cases, max_slab, s);
-    case ST_F16: return window_impl<CodecF16>(cur, p, n_cases, max_slab, s);
-    case ST_BF16: return window_impl<CodecBF16>(cur, p, n_cases, max_slab, s);
-    default: return window_impl<CodecF32>(cur, p, n_cases, max_slab, s);
+    case ST_MOM: return window_impl<CodecMom>(cur, p, n_cases, max_slab, cur_id, s);
+    case ST_F16: return window_impl<CodecF16>(cur, p, n_cases, max_slab, cur_id, s);
+    case ST_BF16: return window_impl<CodecBF16>(cur, p, n_cases, max_slab, cur_id, s);
+    default: return window_impl<CodecF32>(cur, p, n_cases, max_slab, cur_id, s);
     }
 }
 

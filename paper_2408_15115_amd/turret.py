@@ -44,7 +44,7 @@ class lbm_options(C.Structure):
     _fields_ = [("storage", C.c_int32), ("ibm_cycles", C.c_int32), ("block", C.c_int32),
                 ("schedule", C.c_int32), ("persist_wgs", C.c_int32), ("tile_order", C.c_int32),
                 ("ibm_diag", C.c_int32), ("forcing", C.c_int32), ("serial_ibm", C.c_int32),
-                ("collision", C.c_int32), ("lattice", C.c_int32)]
+                ("collision", C.c_int32), ("lattice", C.c_int32), ("fine_box", C.c_int32)]
 
 
 class lbm_buffers(C.Structure):
@@ -152,12 +152,12 @@ def make_body(d: dict | None, keep: list) -> lbm_body:
 
 
 def make_options(storage="f32", ibm_cycles=4, block=256, schedule=0, persist_wgs=0, tile_order=0,
-                 ibm_diag=0, forcing=0, serial_ibm=0, collision=0, lattice=27) -> lbm_options:
+                 ibm_diag=0, forcing=0, serial_ibm=0, collision=0, lattice=27, fine_box=0) -> lbm_options:
     o = lbm_options()
     o.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     o.ibm_cycles, o.block, o.schedule, o.persist_wgs = int(ibm_cycles), int(block), int(schedule), int(persist_wgs)
     o.tile_order, o.ibm_diag, o.forcing, o.serial_ibm = int(tile_order), int(ibm_diag), int(forcing), int(serial_ibm)
-    o.collision, o.lattice = int(collision), int(lattice)
+    o.collision, o.lattice, o.fine_box = int(collision), int(lattice), int(fine_box)
     return o
 
 
@@ -189,7 +189,12 @@ class Solver:
 
     def __init__(self, cases, bodies=None, storage="f32", ibm_cycles=4, block=256, schedule=0,
                  persist_wgs=0, tile_order=0, ibm_diag=0, forcing=0, serial_ibm=0, collision=0, stream=None,
-                 device="cuda", lattice=27):
+                 device="cuda", lattice=27, fine_box=None):
+        # FP16/BF16 storage keeps the full-precision box around each body
+        # unless told otherwise
+        if fine_box is None:
+            fine_box = int(storage in ("f16", "bf16") and bodies is not None
+                           and any(b is not None and len(b["x_body"]) > 0 for b in bodies))
         import torch
 
         self.torch = torch
@@ -199,7 +204,7 @@ class Solver:
         self._bodies = ((lbm_body * self.n)(*[make_body(b, self._keep) for b in bodies])
                         if bodies is not None else None)
         self._opt = make_options(storage, ibm_cycles, block, schedule, persist_wgs, tile_order, ibm_diag, forcing,
-                                 serial_ibm, collision, lattice)
+                                 serial_ibm, collision, lattice, fine_box)
         self.q = 19 if lattice == 19 else 27
         self.dims = [(int(c["nx"]), int(c["ny"]), int(c["nz"])) for c in cases]
         sizes = (C.c_int64 * 3)()
@@ -239,7 +244,7 @@ class Solver:
     def set_schedule(self, block=256, schedule=0, persist_wgs=0, tile_order=0):
         o = make_options(self._opt.storage, self._opt.ibm_cycles, block, schedule, persist_wgs, tile_order,
                          self._opt.ibm_diag, self._opt.forcing, self._opt.serial_ibm, self._opt.collision,
-                         self._opt.lattice)
+                         self._opt.lattice, self._opt.fine_box)
         self._chk("lbm_set_schedule", lbm_set_schedule(self._ctx, C.byref(o)))
         self._opt = o
 

@@ -162,3 +162,19 @@ def test_step_tuner_times_whole_steps_and_caches(T, tmp_path):
     assert r1["ms"] > 0 and r1["lattice_ms"] > 0
     r2 = autotune.tune_step(cases, bodies, candidates=cands, path=path, steps=3, warmup=1)
     assert r2["cached"] and r2["best"] == r1["best"]
+
+
+def test_fp16_batch_case_equals_case_alone(T):
+    """FP16 storage with a full-precision box per body: each case of the
+    batch (persistent work-queue schedule) equals the case run alone."""
+    cases, bodies = small_batch()
+    S = T.Solver(cases, bodies, storage="f16", schedule=3, persist_wgs=11)
+    S.run(12)
+    for c in range(3):
+        A = T.Solver([cases[c]], [bodies[c]], storage="f16")
+        A.run(12)
+        assert np.array_equal(S.populations(c), A.populations()), c
+        for k in ("r", "v", "w", "F", "T"):
+            assert np.array_equal(S.body_state(c)[k], A.body_state()[k]), (c, k)
+        A.close()
+    S.close()

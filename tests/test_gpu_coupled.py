@@ -182,12 +182,15 @@ def test_force_surface_variant_matches_oracle(T, orc):
     assert abs(pm["F"][2] - ost["F"][2]) > 1e-2 * Fs
 
 
-def test_concurrent_coupling_equals_serial(T):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_concurrent_coupling_equals_serial(T, storage):
     """The coupling beside the lattice kernel (second stream) and after it on
-    the context stream give identical results: only the schedule differs."""
+    the context stream give identical results: only the schedule differs
+    (FP16 with its full-precision box around the body, across a window
+    shift)."""
     case, body = small_sphere(h_end=19.5 - 1e-6, h_ini=25.5, sponge=5)
-    A = T.Solver([case], [body], serial_ibm=0)
-    B = T.Solver([case], [body], serial_ibm=1)
+    A = T.Solver([case], [body], serial_ibm=0, storage=storage)
+    B = T.Solver([case], [body], serial_ibm=1, storage=storage)
     A.run(30)
     B.run(30)
     a, b = A.body_state(), B.body_state()
@@ -197,13 +200,14 @@ def test_concurrent_coupling_equals_serial(T):
     assert np.array_equal(A.populations(), B.populations())
 
 
-def test_graph_replay_equals_eager(T):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_graph_replay_equals_eager(T, storage):
     import torch
     case, body = small_sphere()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        A = T.Solver([case], [body], stream=stream)
-        B = T.Solver([case], [body], stream=stream)
+        A = T.Solver([case], [body], stream=stream, storage=storage)
+        B = T.Solver([case], [body], stream=stream, storage=storage)
         A.run(2)
         B.graph_capture(2)
         B.graph_launch()
@@ -230,14 +234,18 @@ def test_runs_are_bitwise_deterministic(T):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
-def test_checkpoint_resume_is_bitwise(T, tmp_path):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_checkpoint_resume_is_bitwise(T, tmp_path, storage):
+    """Save after an odd number of steps, resume in a fresh context (whose
+    current buffer is the other one): the runs continue bit for bit, FP16's
+    full-precision box included."""
     case, body = small_sphere()
-    A = T.Solver([case], [body])
+    A = T.Solver([case], [body], storage=storage)
     A.run(7)
     path = os.path.join(tmp_path, "ck.bin")
     A.save(path)
     A.run(6)
-    B = T.Solver([case], [body])
+    B = T.Solver([case], [body], storage=storage)
     B.load(path)
     B.run(6)
     assert np.array_equal(A.populations(), B.populations())

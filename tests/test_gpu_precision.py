@@ -1,12 +1,16 @@
 """Precision form: the 48^3 sphere case with populations stored as FP32, FP16
-and BF16 deviations f_i - w_i (per-direction scale, FP32 arithmetic, FP64
-force/torque sums and rigid-body update), compared over 2000 steps with the
-stored FP64 oracle trajectory (tests/golden/sphere48_fp64_trajectory.txt,
-written by make_sphere48_trajectory.py from the oracle only).
+and BF16 deviations f_i - w_i (per-direction power-of-two scale, FP32
+arithmetic, FP64 force/torque sums and rigid-body update), compared over 2000
+steps with the stored FP64 oracle trajectory
+(tests/golden/sphere48_fp64_trajectory.txt, written by
+make_sphere48_trajectory.py from the oracle only).  FP16 and BF16 runs keep
+the library's full-precision box around the body (the particle region and a
+one-cell rim stored in FP32); the FP16 run without it is reported beside.
 
 Reported per storage: drag (F_z) relative error at step 200 and its maximum
-over steps 200..2000, and the relative error of the settling velocity v_z at
-step 2000 (the terminal-velocity proxy of the plain-method case)."""
+over steps 200..2000, the drag averaged over steps 1001..2000, and the
+relative error of the settling velocity v_z at step 2000 (the
+terminal-velocity proxy of the plain-method case)."""
 import json
 import os
 
@@ -24,10 +28,12 @@ OUTDIR = os.environ.get("TURRET_RESULTS_DIR")
 
 # Bounds per storage: instantaneous drag error (max over steps 200..2000),
 # drag averaged over steps 1001..2000, and v_z at step 2000.  FP32 is held to
-# the parity tolerance.  FP16 measures 1.3e-3 / 9e-6 / 3.2e-4; BF16 (an 8-bit
-# significand) 2.2e-2 / 1.1e-3 / 4.3e-3, which misses the 1e-3 drag target,
-# and its bounds state that level.
-BOUND = {"f32": (1e-4, 1e-4, 1e-4), "f16": (5e-3, 1e-3, 1e-3), "bf16": (3e-2, 3e-2, 3e-2)}
+# the parity tolerance and FP16 to the 1e-3 target on all three.  BF16 (an
+# 8-bit significand) misses the 1e-3 drag target even with the box (the
+# oracle's model of BF16 storage with the box reaches 1.7e-2 on the
+# instantaneous drag); its bounds state that level.  FP16 without the box
+# reaches 1.3e-3 / 9e-6 / 3.2e-4 and is only reported.
+BOUND = {"f32": (1e-4, 1e-4, 1e-4), "f16": (1e-3, 1e-3, 1e-3), "bf16": (3e-2, 3e-2, 3e-2)}
 
 
 @pytest.fixture(scope="module")
@@ -43,12 +49,13 @@ def T():
     return turret
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f16-nobox"])
 def test_drag_and_settling_velocity_vs_fp64(T, golden, storage):
     case, body = W.case_sphere48()
     steps = int(golden[-1, 0])
     say(f"precision form: sphere48, {storage}, {steps} steps")
-    S = T.Solver([case], [body], storage=storage)
+    fine = 0 if storage.endswith("nobox") else None
+    S = T.Solver([case], [body], storage=storage.split("-")[0], fine_box=fine)
     Fz = np.empty(steps)
     vz = np.empty(steps)
     for n in range(steps):
@@ -71,6 +78,8 @@ def test_drag_and_settling_velocity_vs_fp64(T, golden, storage):
         with open(os.path.join(OUTDIR, f"precision_{storage}.json"), "w") as f:
             json.dump(res, f)
         np.save(os.path.join(OUTDIR, f"precision_{storage}_Fz_vz.npy"), np.stack([Fz, vz]))
+    if storage not in BOUND:
+        return
     b_inst, b_avg, b_v = BOUND[storage]
     assert drag_max < b_inst
     assert drag_avg < b_avg

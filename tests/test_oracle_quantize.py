@@ -77,3 +77,25 @@ def test_quantized_step_is_collide_round_stream(orc, storage):
         g = orc.stream_grid(orc.quantize(orc.collide_grid(g, tau), storage), W.BC_FREESLIP, W.BC_FREESLIP)
     assert np.array_equal(s.populations(), g)
     assert np.array_equal(s.post_collision(), orc.quantize(orc.collide_grid(g, tau), storage))
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_full_precision_box_around_the_body(orc, storage):
+    """With a box, the cells of the cube floor(r - rb) - 3 .. + edge - 1
+    around the body keep the unrounded collision; the others are rounded."""
+    n, nz, tau = 20, 28, 0.7
+    case = W.make_case(n, n, nz, tau, W.BC_FREESLIP, W.BC_FREESLIP, 0, 2e-5)
+    body = W.sphere_fibonacci_body(3.0, 200, 2.0, [n - 2.3, 4.6, 13.2], w0=np.array([0.0, 1e-3, 2e-3]))
+    rb, edge = 6.02, (18, 17, 19)          # reaches across the periodic x edge
+    s = orc.OracleSim(case, body)
+    s.set_storage(storage, (rb, edge))
+    s.step(3)
+    C = s.post_collision()
+    direct = orc.collide_grid(s.populations(), tau, 0, h=s.immersed_force())
+    r = s.body_state()["r"]
+    lo = np.floor(r - rb).astype(int) - 3
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(n), np.arange(n), indexing="ij")
+    inside = (((x - lo[0]) % n) < edge[0]) & (((y - lo[1]) % n) < edge[1]) & ((z - lo[2]) >= 0) & ((z - lo[2]) < edge[2])
+    assert 0 < inside.sum() < inside.size
+    assert np.array_equal(C[inside], direct[inside])
+    assert np.array_equal(C[~inside], orc.quantize(direct[~inside], storage))
