@@ -532,23 +532,142 @@ def lattice_rate_run(T, W, torch, n=(256, 256, 768), steps=20, warmup=3):
     return out
 
 
-def cpu_baseline(case, body, steps):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload: the
-    same body, relaxation time and walls in a 128^3 window."""
-    from oracle import oracle as O
-    c = dict(case)
-    c.update(nx=128, ny=128, nz=128, sponge=10, h_ini=0.0, h_end=0.0)
-    b = dict(body)
-    b["r0"] = [63.5, 63.5, 63.5]
-    sim = O.OracleSim(c, b)
+def long_run(T, W, torch, which, steps, storage="f32", chunk=None):
+    """The stated run lengths, once: the scale case for 20k steps (about five
+    window shifts) or the 64-case batch for 5k steps.  Graph replay in chunks;
+    after each chunk the body states (shifts, drag, velocity, the Reynolds
+    number reached, error bits) are read back and logged."""
+    import numpy as np
+    from paper_2408_15115_amd import autotune
+    if which == "scale":
+        case, body = W.case_ellipsoid_tall()
+        cases, bodies = [case], [body]
+        sched = {}
+        chunk = chunk or 1000
+    else:
+        batch = W.batch_cases(64)
+        cases, bodies = [c for c, _ in batch], [b for _, b in batch]
+        sched = autotune.tune_step(cases, bodies, storage=storage)["best"]
+        chunk = chunk or 250
+    S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), **sched)
+    S.graph_capture(2)
+    nu = [(c["tau"] - 0.5) / 3.0 for c in cases]
+    rows, done = [], 0
+    t0 = time.perf_counter()
+    gpu_ms = 0.0
+    while done < steps:
+        n = min(chunk, steps - done)
+        n -= n % 2
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(S.stream)
+        for _ in range(n // 2):
+            S.graph_launch()
+        e1.record(S.stream)
+        torch.cuda.synchronize()
+        gpu_ms += e0.elapsed_time(e1)
+        done += n
+        st = [S.body_state(c, check=False) for c in range(len(cases))]
+        re = [float(np.linalg.norm(b["v"]) * c.get("d_eq", 0.0) / v) for b, c, v in zip(st, cases, nu)]
+        masked = [c for c, b in enumerate(st) if b["err"]]
+        row = {"step": done, "shifts": [b["shifts"] for b in st] if which != "scale" else st[0]["shifts"],
+               "masked": masked}
+        if which == "scale":
+            row.update(Fz=float(st[0]["F"][2]), vz=float(st[0]["v"][2]), rz=float(st[0]["r"][2]), re=round(re[0], 3),
+                       err=st[0]["err"])
+        rows.append(row)
+        log(f"  {which}: step {done}/{steps}, {gpu_ms / done:.3f} ms per step, shifts "
+            f"{row['shifts'] if which == 'scale' else sum(row['shifts'])}, masked {masked}"
+            + (f", F_z {row['Fz']:.4e}, v_z {row['vz']:.4e}, Re {row['re']:.2f}" if which == "scale" else ""))
+    wall = time.perf_counter() - t0
+    st = [S.body_state(c, check=False) for c in range(len(cases))]
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    cells = sum(c["nx"] * c["ny"] * c["nz"] for c in cases)
+    out = {"workload": which, "steps": steps, "storage": storage, "cells": cells, "ms_per_step": gpu_ms / steps,
+           "mlups": cells * steps / (gpu_ms * 1e-3) / 1e6, "wall_s": round(wall, 1), "chunks": rows}
+    if which != "scale":
+        out["schedule"] = sched
+        out["cases"] = [{"seed": 2408 + c, "shape": cases[c]["shape"], "box": [cases[c]["nx"], cases[c]["ny"], cases[c]["nz"]],
+                         "tau": round(cases[c]["tau"], 5), "kappa": round(bodies[c]["kappa"], 3),
+                         "re_target": round(cases[c]["re"], 3), "re_reached": round(float(
+                             np.linalg.norm(st[c]["v"]) * cases[c]["d_eq"] / nu[c]), 3),
+                         "shifts": st[c]["shifts"], "err": st[c]["err"]} for c in range(len(cases))]
+    return out
+
+
+def cpu_model():
+    """CPU model name of the host (from /proc/cpuinfo, as lscpu reads it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_rate(O, case, body, steps, threads):
+    """MLUPS of the FP64 oracle's coupled step on `threads` threads (one
+    untimed step first)."""
+    O.set_threads(threads)
+    sim = O.OracleSim(case, body)
     sim.step(1)
     t = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t
-    cells = 128 ** 3
-    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"128^3 window of the workload (same ellipsoid, 12252 markers, tau, walls), "
-                      f"{steps} coupled steps after 1 untimed, FP64, {dt:.1f} s"}
+    cells = case["nx"] * case["ny"] * case["nz"]
+    return {"mlups": round(cells * steps / dt / 1e6, 4), "steps": steps, "threads": threads, "seconds": round(dt, 2)}
+
+
+def scale_window(case, body, nx, ny, nz):
+    """A window of the scale case around its body (same body, tau, walls),
+    sponge scaled with the height, no re-injection."""
+    c = dict(case)
+    c.update(nx=nx, ny=ny, nz=nz, sponge=int(round(0.08 * nz)), h_ini=0.0, h_end=0.0)
+    b = dict(body)
+    b["r0"] = [(nx - 1) / 2.0, (ny - 1) / 2.0, 0.5 * nz]
+    return c, b
+
+
+def cpu_baseline(case, body, steps, full=False):
+    """The FP64 oracle, as it stands, timed on the host cores.  Default: a
+    bounded sample -- the 48^3 sphere case for `steps` steps on all threads
+    and for 4 steps on one thread, and a 128^3 window of the scale case for
+    `steps` steps on all threads (the value: its MLUPS).  full=True: the
+    whole set -- the sphere case for 200 and 2,000 steps on all threads and
+    200 on one, the 128 x 128 x 384 slice of the scale case for 100 steps on
+    all threads and 5 on one."""
+    from oracle import oracle as O
+    from paper_2408_15115_amd import workloads as W
+    threads = O.num_threads()
+    s_case, s_body = W.case_sphere48()
+    rows = {}
+    if full:
+        for n in (200, 2000):
+            rows[f"sphere48_{n}_steps_all"] = _oracle_rate(O, s_case, s_body, n, threads)
+            log(f"  cpu: sphere48 {n} steps, {threads} threads: {rows[f'sphere48_{n}_steps_all']}")
+        rows["sphere48_200_steps_1thread"] = _oracle_rate(O, s_case, s_body, 200, 1)
+        log(f"  cpu: sphere48 200 steps, 1 thread: {rows['sphere48_200_steps_1thread']}")
+        c, b = scale_window(case, body, 128, 128, 384)
+        rows["slice128x128x384_100_steps_all"] = _oracle_rate(O, c, b, 100, threads)
+        log(f"  cpu: slice 100 steps, {threads} threads: {rows['slice128x128x384_100_steps_all']}")
+        rows["slice128x128x384_5_steps_1thread"] = _oracle_rate(O, c, b, 5, 1)
+        log(f"  cpu: slice 5 steps, 1 thread: {rows['slice128x128x384_5_steps_1thread']}")
+        value = rows["slice128x128x384_100_steps_all"]
+        sample = "128 x 128 x 384 slice of the workload (same ellipsoid, 12252 markers, tau, walls), 100 coupled steps"
+    else:
+        rows["sphere48_all"] = _oracle_rate(O, s_case, s_body, steps, threads)
+        rows["sphere48_1thread"] = _oracle_rate(O, s_case, s_body, 4, 1)
+        c, b = scale_window(case, body, 128, 128, 128)
+        rows["window128_all"] = _oracle_rate(O, c, b, steps, threads)
+        value = rows["window128_all"]
+        sample = (f"128^3 window of the workload (same ellipsoid, 12252 markers, tau, walls), {steps} coupled steps "
+                  f"after 1 untimed, FP64, {value['seconds']} s")
+    O.set_threads(threads)
+    return {"value": value["mlups"], "unit": "MLUPS", "cores": threads, "kind": "oracle", "sample": sample,
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "one_thread_mlups": (
+                rows.get("sphere48_1thread") or rows.get("sphere48_200_steps_1thread"))["mlups"], "runs": rows}
 
 
 def main():
@@ -558,7 +677,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "mom"])
     ap.add_argument("--variant-steps", type=int, default=400)
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="run only the full CPU-oracle timing set (sphere case 200 / 2,000 steps, slice 100 steps)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -578,6 +699,9 @@ def main():
                     help="run only the fluid-only lattice kernel comparison (D3Q27, D3Q19, moment storage)")
     ap.add_argument("--table3", type=str, default=None,
                     help="D[:Re1,Re2,...]: run only the terminal-velocity comparison of Table 3 at diameter D cells")
+    ap.add_argument("--long", choices=["scale", "batch"], default=None,
+                    help="run only the stated run length of the scale case (20k steps) or the batch (5k steps)")
+    ap.add_argument("--long-steps", type=int, default=None)
     ap.add_argument("--coupling", default="auto", choices=["auto", "serial", "beside"],
                     help="where the coupling runs: chosen by timing both (auto), after the lattice kernel, or "
                          "beside it on a second stream")
@@ -599,6 +723,16 @@ def main():
         copy = None if args.no_copy else round(copy_bandwidth(T, torch), 1)
         print(json.dumps({"metric": "fluid-only lattice kernel rates", "data": "synthetic", "copy_GBps": copy,
                           "rows": lattice_rate_run(T, W, torch, steps=args.steps)}))
+        return
+    if args.cpu_full:
+        case, body = W.case_ellipsoid_tall()
+        print(json.dumps({"metric": "FP64 CPU oracle timings", "data": "synthetic",
+                          "cpu_baseline": cpu_baseline(case, body, 0, full=True)}), flush=True)
+        return
+    if args.long:
+        n = args.long_steps or (20000 if args.long == "scale" else 5000)
+        print(json.dumps({"metric": f"stated run length, {args.long}", "data": "synthetic",
+                          "result": long_run(T, W, torch, args.long, n, storage=args.storage)}), flush=True)
         return
     if args.table3:
         d, _, rl = args.table3.partition(":")
@@ -754,9 +888,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: FP64 oracle on a 128^3 sample")
+        log("cpu baseline: FP64 oracle on bounded samples")
         cpu = cpu_baseline(case, body, args.cpu_steps)
-        log(f"  {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+        log(f"  {cpu['value']:.3f} MLUPS on {cpu['cores']} threads ({cpu['cpu_model']}), one thread "
+            f"{cpu['one_thread_mlups']:.3f} MLUPS")
 
     achieved = main_run["k1_gbps"]
     out = {
