@@ -25,6 +25,7 @@ BODY = "tests/test_oracle_body.py"
 PHYS = "tests/test_oracle_physics.py"
 IBM = "tests/test_oracle_ibm.py"
 WALL = "tests/test_oracle_walls.py"
+SYM = "tests/test_oracle_symmetry.py"
 STOK = "tests/test_oracle_stokes.py"
 
 # (name, text in orc.c, replacement, pin files expected to catch it)
@@ -49,6 +50,7 @@ MUTANTS = [
     ("hermite_rec", "s -= CS2 * hermite(xi, sub, n - 2);", "s -= hermite(xi, sub, n - 2);", [COLL]),
     ("a1_perm_index", "s += prod * P1[al[(m - 1 + r) % m]][al[n - 1]];",
      "s += prod * P1[al[(m - 1) % m]][al[n - 1]];", [COLL]),
+    ("term_asymmetric", "{4, {X_, Y_, Y_, Z_}, 2.0}", "{4, {X_, Y_, Y_, Z_}, 1.0}", [SYM]),
     ("fneq_h2", "double s = h2 / (2.0 * CS2 * CS2);", "double s = h2 / (CS2 * CS2);", [COLL]),
     ("density", "*p = CS2 * (s - RHO0);", "*p = CS2 * s;", [COLL]),
     # collision and stress (Sec. 2.1, 2.2)
