@@ -327,7 +327,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_fine0 = take(sizeof(float) * std::max<long long>(P.fine_elems, 1));
     P.off_fine1 = take(sizeof(float) * std::max<long long>(P.fine_elems, 1));
     P.off_mtiles = take(sizeof(MarkerTile) * NT);
-    P.off_tbox = take(sizeof(TileBox) * NT);
+    P.off_tbox = take(sizeof(TileBox) * 2 * NT);   // the markers' and the force-surface points' boxes
     P.aux_bytes = o;
     (void)eb;
     return "";
@@ -695,8 +695,10 @@ static int32_t do_ibm(lbm_ctx *ctx)
         HIPCHK(ctx, hipEventRecord(ctx->join, ctx->side), "record join event");
         HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->join, 0), "stream waits for the coupling");
     }
+    const int resid_slot =
+        ibm_fused(ctx->warm_mode, ctx->opt.ibm_cycles) && !ctx->opt.ibm_diag ? ctx->opt.ibm_cycles - 1 : -1;
     HIPCHK(ctx, launch_correct(ctx->opt.storage, ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.Mtot, ctx->plan.maxL3,
-                               ctx->cur, ctx->stream),
+                               ctx->cur, resid_slot, ctx->stream),
            "forced correction");
     ctx->needs_ibm = false;
     return LBM_OK;

@@ -49,6 +49,7 @@ struct BodyDev {
     int org[3];      // IBM region origin (physical cell coordinates, x/y unwrapped)
     int fo[2][3];    // full-precision box origin of population buffer 0 / 1 (physical, x/y unwrapped)
     int fvalid[2];   // 1 once a step has written that buffer's box
+    unsigned int tiles_done[2];   // marker tiles of the case done in the current force / residual pass
     int err;         // 1: a marker stencil left the box in z; 2: non-finite or huge IBM value;
                      // 4: non-finite density or |u| > 0.5.  Nonzero masks (freezes) the case.
 };
@@ -117,7 +118,7 @@ struct DevPtrs {
     double *h0;      // per-marker plain start U - I[u*] (3)
     double *hs;      // per-marker scale of the warm-start features, |h0| + |h(t-1)|
     double *dSo;     // per-marker areas of the parallel force surface (cases with force_offset > 0)
-    TileBox *tbox;   // per-tile box, computed each step by k_markers
+    TileBox *tbox;   // per-tile boxes of the markers' stencils, then of the force-surface points', by k_markers
     float *dsh;      // moment storage: per region cell the forcing shift (Delta_x, Delta_y, Delta_z, lambda)
     float *rpop;     // moment storage: collided populations of the region and a one-cell rim, [27][xstride]
     long long xstride;
@@ -161,8 +162,14 @@ hipError_t launch_fine_step(int storage, const void *src, void *dst, const DevPt
 hipError_t launch_ibm(int storage, const void *prev, void *cur, const DevPtrs &p, int n_cases, int Mtot,
                       int n_mtiles, int maxL3, int cycles, int warm_mode, const _Float16 *th16, int warm_cycles,
                       int diag, int force_surface, int prev_id, hipStream_t s);
+// resid_slot >= 0: the correction also forms the case residual of the plain
+// fused forcing sequence (whose last pass leaves the tile maxima) into
+// resid and resid_hist[resid_slot].
 hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3, int cur_id,
-                          hipStream_t s);
+                          int resid_slot, hipStream_t s);
+// Whether the plain forcing sequence runs fused (each spread in the preceding
+// interpolation pass); it then leaves its residual to the correction.
+inline bool ibm_fused(int warm_mode, int cycles) { return warm_mode == 0 && cycles <= kHBufs; }
 hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s);
 hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, hipStream_t s);

@@ -7,8 +7,8 @@
 //                         tile boxes and the marks of the cells they cover
 //   k_region_gather       Sec. 2.1 stress and Sec. 2.2 u* on the particle region
 //   k_interp_force_tiles  Sec. 2.2: l = 0 interpolation and the stress integral
-//                         (+ the first spread)
-//   k_reduce_ft           FP64 force / torque sums (deterministic tree)
+//                         (+ the first spread); the last tile of a case forms
+//                         its FP64 force / torque totals in a fixed order
 //   k_spread_tiles        Sec. 2.2 spreading (deterministic fixed-point atomics)
 //   k_interp_update_tiles Sec. 2.2 interpolation of u* + H and the residual
 //                         (+ the next cycle's spread)
@@ -544,7 +544,8 @@ __global__ void __launch_bounds__(64) k_markers(DevPtrs p, int n_mtiles)
     if (lane == 0) p.tbox[tix] = tb;
     if (dl > 0.0) {
         const double Y[3] = {X[0] + dl * N[0], X[1] + dl * N[1], X[2] + dl * N[2]};
-        mark_points(p, cd, B, Y, mt.count, lane);
+        const TileBox to = mark_points(p, cd, B, Y, mt.count, lane);
+        if (lane == 0) p.tbox[n_mtiles + tix] = to;   // the force-surface points' box
     }
 }
 
@@ -609,6 +610,59 @@ __device__ inline void tile_part_sum(const DevPtrs &p, int tix, int count, const
         double acc = 0.0;
         for (int j = 0; j < count; j++) acc += tp[j][threadIdx.x];
         p.part[(long long)kPart * tix + threadIdx.x] = acc;
+    }
+}
+
+// Case totals of the per-tile force, torque and pressure-force parts, in a
+// fixed order: strided per-thread sums over the case's tiles, a fixed
+// butterfly inside each wavefront, then the wavefronts in order.
+__device__ inline void case_force_total(const DevPtrs &p, const CaseDev &cd, BodyDev &B)
+{
+    __shared__ double sh[4][kPart];
+    double acc[kPart];
+#pragma unroll
+    for (int j = 0; j < kPart; j++) acc[j] = 0.0;
+    for (int t = threadIdx.x; t < cd.n_tiles; t += blockDim.x) {
+        const double *o = p.part + (long long)kPart * (cd.tile_off + t);
+#pragma unroll
+        for (int j = 0; j < kPart; j++) acc[j] += o[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kPart; j++) acc[j] = wave_sum(acc[j]);
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < kPart; j++) sh[wave][j] = acc[j];
+    __syncthreads();
+    if (threadIdx.x < kPart) {
+        double v = 0.0;
+        for (int w = 0; w < nw; w++) v += sh[w][threadIdx.x];
+        double *dst = threadIdx.x < 3 ? &B.F[threadIdx.x] : (threadIdx.x < 6 ? &B.T[threadIdx.x - 3] : &B.Fp[threadIdx.x - 6]);
+        *dst = v;
+    }
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Case maximum of the per-tile residuals into resid and resid_hist[slot].
+__device__ inline void case_resid_total(const DevPtrs &p, const CaseDev &cd, BodyDev &B, int slot)
+{
+    __shared__ double sh[4];
+    double m = 0.0;
+    for (int t = threadIdx.x; t < cd.n_tiles; t += blockDim.x) m = fmax(m, p.res[cd.tile_off + t]);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) v = fmax(v, sh[w]);
+        B.resid = v;
+        if (slot >= 0 && slot < 16) B.resid_hist[slot] = v;
     }
 }
 
@@ -773,52 +827,17 @@ __global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mti
     if (spread && tb.fits) spread_flush(tb, ncell, L, L3, acc, H0);
 }
 
-// Stress-integral parts of marker k on the parallel surface at distance
-// force_offset outside it (point Y = X_k + delta n_k, same normal, area dSo):
-// one wavefront, parts into o[kPart] by lane 0.
-__device__ inline void offset_part(const DevPtrs &p, int k, const CaseDev &cd, const BodyView &B, const float *R,
-                                   int L3, int lane, double *o)
-{
-    const double nk[3] = {p.N[3 * k], p.N[3 * k + 1], p.N[3 * k + 2]};
-    double Y[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) Y[a] = p.X[3 * k + a] + cd.force_offset * nk[a];
-    const Node nd = stencil_node(Y, lane, cd, B);
-    // fields 0 (rho - 1) and 4..9 (sigma xx yy zz xy xz yz)
-    double v[7];
-#pragma unroll
-    for (int f = 0; f < 7; f++) {
-        const int fld = f == 0 ? 0 : f + 3;
-        v[f] = nd.q >= 0 ? nd.W * (double)R[fld * L3 + nd.q] : 0.0;
-    }
-#pragma unroll
-    for (int f = 0; f < 7; f++) v[f] = wave_sum(v[f]);
-    if (lane != 0) return;
-    const double pr = (double)CS2 * v[0];
-    const double sg[3][3] = {{v[1], v[4], v[5]}, {v[4], v[2], v[6]}, {v[5], v[6], v[3]}};
-    double s[3], rel[3], ts[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        s[a] = sg[a][0] * nk[0] + sg[a][1] * nk[1] + sg[a][2] * nk[2];
-        rel[a] = Y[a] - B.r[a];
-    }
-    cross3(rel, s, ts);
-    const double dA = p.dSo[k];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        o[a] = dA * s[a];
-        o[3 + a] = dA * ts[a];
-        o[6 + a] = dA * (-pr) * nk[a];
-    }
-}
-
 // Force surface variant: the stress integral on the parallel surface at
-// distance force_offset outside the markers (points X_k + delta n_k, same
-// normals, areas dSo).  One workgroup per marker tile, one wavefront per
-// marker; overwrites the tile's force, torque and pressure sums written by
-// the tile kernel.
+// distance force_offset outside the markers (points Y_k = X_k + delta n_k,
+// same normals, areas dSo).  One workgroup per marker tile, as the force
+// kernel: the box of the tile's surface-point stencils (from k_markers) is
+// staged in LDS with rho - 1 and sigma, a row of 16 lanes per marker sums
+// its stencil, one thread per marker forms its parts.  Overwrites the
+// tile's force, torque and pressure-force sums written by the tile kernel.
 __global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int n_mtiles)
 {
+    __shared__ float box[7][kBoxCells];
+    __shared__ double ev[kTileMarkers][7];
     __shared__ double tp[kTileMarkers][kPart];
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
@@ -826,12 +845,73 @@ __global__ void __launch_bounds__(256) k_offset_force(DevPtrs p, int n_mtiles)
     const CaseDev cd = p.cases[mt.c];
     const BodyView B = body_view(p.body[mt.c]);
     if (B.err != 0 || !(cd.force_offset > 0.0)) return;
-    const int L3 = cd.L * cd.L * cd.L;
+    const int L = cd.L, L3 = L * L * L;
     const float *R = p.reg + cd.reg_off * kRegFields;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int j = wave; j < mt.count; j += blockDim.x >> 6) {
-        const int k = mt.first + j;
-        offset_part(p, k, cd, B, R, L3, lane, tp[j]);
+    const TileBox tb = p.tbox[n_mtiles + tix];
+    const int ncell = tb.e[0] * tb.e[1] * tb.e[2];
+    // fields 0 (rho - 1) and 4..9 (sigma xx yy zz xy xz yz)
+    if (tb.fits) {
+        for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+            const int q = box_region_cell(i, tb, L);
+            box[0][i] = R[q];
+#pragma unroll
+            for (int f = 1; f < 7; f++) box[f][i] = R[(f + 3) * L3 + q];
+        }
+    }
+    __syncthreads();
+    const int j = threadIdx.x >> 4, col = threadIdx.x & 15;
+    const bool on = j < mt.count;
+    const int k = mt.first + (on ? j : 0);
+    const double dl = cd.force_offset;
+    double Y[3], w[12];
+#pragma unroll
+    for (int a = 0; a < 3; a++) Y[a] = p.X[3 * k + a] + dl * p.N[3 * k + a];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int n0 = (int)floor(Y[d]) - 1;
+#pragma unroll
+        for (int o = 0; o < 4; o++) w[4 * d + o] = phi4((double)(n0 + o) - Y[d]);
+    }
+    const Column cn = column_nodes(Y, w, col, tb, cd, B);
+    double v[7];
+#pragma unroll
+    for (int f = 0; f < 7; f++) v[f] = 0.0;
+#pragma unroll
+    for (int z = 0; z < 4; z++) {
+        if (tb.fits) {
+#pragma unroll
+            for (int f = 0; f < 7; f++) v[f] += cn.W[z] * (double)box[f][cn.i[z]];
+        } else if (cn.q[z] >= 0) {
+#pragma unroll
+            for (int f = 0; f < 7; f++) v[f] += cn.W[z] * (double)R[(f == 0 ? 0 : f + 3) * L3 + cn.q[z]];
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 7; f++) v[f] = row_sum(v[f]);
+    if (on && col == 0)
+#pragma unroll
+        for (int f = 0; f < 7; f++) ev[j][f] = v[f];
+    __syncthreads();
+    if ((int)threadIdx.x < mt.count) {
+        const int m = mt.first + threadIdx.x;
+        const double *e = ev[threadIdx.x];
+        const double nk[3] = {p.N[3 * m], p.N[3 * m + 1], p.N[3 * m + 2]};
+        const double pr = (double)CS2 * e[0];
+        const double sg[3][3] = {{e[1], e[4], e[5]}, {e[4], e[2], e[6]}, {e[5], e[6], e[3]}};
+        double s[3], rel[3], ts[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            s[a] = sg[a][0] * nk[0] + sg[a][1] * nk[1] + sg[a][2] * nk[2];
+            rel[a] = p.X[3 * m + a] + dl * nk[a] - B.r[a];
+        }
+        cross3(rel, s, ts);
+        const double dA = p.dSo[m];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            tp[threadIdx.x][a] = dA * s[a];
+            tp[threadIdx.x][3 + a] = dA * ts[a];
+            tp[threadIdx.x][6 + a] = dA * (-pr) * nk[a];
+        }
     }
     tile_part_sum(p, tix, mt.count, tp);
 }
@@ -887,7 +967,8 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, i
 // h_k += dh) into accumulator spread_to, which no interpolation of this
 // pass reads.
 template <int NB>
-__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked, int spread_to)
+__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked, int spread_to,
+                                                             int ft_total)
 {
     __shared__ double box[3][kBoxCells];
     __shared__ unsigned long long acc[3][kBoxCells];
@@ -972,76 +1053,36 @@ __global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mt
         p.res[tix] = m;
     }
     if (spread_to >= 0 && tb.fits) spread_flush(tb, ncell, L, L3, acc, Hs);
+    // the case's force totals from the force kernels' tile parts (complete at
+    // this kernel's start), formed by the workgroup of its first tile
+    if (ft_total && tix == cd.tile_off) case_force_total(p, cd, p.body[mt.c]);
 }
 
-// Deterministic FP64 sums of the per-tile parts of one case: strided
-// per-thread sums, a fixed butterfly inside each wavefront, then the
-// wavefronts in order.
-__global__ void __launch_bounds__(1024) k_reduce_ft(DevPtrs p)
+// FP64 force, torque and pressure-force totals of each case from its tile
+// parts (one 256-thread workgroup per case, fixed order).
+__global__ void __launch_bounds__(256) k_reduce_ft(DevPtrs p)
 {
-    __shared__ double sh[16][kPart];
     const int c = blockIdx.x;
     const CaseDev &cd = p.cases[c];
     if (cd.M == 0 || p.body[c].err != 0) return;
-    double acc[kPart];
-#pragma unroll
-    for (int j = 0; j < kPart; j++) acc[j] = 0.0;
-    for (int t = threadIdx.x; t < cd.n_tiles; t += blockDim.x) {
-        const double *o = p.part + (long long)kPart * (cd.tile_off + t);
-#pragma unroll
-        for (int j = 0; j < kPart; j++) acc[j] += o[j];
-    }
-#pragma unroll
-    for (int j = 0; j < kPart; j++) acc[j] = wave_sum(acc[j]);
-    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int j = 0; j < kPart; j++) sh[wave][j] = acc[j];
-    __syncthreads();
-    if (threadIdx.x < kPart) {
-        double v = 0.0;
-        for (int w = 0; w < nw; w++) v += sh[w][threadIdx.x];
-        sh[0][threadIdx.x] = v;   // each thread reads and writes only its own column
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        BodyDev &B = p.body[c];
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            B.F[a] = sh[0][a];
-            B.T[a] = sh[0][3 + a];
-            B.Fp[a] = sh[0][6 + a];
-        }
-    }
+    case_force_total(p, cd, p.body[c]);
 }
 
 // Max residual over the tiles of a case: into resid and resid_hist[slot].
 // With masked set only cases still active are reduced; with gate_cycle > 0
 // (a learned-start cycle) a case whose residual is at or below its gate is
 // accepted and leaves the sequence.
-__global__ void __launch_bounds__(1024) k_reduce_resid(DevPtrs p, int slot, int masked, int gate_cycle)
+__global__ void __launch_bounds__(256) k_reduce_resid(DevPtrs p, int slot, int masked, int gate_cycle)
 {
-    __shared__ double sh[1024];
     const int c = blockIdx.x;
     const CaseDev &cd = p.cases[c];
-    if (cd.M == 0 || p.body[c].err != 0 || (masked && !p.body[c].active)) return;
-    double m = 0.0;
-    for (int t = threadIdx.x; t < cd.n_tiles; t += blockDim.x) m = fmax(m, p.res[cd.tile_off + t]);
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        BodyDev &B = p.body[c];
-        B.resid = sh[0];
-        if (slot >= 0 && slot < 16) B.resid_hist[slot] = sh[0];
-        if (gate_cycle > 0 && sh[0] <= B.gate) {
-            B.active = 0;
-            B.accepts += 1;
-            B.warm_cyc_sum += gate_cycle;
-        }
+    BodyDev &B = p.body[c];
+    if (cd.M == 0 || B.err != 0 || (masked && !B.active)) return;
+    case_resid_total(p, cd, B, slot);
+    if (threadIdx.x == 0 && gate_cycle > 0 && B.resid <= B.gate) {
+        B.active = 0;
+        B.accepts += 1;
+        B.warm_cyc_sum += gate_cycle;
     }
 }
 
@@ -1131,12 +1172,14 @@ __global__ void k_targets(DevPtrs p, int Mtot, float *out)
 // the first-order term w_i xi_i . (tau - 1) rho h / cs^2).  Only cells
 // marked this step can carry a force; their marks are cleared here.
 template <class CD>
-__global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p, int did)
+__global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p, int did, int resid_slot)
 {
     const int c = blockIdx.y;
     const CaseDev cd = p.cases[c];
     const BodyView B = body_view(p.body[c]);
     if (cd.M == 0 || B.err != 0) return;
+    // the forcing sequence's residual (its tile maxima are complete here)
+    if (resid_slot >= 0 && blockIdx.x == 0) case_resid_total(p, cd, p.body[c], resid_slot);
     const int L = cd.L, L3 = L * L * L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= L3) return;
@@ -1215,12 +1258,13 @@ __global__ void k_correct(typename CD::T *__restrict__ cur, DevPtrs p, int did)
 // with lambda = 1, or 1 / tau in the momentum-exact variant (the first-order
 // term then carries rho h).  The box's origin is recorded in ring-slot
 // coordinates, which a window shift leaves in place.  Marks are cleared.
-__global__ void k_correct_mom(DevPtrs p)
+__global__ void k_correct_mom(DevPtrs p, int resid_slot)
 {
     const int c = blockIdx.y;
     const CaseDev cd = p.cases[c];
     const BodyView B = body_view(p.body[c]);
     if (cd.M == 0 || B.err != 0) return;
+    if (resid_slot >= 0 && blockIdx.x == 0) case_resid_total(p, cd, p.body[c], resid_slot);
     const int L = cd.L, L3 = L * L * L;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q == 0) {
@@ -1338,32 +1382,37 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     // plain start with at most kHBufs cycles: each cycle's spread rides on
     // the pass before it (force + spread 1, update c + spread c + 1)
     static_assert(kHBufs == 4, "the launch below instantiates 1..4 accumulators");
-    const int fused = warm_mode == 0 && cycles <= kHBufs;
+    const int fused = ibm_fused(warm_mode, cycles);
     hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p, n_mtiles, fused);
     if (force_surface) hipLaunchKernelGGL(k_offset_force, tile_grid, blk, 0, s, p, n_mtiles);
-    hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), dim3(1024), 0, s, p);
+    // the fused sequence forms the force totals in its first update pass
+    if (!fused) hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), blk, 0, s, p);
     // one sequence of multi-direct forcing cycles (Sec. 2.2, l = 1..4): spread
     // the increment, then interpolate and form the next increment; the
     // residual after the last spread is the sequence's residual
     auto sequence = [&](int ncyc, int slot0, int masked) {
         for (int cyc = 1; cyc <= ncyc; cyc++) {
             hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, masked);
-            hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, masked, -1);
+            hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, masked, -1, 0);
             if (diag || cyc == ncyc)
-                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, slot0 + cyc - 1, masked, 0);
+                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p, slot0 + cyc - 1, masked, 0);
         }
     };
     if (fused) {
         for (int cyc = 1; cyc <= cycles; cyc++) {
             const int to = cyc < cycles ? cyc : -1;
+            // the first pass forms the force totals; the last pass's residual
+            // is reduced by the forced correction (or, with diag, every
+            // cycle's by its own kernel)
+            const int ft = cyc == 1;
             switch (cyc) {
-            case 1: hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, 0, to); break;
-            case 2: hipLaunchKernelGGL(k_interp_update_tiles<2>, tile_grid, blk, 0, s, p, n_mtiles, 0, to); break;
-            case 3: hipLaunchKernelGGL(k_interp_update_tiles<3>, tile_grid, blk, 0, s, p, n_mtiles, 0, to); break;
-            default: hipLaunchKernelGGL(k_interp_update_tiles<4>, tile_grid, blk, 0, s, p, n_mtiles, 0, to); break;
+            case 1: hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, 0, to, ft); break;
+            case 2: hipLaunchKernelGGL(k_interp_update_tiles<2>, tile_grid, blk, 0, s, p, n_mtiles, 0, to, ft); break;
+            case 3: hipLaunchKernelGGL(k_interp_update_tiles<3>, tile_grid, blk, 0, s, p, n_mtiles, 0, to, ft); break;
+            default: hipLaunchKernelGGL(k_interp_update_tiles<4>, tile_grid, blk, 0, s, p, n_mtiles, 0, to, ft); break;
             }
-            if (diag || cyc == cycles)
-                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, cyc - 1, 0, 0);
+            if (diag)
+                hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p, cyc - 1, 0, 0);
         }
         (void)cur;
         return hipGetLastError();
@@ -1381,8 +1430,8 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
         hipLaunchKernelGGL(k_gate_begin, case_grid, case_blk, 0, s, p, n_cases);
         for (int cyc = 1; cyc <= warm_cycles; cyc++) {
             hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, 1);
-            hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, 1, -1);
-            hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), dim3(1024), 0, s, p, cyc - 1, 1, cyc);
+            hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, 1, -1, 0);
+            hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p, cyc - 1, 1, cyc);
         }
         hipLaunchKernelGGL(k_gate, case_grid, case_blk, 0, s, p, n_cases);
         hipLaunchKernelGGL(k_fallback_markers, mark_grid, blk, 0, s, p, Mtot);
@@ -1396,24 +1445,25 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
 }
 
 template <class CD>
-static hipError_t correct_impl(void *cur, const DevPtrs &p, int n_cases, int maxL3, int cur_id, hipStream_t s)
+static hipError_t correct_impl(void *cur, const DevPtrs &p, int n_cases, int maxL3, int cur_id, int resid_slot,
+                               hipStream_t s)
 {
     const dim3 reg_grid((maxL3 + 255) / 256, n_cases);
-    hipLaunchKernelGGL(k_correct<CD>, reg_grid, dim3(256), 0, s, (typename CD::T *)cur, p, cur_id);
+    hipLaunchKernelGGL(k_correct<CD>, reg_grid, dim3(256), 0, s, (typename CD::T *)cur, p, cur_id, resid_slot);
     return hipGetLastError();
 }
 
 hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases, int Mtot, int maxL3, int cur_id,
-                          hipStream_t s)
+                          int resid_slot, hipStream_t s)
 {
     if (Mtot == 0) return hipSuccess;
     switch (storage) {
     case ST_MOM:
-        hipLaunchKernelGGL(k_correct_mom, dim3((maxL3 + 255) / 256, n_cases), dim3(256), 0, s, p);
+        hipLaunchKernelGGL(k_correct_mom, dim3((maxL3 + 255) / 256, n_cases), dim3(256), 0, s, p, resid_slot);
         return hipGetLastError();
-    case ST_F16: return correct_impl<CodecF16>(cur, p, n_cases, maxL3, cur_id, s);
-    case ST_BF16: return correct_impl<CodecBF16>(cur, p, n_cases, maxL3, cur_id, s);
-    default: return correct_impl<CodecF32>(cur, p, n_cases, maxL3, cur_id, s);
+    case ST_F16: return correct_impl<CodecF16>(cur, p, n_cases, maxL3, cur_id, resid_slot, s);
+    case ST_BF16: return correct_impl<CodecBF16>(cur, p, n_cases, maxL3, cur_id, resid_slot, s);
+    default: return correct_impl<CodecF32>(cur, p, n_cases, maxL3, cur_id, resid_slot, s);
     }
 }
 
