@@ -319,6 +319,20 @@ int32_t lbm_get_populations_noalloc(lbm_ctx *ctx, int32_t case_id, double *dev_o
  *   cases of the batch go on; the call then returns LBM_EUNSTABLE. */
 int32_t body_get_state(lbm_ctx *ctx, int32_t case_id, double out[32]);
 
+/* Step log (synchronizing): at the end of every step (in window_shift)
+ * each case appends its state, the 32 values of body_get_state in the same
+ * layout (Sec. 2.2 force and torque, Sec. 2.3 motion, Sec. 2.5 window), to
+ * a device ring of 1024 records.  lbm_log_read copies the records of case
+ * case_id not read before, oldest first, at most max_records of them, into
+ * host_out (max_records x 32 doubles), and sets *n_read to their number.
+ * Records overwritten before they were read are skipped; their number goes
+ * to *n_lost (which may be NULL).  Records left over stay for the next call.
+ * After lbm_load only records of later steps are readable.  Errors:
+ * LBM_EINVAL (bad case, negative count, NULL n_read, NULL host_out with
+ * max_records > 0), LBM_EHIP. */
+int32_t lbm_log_read(lbm_ctx *ctx, int32_t case_id, double *host_out, int32_t max_records, int32_t *n_read,
+                     int64_t *n_lost);
+
 /* Checkpoint: populations (storage format), body states, ring origins and
  * step counters; lbm_load needs a context created with the same cases. */
 int32_t lbm_save(lbm_ctx *ctx, const char *path);

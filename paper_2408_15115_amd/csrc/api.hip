@@ -38,7 +38,7 @@ struct Plan {
     int planes = 27;          // stored planes per case: q, or 10 with moment storage
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
-        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox,
+        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox, off_log,
         off_mark, off_wt, off_dsh, off_rpop, off_fine0, off_fine1, aux_bytes;
     long long xreg_cells = 0;   // moment storage: cells of all expanded regions (edge L + 2)
     long long fine_elems = 0;   // FP16/BF16 storage: floats of all full-precision boxes (per buffer)
@@ -328,6 +328,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_fine1 = take(sizeof(float) * std::max<long long>(P.fine_elems, 1));
     P.off_mtiles = take(sizeof(MarkerTile) * NT);
     P.off_tbox = take(sizeof(TileBox) * 2 * NT);   // the markers' and the force-surface points' boxes
+    P.off_log = take(sizeof(double) * kLogFields * kLogCap * P.cd.size());
     P.aux_bytes = o;
     (void)eb;
     return "";
@@ -360,6 +361,7 @@ struct lbm_ctx {
     // everything after it wait for `join` on `stream`.
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    std::vector<uint32_t> log_read;   // per case: step-log records read so far (the device counts modulo 2^32)
     std::string err;
     ~lbm_ctx()
     {
@@ -525,6 +527,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     if (buf_bytes[0] < P.pop_elems * eb || buf_bytes[1] < P.pop_elems * eb || buf_bytes[2] < (int64_t)P.aux_bytes)
         return bail(LBM_ENOMEM, "a buffer is smaller than lbm_required_bytes");
     ctx->n = n_cases;
+    ctx->log_read.assign(n_cases, 0u);
     ctx->cases.assign(cases, cases + n_cases);
     ctx->stream = (hipStream_t)hip_stream;
     ctx->pop[0] = buf->pop_a;
@@ -561,6 +564,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.hs = (double *)(a + P.off_hs);
     p.dSo = (double *)(a + P.off_dSo);
     p.tbox = (TileBox *)(a + P.off_tbox);
+    p.log = (double *)(a + P.off_log);
     p.fine[0] = (float *)(a + P.off_fine0);
     p.fine[1] = (float *)(a + P.off_fine1);
 
@@ -1142,6 +1146,42 @@ int32_t lbm_load(lbm_ctx *ctx, const char *path)
         HIPCHK(ctx, hipMemcpyAsync(extra_dst, pop.data() + popb, extra, hipMemcpyHostToDevice, ctx->stream), "load");
     HIPCHK(ctx, hipMemcpyAsync(ctx->p.body, bd.data(), sizeof(BodyDev) * ctx->n, hipMemcpyHostToDevice, ctx->stream), "load");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    for (int c = 0; c < ctx->n; c++) ctx->log_read[c] = bd[c].logged;   // the ring holds none of the loaded steps
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------- step log
+int32_t lbm_log_read(lbm_ctx *ctx, int32_t c, double *out, int32_t max_records, int32_t *n_read, int64_t *n_lost)
+{
+    if (!ctx || c < 0 || c >= ctx->n || max_records < 0 || !n_read || (max_records > 0 && !out))
+        return fail(ctx, LBM_EINVAL, "lbm_log_read: bad case, negative count or NULL output");
+    *n_read = 0;
+    if (n_lost) *n_lost = 0;
+    BodyDev B;
+    int32_t r = read_body(ctx, c, B);   // synchronizes: every launched step has written its record
+    if (r) return r;
+    uint32_t &cur = ctx->log_read[c];
+    uint32_t avail = B.logged - cur;
+    if (avail > (uint32_t)kLogCap) {
+        if (n_lost) *n_lost = avail - (uint32_t)kLogCap;
+        cur = B.logged - (uint32_t)kLogCap;
+        avail = kLogCap;
+    }
+    const int n = (int)std::min<uint32_t>(avail, (uint32_t)max_records);
+    if (n == 0) return LBM_OK;
+    const double *ring = ctx->p.log + (size_t)c * kLogCap * kLogFields;
+    const int slot = (int)(cur % (uint32_t)kLogCap);
+    const int first = std::min(n, kLogCap - slot);
+    const size_t rb = sizeof(double) * kLogFields;
+    HIPCHK(ctx, hipMemcpyAsync(out, ring + (size_t)slot * kLogFields, rb * first, hipMemcpyDeviceToHost, ctx->stream),
+           "read the step log");
+    if (n > first)
+        HIPCHK(ctx, hipMemcpyAsync(out + (size_t)first * kLogFields, ring, rb * (n - first), hipMemcpyDeviceToHost,
+                                   ctx->stream),
+               "read the step log");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    cur += (uint32_t)n;
+    *n_read = n;
     return LBM_OK;
 }
 

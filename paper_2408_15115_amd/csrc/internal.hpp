@@ -49,7 +49,8 @@ struct BodyDev {
     int org[3];      // IBM region origin (physical cell coordinates, x/y unwrapped)
     int fo[2][3];    // full-precision box origin of population buffer 0 / 1 (physical, x/y unwrapped)
     int fvalid[2];   // 1 once a step has written that buffer's box
-    unsigned int tiles_done[2];   // marker tiles of the case done in the current force / residual pass
+    unsigned int logged;          // records written to the case's step log so far
+    unsigned int pad_;
     int err;         // 1: a marker stencil left the box in z; 2: non-finite or huge IBM value;
                      // 4: non-finite density or |u| > 0.5.  Nonzero masks (freezes) the case.
 };
@@ -123,7 +124,14 @@ struct DevPtrs {
     float *rpop;     // moment storage: collided populations of the region and a one-cell rim, [27][xstride]
     long long xstride;
     float *fine[2];  // FP16/BF16 storage: the full-precision boxes of population buffers 0 and 1
+    double *log;     // per case a ring of kLogCap step records of kLogFields values
 };
+
+// Step log: at the end of every step each case appends one record, in the
+// layout of the body-state read (r, d, v, w, F, T, F_pressure, residual,
+// steps, shifts, z0, err), to a ring of kLogCap records.
+constexpr int kLogCap = 1024;
+constexpr int kLogFields = 32;
 
 // ---------------------------------------------------------------- launchers
 // collision: 0 = recursive regularized, 1 = BGK (comparison; plain schedule)

@@ -1310,13 +1310,33 @@ __global__ void k_window_trigger(DevPtrs p, int n_cases)
     const CaseDev &cd = p.cases[c];
     BodyDev &B = p.body[c];
     B.shift_now = 0;
-    if (cd.M == 0 || B.err != 0 || cd.dz <= 0 || !(cd.h_end > 0.0) || !(B.r[2] < cd.h_end)) return;
-    B.r[2] += (double)cd.dz;
-    B.z0 = wrapi(B.z0 - cd.dz, cd.nz);
-    B.fo[0][2] += cd.dz;   // the full-precision boxes move with the content
-    B.fo[1][2] += cd.dz;
-    B.shift_now = 1;
-    B.shifts += 1;
+    if (cd.M > 0 && B.err == 0 && cd.dz > 0 && cd.h_end > 0.0 && B.r[2] < cd.h_end) {
+        B.r[2] += (double)cd.dz;
+        B.z0 = wrapi(B.z0 - cd.dz, cd.nz);
+        B.fo[0][2] += cd.dz;   // the full-precision boxes move with the content
+        B.fo[1][2] += cd.dz;
+        B.shift_now = 1;
+        B.shifts += 1;
+    }
+    // the step's record in the case's log ring
+    double *rec = p.log + ((long long)c * kLogCap + B.logged % kLogCap) * kLogFields;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        rec[a] = B.r[a];
+        rec[12 + a] = B.v[a];
+        rec[15 + a] = B.w[a];
+        rec[18 + a] = B.F[a];
+        rec[21 + a] = B.T[a];
+        rec[24 + a] = B.Fp[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 9; a++) rec[3 + a] = B.d[a];
+    rec[27] = B.resid;
+    rec[28] = B.steps;
+    rec[29] = B.shifts;
+    rec[30] = B.z0;
+    rec[31] = B.err;
+    B.logged += 1;
 }
 
 template <class CD>

@@ -73,6 +73,7 @@ _sig = {
     "lbm_set_populations": (C.c_int32, [_ctx, C.c_int32, _P(C.c_double)]),
     "lbm_get_populations_noalloc": (C.c_int32, [_ctx, C.c_int32, C.c_void_p]),
     "body_get_state": (C.c_int32, [_ctx, C.c_int32, _P(C.c_double)]),
+    "lbm_log_read": (C.c_int32, [_ctx, C.c_int32, _P(C.c_double), C.c_int32, _P(C.c_int32), _P(C.c_int64)]),
     "lbm_save": (C.c_int32, [_ctx, C.c_char_p]),
     "lbm_load": (C.c_int32, [_ctx, C.c_char_p]),
     "lbm_pop_offset": (C.c_int64, [_ctx, C.c_int32]),
@@ -283,6 +284,18 @@ class Solver:
                 "w": o[15:18].copy(), "F": o[18:21].copy(), "T": o[21:24].copy(),
                 "F_pressure": o[24:27].copy(), "ibm_residual": o[27], "steps": int(o[28]),
                 "shifts": int(o[29]), "z0": int(o[30]), "err": int(o[31])}
+
+    LOG_CAPACITY = 1024
+
+    def log_read(self, case=0, max_records=LOG_CAPACITY):
+        """Step records of the case not read before, oldest first, as an
+        (n, 32) array in the layout of body_get_state, and the number of
+        records overwritten before they were read."""
+        out = np.zeros((max(int(max_records), 1), 32))
+        n, lost = C.c_int32(0), C.c_int64(0)
+        self._chk("lbm_log_read", lbm_log_read(self._ctx, int(case), _dptr(out), int(max_records), C.byref(n),
+                                               C.byref(lost)))
+        return out[:n.value].copy(), int(lost.value)
 
     # --- learned warm start
     def set_warm_start(self, mode, mlp=None, cycles=4):
