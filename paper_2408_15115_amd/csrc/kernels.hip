@@ -585,7 +585,7 @@ __device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyView &B
         ft[a] = (float)(h0[a] / sc);
         ft[3 + a] = (float)(p.U[3 * k + a] * kFeatScale);
         ft[6 + a] = (float)nk[a];
-        ft[9 + a] = (float)(hp[a] / sc);
+        ft[kFeatHPrev + a] = (float)(hp[a] / sc);
         // h_k holds what has been spread so far; dh is the next increment
         p.h0[3 * k + a] = h0[a];
         p.hk[3 * k + a] = spread ? 0.0 + h0[a] : 0.0;
@@ -700,6 +700,44 @@ __device__ inline void spread_flush(const TileBox &tb, int ncell, int L, int L3,
 // Entry f of marker k's record: X (0..2), U (3..5), dS (6), the stencil
 // weights (7..18), h_k (19..21).  The force kernel keeps entries 0..18.
 constexpr int kRecW = 7, kRecH = 19, kRecForce = 19, kRecUpdate = 22;
+
+// The tile kernels of the coupling run beside the lattice kernel, whose waves
+// each hold 64 VGPRs and 96 SGPRs and fill every wave slot of a SIMD.  A
+// coupling wave starts only in a slot a lattice wave frees, so the force and
+// update passes come in two register budgets, MINW = 8 waves per SIMD (the
+// lattice kernel's own budget) and MINW = 1 (registers as the LDS-bound
+// occupancy allows).
+// FP32 storage takes the first: measured at the 256 x 256 x 768 case, its
+// coupling then runs during the lattice kernel instead of after it, 50 us
+// less per step.  With FP16 storage the coupling already runs beside the
+// lattice kernel and the tighter budget only slows that kernel, so the
+// reduced-precision and moment stores take the second.  The LDS of these
+// kernels is taken at launch (dynamic), so that the compiler's occupancy
+// target is set by the register budget and not by the LDS size; the layouts
+// are carved below, 8-byte arrays first.
+
+struct LdsCarve {
+    unsigned char *at;
+    template <class A>
+    __device__ A &take()
+    {
+        A &r = *reinterpret_cast<A *>(at);
+        at += sizeof(A);
+        return r;
+    }
+};
+
+constexpr size_t kLdsForce = sizeof(unsigned long long[3][kBoxCells]) + sizeof(double[kTileMarkers][kRegFields]) +
+                             sizeof(double[kTileMarkers][kRecForce]) + sizeof(double[kTileMarkers][3]) +
+                             sizeof(float[kRegFields][kBoxCells]);
+constexpr size_t kLdsUpdate = sizeof(double[3][kBoxCells]) + sizeof(unsigned long long[3][kBoxCells]) +
+                              sizeof(double[kTileMarkers][kRecUpdate]) + sizeof(double[kTileMarkers][3]) +
+                              sizeof(double[kTileMarkers]);
+static_assert(kLdsForce <= 65536 && kLdsUpdate <= 65536, "tile kernel LDS");
+// Waves per SIMD that the LDS of a 256-thread workgroup allows (160 KB per
+// CU): the occupancy the unconstrained budget is compiled for, as with static
+// LDS.
+constexpr int lds_waves(size_t bytes) { return (int)std::min<size_t>(8, (160 * 1024) / bytes); }
 __device__ inline double marker_record(const DevPtrs &p, int k, int f)
 {
     if (f < 3) return p.X[3 * k + f];
@@ -761,13 +799,17 @@ __device__ inline void spread_tile(const DevPtrs &p, const MarkerTile &mt, const
 // l = 0 and the stress integral over a tile (a row of 16 lanes per marker).
 // With spread set, also the first forcing cycle's spread of the plain start
 // h0 into accumulator 0 (h_k = h0).
-__global__ void __launch_bounds__(256) k_interp_force_tiles(DevPtrs p, int n_mtiles, int spread)
+template <int MINW>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW, MINW == 8 ? 8 : lds_waves(kLdsForce))))
+k_interp_force_tiles(DevPtrs p, int n_mtiles, int spread)
 {
-    __shared__ float box[kRegFields][kBoxCells];
-    __shared__ unsigned long long acc[3][kBoxCells];
-    __shared__ double ep[kTileMarkers][kRegFields];   // interpolated fields, then the marker's parts
-    __shared__ double mrec[kTileMarkers][kRecForce];  // the tile's marker records
-    __shared__ double dinc[kTileMarkers][3];          // the markers' increments (h0) to spread
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    LdsCarve lc{lds_dyn};
+    auto &acc = lc.take<unsigned long long[3][kBoxCells]>();
+    auto &ep = lc.take<double[kTileMarkers][kRegFields]>();    // interpolated fields, then the marker's parts
+    auto &mrec = lc.take<double[kTileMarkers][kRecForce]>();   // the tile's marker records
+    auto &dinc = lc.take<double[kTileMarkers][3]>();           // the markers' increments (h0) to spread
+    auto &box = lc.take<float[kRegFields][kBoxCells]>();
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
@@ -966,15 +1008,17 @@ __global__ void __launch_bounds__(256) k_spread_tiles(DevPtrs p, int n_mtiles, i
 // With spread_to >= 0 the same pass spreads dh (the next cycle's spread,
 // h_k += dh) into accumulator spread_to, which no interpolation of this
 // pass reads.
-template <int NB>
-__global__ void __launch_bounds__(256) k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked, int spread_to,
-                                                             int ft_total)
+template <int NB, int MINW>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW, MINW == 8 ? 8 : lds_waves(kLdsUpdate))))
+k_interp_update_tiles(DevPtrs p, int n_mtiles, int masked, int spread_to, int ft_total)
 {
-    __shared__ double box[3][kBoxCells];
-    __shared__ unsigned long long acc[3][kBoxCells];
-    __shared__ double mrec[kTileMarkers][kRecUpdate];   // the tile's marker records
-    __shared__ double dinc[kTileMarkers][3];            // the markers' increments e to spread
-    __shared__ double rmax[kTileMarkers];
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    LdsCarve lc{lds_dyn};
+    auto &box = lc.take<double[3][kBoxCells]>();
+    auto &acc = lc.take<unsigned long long[3][kBoxCells]>();
+    auto &mrec = lc.take<double[kTileMarkers][kRecUpdate]>();   // the tile's marker records
+    auto &dinc = lc.take<double[kTileMarkers][3]>();            // the markers' increments e to spread
+    auto &rmax = lc.take<double[kTileMarkers]>();
     const int tix = tile_of_block((int)blockIdx.x, n_mtiles);
     if (tix >= n_mtiles) return;
     const MarkerTile mt = p.mtiles[tix];
@@ -1116,7 +1160,7 @@ __global__ void k_warm_previous(DevPtrs p, int Mtot)
     if (k >= Mtot || p.body[p.mcase[k]].err != 0) return;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const double h = (double)p.feat[(long long)kMlpIn * k + 9 + a] * p.hs[k];
+        const double h = (double)p.feat[(long long)kMlpIn * k + kFeatHPrev + a] * p.hs[k];
         p.hk[3 * k + a] = 0.0;
         p.dh[3 * k + a] = h;
     }
@@ -1163,7 +1207,7 @@ __global__ void k_targets(DevPtrs p, int Mtot, float *out)
     if (k >= Mtot) return;
     const float *ft = p.feat + (long long)kMlpIn * k;
 #pragma unroll
-    for (int a = 0; a < 3; a++) out[3 * k + a] = (float)(p.hk[3 * k + a] / p.hs[k] - (double)ft[9 + a]);
+    for (int a = 0; a < 3; a++) out[3 * k + a] = (float)(p.hk[3 * k + a] / p.hs[k] - (double)ft[kFeatHPrev + a]);
 }
 
 // Forced collision of Sec. 2.2: the lattice kernel wrote
@@ -1402,8 +1446,9 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     // plain start with at most kHBufs cycles: each cycle's spread rides on
     // the pass before it (force + spread 1, update c + spread c + 1)
     static_assert(kHBufs == 4, "the launch below instantiates 1..4 accumulators");
+    constexpr int W = std::is_same<CD, CodecF32>::value ? 8 : 1;   // register budget of the tile passes
     const int fused = ibm_fused(warm_mode, cycles);
-    hipLaunchKernelGGL(k_interp_force_tiles, tile_grid, blk, 0, s, p, n_mtiles, fused);
+    hipLaunchKernelGGL(k_interp_force_tiles<W>, tile_grid, blk, kLdsForce, s, p, n_mtiles, fused);
     if (force_surface) hipLaunchKernelGGL(k_offset_force, tile_grid, blk, 0, s, p, n_mtiles);
     // the fused sequence forms the force totals in its first update pass
     if (!fused) hipLaunchKernelGGL(k_reduce_ft, dim3(n_cases), blk, 0, s, p);
@@ -1413,7 +1458,7 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     auto sequence = [&](int ncyc, int slot0, int masked) {
         for (int cyc = 1; cyc <= ncyc; cyc++) {
             hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, masked);
-            hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, masked, -1, 0);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_interp_update_tiles<1, W>), tile_grid, blk, kLdsUpdate, s, p, n_mtiles, masked, -1, 0);
             if (diag || cyc == ncyc)
                 hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p, slot0 + cyc - 1, masked, 0);
         }
@@ -1426,10 +1471,10 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
             // cycle's by its own kernel)
             const int ft = cyc == 1;
             switch (cyc) {
-            case 1: hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, 0, to, ft); break;
-            case 2: hipLaunchKernelGGL(k_interp_update_tiles<2>, tile_grid, blk, 0, s, p, n_mtiles, 0, to, ft); break;
-            case 3: hipLaunchKernelGGL(k_interp_update_tiles<3>, tile_grid, blk, 0, s, p, n_mtiles, 0, to, ft); break;
-            default: hipLaunchKernelGGL(k_interp_update_tiles<4>, tile_grid, blk, 0, s, p, n_mtiles, 0, to, ft); break;
+            case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_interp_update_tiles<1, W>), tile_grid, blk, kLdsUpdate, s, p, n_mtiles, 0, to, ft); break;
+            case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_interp_update_tiles<2, W>), tile_grid, blk, kLdsUpdate, s, p, n_mtiles, 0, to, ft); break;
+            case 3: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_interp_update_tiles<3, W>), tile_grid, blk, kLdsUpdate, s, p, n_mtiles, 0, to, ft); break;
+            default: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_interp_update_tiles<4, W>), tile_grid, blk, kLdsUpdate, s, p, n_mtiles, 0, to, ft); break;
             }
             if (diag)
                 hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p, cyc - 1, 0, 0);
@@ -1450,7 +1495,7 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
         hipLaunchKernelGGL(k_gate_begin, case_grid, case_blk, 0, s, p, n_cases);
         for (int cyc = 1; cyc <= warm_cycles; cyc++) {
             hipLaunchKernelGGL(k_spread_tiles, tile_grid, blk, 0, s, p, n_mtiles, 1);
-            hipLaunchKernelGGL(k_interp_update_tiles<1>, tile_grid, blk, 0, s, p, n_mtiles, 1, -1, 0);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_interp_update_tiles<1, W>), tile_grid, blk, kLdsUpdate, s, p, n_mtiles, 1, -1, 0);
             hipLaunchKernelGGL(k_reduce_resid, dim3(n_cases), blk, 0, s, p, cyc - 1, 1, cyc);
         }
         hipLaunchKernelGGL(k_gate, case_grid, case_blk, 0, s, p, n_cases);

@@ -19,6 +19,9 @@ constexpr int kMlpSlice = 256;                 // samples per weight-gradient pa
 // terminal velocity of the cases, so it is O(1); the force-like features
 // and the output are taken over a per-marker scale instead.
 constexpr double kFeatScale = 50.0;
+// Features kFeatHPrev .. kFeatHPrev + 2 are the previous step's final h over
+// the marker's scale; a zero network output starts from them.
+constexpr int kFeatHPrev = 9;
 
 // Per-sample training scratch, [field][sample] layout (n samples).
 struct MlpScratch {

@@ -309,11 +309,20 @@ class Solver:
         return int(lbm_marker_count(self._ctx))
 
     def ibm_samples(self):
-        """(features, targets) of the last ibm_couple as new device tensors."""
+        """(features, targets) of the last ibm_couple as new device tensors.
+        The library writes them on the context's stream; the caller's current
+        stream is made to wait for that before they are returned."""
+        torch = self.torch
         M = self.marker_count()
-        f = self.torch.empty((M, 12), dtype=self.torch.float32, device="cuda")
-        t = self.torch.empty((M, 3), dtype=self.torch.float32, device="cuda")
-        self._chk("lbm_ibm_samples", lbm_ibm_samples(self._ctx, C.c_void_p(f.data_ptr()), C.c_void_p(t.data_ptr())))
+        cur = torch.cuda.current_stream()
+        with torch.cuda.stream(self.stream):
+            f = torch.empty((M, 12), dtype=torch.float32, device="cuda")
+            t = torch.empty((M, 3), dtype=torch.float32, device="cuda")
+            self._chk("lbm_ibm_samples", lbm_ibm_samples(self._ctx, C.c_void_p(f.data_ptr()),
+                                                         C.c_void_p(t.data_ptr())))
+        cur.wait_stream(self.stream)
+        f.record_stream(cur)
+        t.record_stream(cur)
         return f, t
 
     def ibm_stats(self, case=0):

@@ -140,6 +140,23 @@ def evaluate(T, cases, bodies, mode, net=None, cycles=1, gate=1e30, steps=80, sk
             "cycles_accepted": sum(x["warm_cycles_accepted"] for x in stats)}
 
 
+def test_samples_from_a_side_stream_are_ready_on_the_current_stream(T):
+    """The solver runs on its own stream; the samples it returns are read on
+    the caller's current stream right away (no explicit synchronization) and
+    must hold every marker's features: the unit normals (features 6..8)."""
+    import torch
+    cases, bodies = learned_batch(5)
+    S = T.Solver(cases, bodies, stream=torch.cuda.Stream())
+    S.run(20)                      # queued on the solver's stream
+    f, t = S.ibm_samples()
+    fa, ta = f.cpu().numpy(), t.cpu().numpy()
+    torch.cuda.synchronize()
+    fb, tb = f.cpu().numpy(), t.cpu().numpy()
+    S.close()
+    assert np.array_equal(fa, fb) and np.array_equal(ta, tb)
+    assert np.allclose(np.linalg.norm(fa[:, 6:9], axis=1), 1.0, atol=1e-6)
+
+
 def test_gate_extremes(T):
     """Gate 0 rejects every learned start and reproduces the plain run
     bitwise; an infinite gate accepts every start after its first cycle."""
