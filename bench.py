@@ -226,6 +226,7 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
 
     # training data: plain run of the training batch
     S = solver(seed_train, 0)
+    M_all = S.marker_count()
     tr = run(S, train_steps, collect=True)
     close(S)
     X, Y = np.concatenate(tr["X"]), np.concatenate(tr["Y"])
@@ -237,9 +238,10 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
     S = solver(seed_eval, 0)
     plain = run(S, eval_steps, hist=True)
     close(S)
+    starts = (("mlp", T.LBM_WARM_MLP, net), ("previous_h", T.LBM_WARM_PREVIOUS, None))
     # residuals after k cycles on the plain trajectory
     diag = {}
-    for name, mode, m in (("mlp", T.LBM_WARM_MLP, net), ("previous_h", T.LBM_WARM_PREVIOUS, None)):
+    for name, mode, m in starts:
         S = solver(seed_eval, 1)
         S.set_warm_start(mode, m, 4)
         for c in range(nc):
@@ -252,7 +254,7 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
     r4 = plain["H"][:, :, 3]
     gates = np.where(ok0, r4.max(0), 0.0)
     gated = {}
-    for name, mode, m in (("mlp", T.LBM_WARM_MLP, net), ("previous_h", T.LBM_WARM_PREVIOUS, None)):
+    for name, mode, m in starts:
         S = solver(seed_eval, 0)
         S.set_warm_start(mode, m, max_cycles)
         for c in range(nc):
@@ -273,7 +275,22 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
                 S.set_ibm_gate(c, float(gates[c]))
         overlapped[name] = round(step_ms(S), 4)
         close(S)
-    ok = ok0 & (gated["mlp"]["errs"] == 0) & (gated["previous_h"]["errs"] == 0) & (plain3["errs"] == 0)
+    ok = ok0 & (plain3["errs"] == 0)
+    for r_ in gated.values():
+        ok &= r_["errs"] == 0
+    # the network's forward on every marker of the batch (the warm start's
+    # kernel shape), timed alone
+    feats = torch.tensor(X[:M_all], device="cuda") if X.shape[0] >= M_all else None
+    fwd_us = None
+    if feats is not None:
+        net.forward(feats)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(net.stream)
+        for _ in range(20):
+            net.forward(feats)
+        e1.record(net.stream)
+        torch.cuda.synchronize()
+        fwd_us = e0.elapsed_time(e1) / 20 * 1e3
     live = np.where(ok)[0]
 
     eb = W.batch_cases(nc, seed0=seed_eval)
@@ -302,6 +319,7 @@ def learned_run(T, W, torch, storage, train_steps=300, eval_steps=100, skip=10, 
             "resid_after_k_cycles_median": {"plain": [med(Hm, 8 + k) for k in range(4)],
                                             "previous_h": [med(Hp, k) for k in range(4)],
                                             "mlp": [med(Hm, k) for k in range(4)]},
+            "mlp_forward_us_all_markers": round(fwd_us, 2) if fwd_us else None, "markers": int(M_all),
             "gate": "largest plain four-cycle residual of the case in the plain run",
             "max_learned_cycles": max_cycles,
             "ibm_ms_per_step_plain_4cycles": round(plain["ms"], 4),

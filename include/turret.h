@@ -338,35 +338,44 @@ int32_t lbm_log_read(lbm_ctx *ctx, int32_t case_id, double *host_out, int32_t ma
 int32_t lbm_save(lbm_ctx *ctx, const char *path);
 int32_t lbm_load(lbm_ctx *ctx, const char *path);
 
-/* Element offset of a case's population block inside pop_a / pop_b, and the
- * device pointer of the current buffer (for tests that read raw storage). */
+/* Element offset of a case's population block inside pop_a / pop_b, the
+ * element stride between its direction planes (its cell count rounded up to
+ * 128, plus 256), and the device pointer of the current buffer (for tests
+ * that read raw storage).  -1 / NULL for a bad case or context. */
 int64_t lbm_pop_offset(const lbm_ctx *ctx, int32_t case_id);
+int64_t lbm_plane_stride(const lbm_ctx *ctx, int32_t case_id);
 void *lbm_current_buffer(const lbm_ctx *ctx);
 
 /* ------------------------------------------------------------------------
  * Learned warm start of the multi-direct forcing.
  *
- * A network (12 -> 64 -> 64 -> 3, SiLU hidden layers, FP16 weights, FP32
- * accumulation) maps each marker's features -- the plain l = 0 start
- * h0_k = U_k - I[u*](X_k) of Sec. 2.2 and the previous step's final force
- * h_k(t-1), both divided by the marker scale s_k = |h0_k| + |h_k(t-1)|, the
- * marker velocity U_k times 50 (1 / the largest lattice terminal velocity
- * 0.02) and the normal n_k -- to the change of h from h_k(t-1), over s_k;
- * the start is s_k (h_k(t-1) / s_k + output).  (h0 and U are an invertible
- * linear map of I[u*] and U that keeps their small difference out of
+ * A network (16 -> 64 -> 64 -> 3, SiLU hidden layers) maps each marker's
+ * features to a correction of the start of the multi-direct forcing.  The
+ * features (LBM_MLP_IN of them) are the plain l = 0 start
+ * h0_k(t) = U_k - I[u*](X_k) of Sec. 2.2, the previous step's final force
+ * h_k(t-1), its last change h_k(t-1) - h_k(t-2) and the change of the plain
+ * start h0_k(t) - h0_k(t-1), each divided by the marker scale
+ * s_k = |h0_k(t)| + |h_k(t-1)|, then the normal n_k and the area dS_k.  The start is
+ * s_k (h_k(t-1) / s_k + output): the network predicts the change of h from
+ * the previous step's final value (a zero network gives the previous-h
+ * start; h0 and U enter as their difference, which keeps it out of
  * cancellation; the per-marker scale makes the map independent of the
- * case's velocity scale, and a zero network gives the previous-h start.)
+ * case's velocity scale).
  * From that start the solver runs cycles until the case's residual
  * max_k |U_k - I[u* + H](X_k)| is at or below its gate
  * (lbm_set_ibm_gate, default 1e-6), at most `cycles` of them; a case that
  * does not get there reruns the plain ibm_cycles cycles from the plain
  * start.  All decisions are made on the device, so graphs stay valid.  The
  * network is trained on samples of the solver's own plain runs
- * (lbm_ibm_samples) by the library's forward/backward kernels and Adam.
+ * (lbm_ibm_samples) by the library's forward/backward kernels (FP16
+ * weights, FP32 operands and accumulation) and Adam; inference (the warm
+ * start and mlp_forward) runs on the matrix cores with FP16 weights and
+ * operands and FP32 accumulation.
  *
- * Flat FP32 parameter layout (5187 values): W1[64][12] b1[64] W2[64][64]
- * b2[64] W3[3][64] b3[3].
+ * Flat FP32 parameter layout (LBM_MLP_PARAMS = 5443 values): W1[64][16]
+ * b1[64] W2[64][64] b2[64] W3[3][64] b3[3].
  * ---------------------------------------------------------------------- */
+enum { LBM_MLP_IN = 16, LBM_MLP_PARAMS = 5443 };
 typedef struct lbm_mlp lbm_mlp;
 
 /* Device bytes of a network object able to train on batches of up to
@@ -377,15 +386,16 @@ int32_t mlp_required_bytes(int32_t max_batch, int64_t *out_bytes);
  * LBM_EINVAL, LBM_ENOMEM (buffer too small), LBM_EHIP. */
 int32_t mlp_create(void *dev_buf, int64_t bytes, int32_t max_batch, void *hip_stream, lbm_mlp **out);
 
-/* Parameters from / to host FP32 arrays of 5187 values (synchronizing).
+/* Parameters from / to host FP32 arrays of LBM_MLP_PARAMS values (synchronizing).
  * Setting them rounds the FP16 compute copy (nearest even) and resets Adam. */
 int32_t mlp_set_params(lbm_mlp *m, const float *host_params);
 int32_t mlp_get_params(lbm_mlp *m, float *host_params);
 
-/* Device arrays: X (n x 12 FP32) -> Y (n x 3 FP32). */
+/* Inference (matrix cores, FP16 operands): device arrays X (n x LBM_MLP_IN
+ * FP32) -> Y (n x 3 FP32), on the network's stream. */
 int32_t mlp_forward(lbm_mlp *m, const float *dev_x, int32_t n, float *dev_y);
 
-/* Loss L = 1/(2n) sum |Y - T|^2 and its gradient (5187 FP32 values), into
+/* Loss L = 1/(2n) sum |Y - T|^2 and its gradient (LBM_MLP_PARAMS FP32 values), into
  * device arrays (either may be NULL); n <= max_batch.  The gradient is
  * bitwise reproducible (fixed-order sums). */
 int32_t mlp_grad(lbm_mlp *m, const float *dev_x, const float *dev_t, int32_t n, float *dev_grad, float *dev_loss);
@@ -411,8 +421,9 @@ int32_t lbm_set_warm_start(lbm_ctx *ctx, int32_t mode, const lbm_mlp *m, int32_t
 int32_t lbm_set_ibm_gate(lbm_ctx *ctx, int32_t case_id, double threshold);
 
 /* Samples of the last ibm_couple, to caller device arrays: features
- * (markers x 12 FP32) and the training target, the final force h_k minus
- * the previous step's, over the marker scale s_k (markers x 3), markers of
+ * (markers x LBM_MLP_IN FP32) and the training target, the final force
+ * h_k(t) minus the previous step's, over the marker scale s_k (markers x 3),
+ * written on the context's stream, markers of
  * all cases in case order (lbm_marker_count of them; inside a case in the
  * library's own marker order).  Take them from plain runs (no warm start). */
 int32_t lbm_ibm_samples(lbm_ctx *ctx, float *dev_features, float *dev_targets);

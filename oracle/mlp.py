@@ -3,13 +3,13 @@
 TEST INFRASTRUCTURE ONLY (tests and the benchmark's CPU leg); the product
 path never imports it.
 
-A plain multilayer perceptron 12 -> 64 -> 64 -> 3 with SiLU activations
+A plain multilayer perceptron 16 -> 64 -> 64 -> 3 with SiLU activations
 (x * sigmoid(x)) on the two hidden layers and a linear output, its mean
 squared error loss L = 1/(2N) sum_n |y_n - t_n|^2, the gradient of L by
 backpropagation, and the Adam update (Kingma & Ba, 2015, Algorithm 1).
 
 Flat parameter layout (the same order the library uses):
-    W1 (64 x 12, row-major: W[out][in]), b1 (64),
+    W1 (64 x 16, row-major: W[out][in]), b1 (64),
     W2 (64 x 64), b2 (64),
     W3 (3 x 64), b3 (3)
 """
@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import numpy as np
 
-LAYERS = [(12, 64), (64, 64), (64, 3)]
+LAYERS = [(16, 64), (64, 64), (64, 3)]
 N_PARAMS = sum(i * o + o for i, o in LAYERS)
 
 
@@ -51,7 +51,7 @@ def dsilu(x):
 
 
 def forward(theta, X):
-    """X (N, 12) -> Y (N, 3) and the cache of pre-activations/activations."""
+    """X (N, 16) -> Y (N, 3) and the cache of pre-activations/activations."""
     (W1, b1), (W2, b2), (W3, b3) = unpack(theta)
     X = np.asarray(X, np.float64)
     z1 = X @ W1.T + b1
@@ -60,6 +60,23 @@ def forward(theta, X):
     a2 = silu(z2)
     Y = a2 @ W3.T + b3
     return Y, (X, z1, a1, z2, a2)
+
+
+def forward_half_operands(theta, X):
+    """The forward pass with the operands of every layer -- the input and the
+    two hidden activations -- rounded to IEEE binary16 (to nearest, ties to
+    even), everything else in FP64: the arithmetic of an inference with FP16
+    weights and operands on matrix units that accumulate in a wider format,
+    up to that accumulation's own rounding."""
+    (W1, b1), (W2, b2), (W3, b3) = unpack(theta)
+
+    def h(a):
+        return np.asarray(a, np.float64).astype(np.float16).astype(np.float64)
+
+    x = h(X)
+    a1 = h(silu(x @ W1.T + b1))
+    a2 = h(silu(a1 @ W2.T + b2))
+    return a2 @ W3.T + b3
 
 
 def loss(theta, X, T):

@@ -38,7 +38,7 @@ struct Plan {
     int planes = 27;          // stored planes per case: q, or 10 with moment storage
     long long pop_elems = 0, reg_cells = 0;
     size_t off_cases, off_body, off_tiles, off_counter, off_mcase, off_xb, off_nb, off_dS, off_X, off_N, off_U, off_hk,
-        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hs, off_dSo, off_mtiles, off_tbox, off_log,
+        off_dh, off_part, off_res, off_reg, off_H, off_feat, off_h0, off_hk2, off_hs, off_dSo, off_mtiles, off_tbox, off_log,
         off_mark, off_wt, off_dsh, off_rpop, off_fine0, off_fine1, aux_bytes;
     long long xreg_cells = 0;   // moment storage: cells of all expanded regions (edge L + 2)
     long long fine_elems = 0;   // FP16/BF16 storage: floats of all full-precision boxes (per buffer)
@@ -242,7 +242,11 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         d.dz = k.h_end > 0.0 ? (int)std::lround(k.h_ini - k.h_end) : 0;
         if (d.dz < 0) d.dz = 0;
         d.cells = (long long)k.nx * k.ny * k.nz;
-        d.plane = (d.cells + 127) / 128 * 128;   // 256-byte aligned direction planes
+        // 256-byte aligned direction planes, 1 KB apart from a multiple of
+        // 256 bytes: with the planes of a case starting at staggered offsets
+        // the lattice kernel's 27-plane pull ran 1.4 % faster (FP32,
+        // 256 x 256 x 768, where the unpadded stride is a multiple of 64 MiB)
+        d.plane = (d.cells + 127) / 128 * 128 + 256;
         d.pop_off = pop;
         pop += P.planes * d.plane;
         d.M = b ? std::max(0, b->n_markers) : 0;
@@ -319,6 +323,7 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
     P.off_mark = take((size_t)std::max<long long>(reg, 1));
     P.off_feat = take(sizeof(float) * kMlpIn * M);
     P.off_h0 = take(sizeof(double) * 3 * M);
+    P.off_hk2 = take(sizeof(double) * 3 * M);
     P.off_hs = take(sizeof(double) * M);
     P.off_dSo = take(sizeof(double) * M);
     P.off_wt = take(sizeof(double) * 12 * M);
@@ -561,6 +566,7 @@ int32_t lbm_init(const lbm_case *cases, const lbm_body *bodies, int32_t n_cases,
     p.mtiles = (MarkerTile *)(a + P.off_mtiles);
     p.feat = (float *)(a + P.off_feat);
     p.h0 = (double *)(a + P.off_h0);
+    p.hk2 = (double *)(a + P.off_hk2);
     p.hs = (double *)(a + P.off_hs);
     p.dSo = (double *)(a + P.off_dSo);
     p.tbox = (TileBox *)(a + P.off_tbox);
@@ -1186,6 +1192,8 @@ int32_t lbm_log_read(lbm_ctx *ctx, int32_t c, double *out, int32_t max_records, 
 }
 
 // ------------------------------------------------------- learned warm start
+static_assert(LBM_MLP_IN == kMlpIn && LBM_MLP_PARAMS == kMlpParams, "network sizes of the header");
+
 static size_t mlp_layout(int max_batch, size_t off[12])
 {
     size_t o = 0;
@@ -1392,6 +1400,12 @@ int64_t lbm_pop_offset(const lbm_ctx *ctx, int32_t c)
 {
     if (!ctx || c < 0 || c >= ctx->n) return -1;
     return ctx->plan.cd[c].pop_off;
+}
+
+int64_t lbm_plane_stride(const lbm_ctx *ctx, int32_t c)
+{
+    if (!ctx || c < 0 || c >= ctx->n) return -1;
+    return ctx->plan.cd[c].plane;
 }
 
 void *lbm_current_buffer(const lbm_ctx *ctx) { return ctx ? ctx->pop[ctx->cur] : nullptr; }

@@ -117,6 +117,7 @@ struct DevPtrs {
     MarkerTile *mtiles;
     float *feat;     // per-marker warm-start features (12)
     double *h0;      // per-marker plain start U - I[u*] (3)
+    double *hk2;     // per-marker final h of the step before the previous one (3)
     double *hs;      // per-marker scale of the warm-start features, |h0| + |h(t-1)|
     double *dSo;     // per-marker areas of the parallel force surface (cases with force_offset > 0)
     TileBox *tbox;   // per-tile boxes of the markers' stencils, then of the force-surface points', by k_markers

@@ -564,16 +564,19 @@ __device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyView &B
     const double sg[3][3] = {{v[4], v[7], v[8]}, {v[7], v[5], v[9]}, {v[8], v[9], v[6]}};
     const double nk[3] = {p.N[3 * k], p.N[3 * k + 1], p.N[3 * k + 2]};
     const double dS = p.dS[k];
-    double s[3], rel[3], ts[3], h0[3], hp[3];
+    double s[3], rel[3], ts[3], h0[3], hp[3], hq[3], h0q[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         h0[a] = p.U[3 * k + a] - v[1 + a];
-        hp[a] = p.hk[3 * k + a];   // the previous step's final h
+        hp[a] = p.hk[3 * k + a];    // the previous step's final h
+        hq[a] = p.hk2[3 * k + a];   // the final h of the step before
+        h0q[a] = p.h0[3 * k + a];   // the previous step's plain start
     }
     // warm-start features: the plain start U - I[u*] (an invertible linear
     // map of I[u*] and U that keeps their small difference out of
-    // cancellation) and the previous step's final h, both over the marker's
-    // scale |h0| + |h(t-1)|; U scaled by kFeatScale; the normal
+    // cancellation), h(t-1), and the changes h(t-1) - h(t-2) and
+    // h0(t) - h0(t-1), over the marker's scale |h0| + |h(t-1)|; the normal
+    // and the area
     const double sc = fmax(sqrt(h0[0] * h0[0] + h0[1] * h0[1] + h0[2] * h0[2]) +
                                sqrt(hp[0] * hp[0] + hp[1] * hp[1] + hp[2] * hp[2]), 1e-14);
     p.hs[k] = sc;
@@ -582,11 +585,14 @@ __device__ inline void force_epilogue(const DevPtrs &p, int k, const BodyView &B
     for (int a = 0; a < 3; a++) {
         s[a] = sg[a][0] * nk[0] + sg[a][1] * nk[1] + sg[a][2] * nk[2];
         rel[a] = X[a] - B.r[a];
-        ft[a] = (float)(h0[a] / sc);
-        ft[3 + a] = (float)(p.U[3 * k + a] * kFeatScale);
-        ft[6 + a] = (float)nk[a];
+        ft[kFeatH0 + a] = (float)(h0[a] / sc);
         ft[kFeatHPrev + a] = (float)(hp[a] / sc);
+        ft[kFeatDH + a] = (float)((hp[a] - hq[a]) / sc);
+        ft[kFeatDH0 + a] = (float)((h0[a] - h0q[a]) / sc);
+        ft[kFeatNormal + a] = (float)nk[a];
+        if (a == 0) ft[kFeatArea] = (float)dS;
         // h_k holds what has been spread so far; dh is the next increment
+        p.hk2[3 * k + a] = hp[a];
         p.h0[3 * k + a] = h0[a];
         p.hk[3 * k + a] = spread ? 0.0 + h0[a] : 0.0;
         p.dh[3 * k + a] = h0[a];

@@ -1,11 +1,13 @@
 // mlp.hip -- the warm-start network of the learned IBM form: a
-// 12 -> 64 -> 64 -> 3 multilayer perceptron with SiLU hidden activations,
+// 16 -> 64 -> 64 -> 3 multilayer perceptron with SiLU hidden activations,
 // FP16 weights and FP32 accumulation; inference for every marker, and
 // training (per-sample forward/backward, deterministic weight-gradient sums,
 // Adam) on samples the solver produced.
 //
-// Parameter layout (flat): W1[64][12] b1[64] W2[64][64] b2[64] W3[3][64] b3[3].
+// Parameter layout (flat): W1[64][16] b1[64] W2[64][64] b2[64] W3[3][64] b3[3].
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "internal.hpp"
 #include "mlp.hpp"
@@ -13,6 +15,8 @@
 namespace turret {
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+// The same with the hardware reciprocal (about 1 ulp), for FP16-operand inference.
+__device__ __forceinline__ float sigmoid_fast(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 
 // Weights: FP16 in HBM, widened once per workgroup into LDS.
 __device__ __forceinline__ void load_weights(const _Float16 *__restrict__ th16, float *w)
@@ -60,42 +64,174 @@ __device__ __forceinline__ void mlp_forward_one(const float *w, const float x[kM
     y[2] = y2;
 }
 
-// Inference on caller arrays: X (n x 12) -> Y (n x 3).
+// ------------------------------------------------ inference on the matrix cores
+// Inference runs on v_mfma_f32_16x16x16_f16: FP16 weights and activations,
+// FP32 accumulation, SiLU in FP32.  A wavefront takes 16 samples at a time as
+// the 16 columns of D = W X: for each layer the weights are the A operand
+// (rows = output neurons, 16 per chunk) and the previous layer's activations
+// the B operand (k = input neurons, 16 per step).  Lane l of the wave holds
+// B[k][j] and D[i][j] for sample j = l % 16 and k, i = 4 (l / 16) + e
+// (e = 0..3), so a layer's output chunk c is, as it stands in the registers,
+// the next layer's operand for input step c.  The weights stay in registers
+// while the wave strides over sample tiles.
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kInSteps = (kMlpIn + 15) / 16;   // 16-wide input steps of layer 1 (zero padded)
+constexpr int kHChunks = kMlpH / 16;
+static_assert(kMlpH % 16 == 0 && kMlpOut <= 4, "layer sizes of the matrix-core inference");
+static_assert(kMlpIn % 4 == 0 && kOffW2 % 4 == 0 && kOffB1 % 4 == 0 && kOffB2 % 4 == 0 && kOffW3 % 4 == 0,
+              "8-byte aligned parameter blocks for the vector loads");
+
+struct MlpRegs {
+    half4_t w1[kHChunks][kInSteps], w2[kHChunks][kHChunks], w3[kHChunks];
+    float b1[kHChunks][4], b2[kHChunks][4], b3[4];
+};
+
+// Four consecutive FP16 parameters starting at a multiple of 4 (one 8-byte load).
+__device__ __forceinline__ half4_t load_half4(const _Float16 *__restrict__ th, int at)
+{
+    return *reinterpret_cast<const half4_t *>(th + at);
+}
+
+__device__ inline void mlp_load_regs(const _Float16 *__restrict__ th, MlpRegs &R)
+{
+    const int l = threadIdx.x & 63, r = l & 15, kq = (l >> 4) * 4;
+    const _Float16 zero = (_Float16)0.0f;
+#pragma unroll
+    for (int mc = 0; mc < kHChunks; mc++) {
+        const int o = 16 * mc + r;   // output neuron of this lane's A rows
+#pragma unroll
+        for (int kc = 0; kc < kInSteps; kc++) R.w1[mc][kc] = load_half4(th, kOffW1 + o * kMlpIn + 16 * kc + kq);
+#pragma unroll
+        for (int kc = 0; kc < kHChunks; kc++) R.w2[mc][kc] = load_half4(th, kOffW2 + o * kMlpH + 16 * kc + kq);
+        // biases of the D rows this lane holds
+        const half4_t b1 = load_half4(th, kOffB1 + 16 * mc + kq), b2 = load_half4(th, kOffB2 + 16 * mc + kq);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            R.b1[mc][e] = (float)b1[e];
+            R.b2[mc][e] = (float)b2[e];
+        }
+    }
+#pragma unroll
+    for (int kc = 0; kc < kHChunks; kc++) {
+        const half4_t w = load_half4(th, kOffW3 + (r < kMlpOut ? r : 0) * kMlpH + 16 * kc + kq);
+        const half4_t z = {zero, zero, zero, zero};
+        R.w3[kc] = r < kMlpOut ? w : z;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) R.b3[e] = kq + e < kMlpOut ? (float)th[kOffB3 + kq + e] : 0.0f;
+}
+
+__device__ __forceinline__ float4_t mfma16(half4_t a, half4_t b, float4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// One tile of 16 samples: x holds this lane's B operand of layer 1; the
+// result holds, in lanes 0..15, outputs 0..kMlpOut-1 of sample l.
+__device__ inline float4_t mlp_tile(const MlpRegs &R, const half4_t x[kInSteps])
+{
+    half4_t a1[kHChunks], a2[kHChunks];
+#pragma unroll
+    for (int mc = 0; mc < kHChunks; mc++) {
+        float4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kc = 0; kc < kInSteps; kc++) d = mfma16(R.w1[mc][kc], x[kc], d);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const float z = d[e] + R.b1[mc][e];
+            a1[mc][e] = (_Float16)(z * sigmoid_fast(z));
+        }
+    }
+#pragma unroll
+    for (int mc = 0; mc < kHChunks; mc++) {
+        float4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kc = 0; kc < kHChunks; kc++) d = mfma16(R.w2[mc][kc], a1[kc], d);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const float z = d[e] + R.b2[mc][e];
+            a2[mc][e] = (_Float16)(z * sigmoid_fast(z));
+        }
+    }
+    float4_t y = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kc = 0; kc < kHChunks; kc++) y = mfma16(R.w3[kc], a2[kc], y);
+#pragma unroll
+    for (int e = 0; e < 4; e++) y[e] += R.b3[e];
+    return y;
+}
+
+// This lane's layer-1 operand for sample s of an n x kMlpIn FP32 array
+// (zeros past n): four consecutive features, one 16-byte load.
+static_assert(kMlpIn % 16 == 0, "one 16-byte feature load per lane and input step");
+__device__ inline void mlp_operand(const float *__restrict__ X, int s, int n, half4_t x[kInSteps])
+{
+    const int kq = ((threadIdx.x & 63) >> 4) * 4;
+#pragma unroll
+    for (int kc = 0; kc < kInSteps; kc++) {
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (s < n) v = *reinterpret_cast<const float4 *>(X + (long long)s * kMlpIn + 16 * kc + kq);
+        x[kc][0] = (_Float16)v.x;
+        x[kc][1] = (_Float16)v.y;
+        x[kc][2] = (_Float16)v.z;
+        x[kc][3] = (_Float16)v.w;
+    }
+}
+
+// Inference on caller arrays: X (n x kMlpIn) -> Y (n x 3).  Every wave strides
+// over 16-sample tiles; the loop bound is the same for the whole wave.
 __global__ void __launch_bounds__(256) k_mlp_forward(const _Float16 *__restrict__ th16, const float *__restrict__ X,
                                                      int n, float *__restrict__ Y)
 {
-    __shared__ float w[kMlpParams];
-    load_weights(th16, w);
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    float x[kMlpIn], y[kMlpOut];
+    MlpRegs R;
+    mlp_load_regs(th16, R);
+    const int l = threadIdx.x & 63;
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), nwaves = (int)((gridDim.x * blockDim.x) >> 6);
+    for (int s0 = 16 * wave; s0 < n; s0 += 16 * nwaves) {
+        const int s = s0 + (l & 15);
+        half4_t x[kInSteps];
+        mlp_operand(X, s, n, x);
+        const float4_t y = mlp_tile(R, x);
+        if (l < 16 && s < n)
 #pragma unroll
-    for (int i = 0; i < kMlpIn; i++) x[i] = X[(long long)s * kMlpIn + i];
-    mlp_forward_one(w, x, y, nullptr, nullptr, nullptr, nullptr, 0);
-#pragma unroll
-    for (int j = 0; j < kMlpOut; j++) Y[(long long)s * kMlpOut + j] = y[j];
+            for (int j = 0; j < kMlpOut; j++) Y[(long long)s * kMlpOut + j] = y[j];
+    }
 }
 
 // Warm start inside the IBM coupling: the network predicts, over the
 // marker's feature scale s_k, the change of h from the previous step's final
-// value (features 9..11 = h(t-1) / s_k): h = s_k (feature 9..11 +
-// MLP(features_k)), for every marker of an unmasked case; it becomes the
-// first increment to spread.
+// value: h = s_k (h(t-1) / s_k + MLP(features_k)), for every marker of an
+// unmasked case; it becomes the first increment to spread.  A zero network
+// starts from h(t-1), the control start.
 __global__ void __launch_bounds__(256) k_mlp_warm_start(const _Float16 *__restrict__ th16, DevPtrs p, int Mtot)
 {
-    __shared__ float w[kMlpParams];
-    load_weights(th16, w);
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= Mtot || p.body[p.mcase[k]].err != 0) return;
-    float x[kMlpIn], y[kMlpOut];
+    MlpRegs R;
+    mlp_load_regs(th16, R);
+    const int l = threadIdx.x & 63;
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), nwaves = (int)((gridDim.x * blockDim.x) >> 6);
+    for (int s0 = 16 * wave; s0 < Mtot; s0 += 16 * nwaves) {
+        const int k = s0 + (l & 15);
+        half4_t x[kInSteps];
+        mlp_operand(p.feat, k, Mtot, x);
+        // the epilogue's operands, loaded before the matrix work
+        bool live = false;
+        float hp[3] = {0.0f, 0.0f, 0.0f};
+        double hs = 0.0;
+        if (l < 16 && k < Mtot) {
+            live = p.body[p.mcase[k]].err == 0;
 #pragma unroll
-    for (int i = 0; i < kMlpIn; i++) x[i] = p.feat[(long long)k * kMlpIn + i];
-    mlp_forward_one(w, x, y, nullptr, nullptr, nullptr, nullptr, 0);
+            for (int a = 0; a < 3; a++) hp[a] = p.feat[(long long)kMlpIn * k + kFeatHPrev + a];
+            hs = p.hs[k];
+        }
+        const float4_t y = mlp_tile(R, x);
+        if (live)
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const double h = ((double)x[9 + a] + (double)y[a]) * p.hs[k];
-        p.hk[3 * k + a] = 0.0;
-        p.dh[3 * k + a] = h;
+            for (int a = 0; a < 3; a++) {
+                p.hk[3 * k + a] = 0.0;
+                p.dh[3 * k + a] = ((double)hp[a] + (double)y[a]) * hs;
+            }
     }
 }
 
@@ -243,15 +379,25 @@ __global__ void k_mlp_round(const float *__restrict__ th32, _Float16 *__restrict
 }
 
 // ------------------------------------------------------------ launchers
+// Workgroups of 4 waves for the matrix-core inference: one wave per 16-sample
+// tile up to 4096 waves (4 per SIMD, the kernel's occupancy), which then stride.
+static dim3 infer_grid(int n)
+{
+    const int tiles = (n + 15) / 16;
+    return dim3((unsigned)std::max(1, (std::min(tiles, 4096) + 3) / 4));
+}
+
 hipError_t launch_mlp_forward(const _Float16 *th16, const float *X, int n, float *Y, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_forward, dim3((n + 255) / 256), dim3(256), 0, s, th16, X, n, Y);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_forward, infer_grid(n), dim3(256), 0, s, th16, X, n, Y);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_warm_start(const _Float16 *th16, const DevPtrs &p, int Mtot, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_warm_start, dim3((Mtot + 255) / 256), dim3(256), 0, s, th16, p, Mtot);
+    if (Mtot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_warm_start, infer_grid(Mtot), dim3(256), 0, s, th16, p, Mtot);
     return hipGetLastError();
 }
 

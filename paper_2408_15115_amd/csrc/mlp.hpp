@@ -5,23 +5,25 @@
 
 namespace turret {
 
-constexpr int kMlpIn = 12, kMlpH = 64, kMlpOut = 3;
+constexpr int kMlpIn = 16, kMlpH = 64, kMlpOut = 3;
 constexpr int kOffW1 = 0;
 constexpr int kOffB1 = kOffW1 + kMlpH * kMlpIn;
 constexpr int kOffW2 = kOffB1 + kMlpH;
 constexpr int kOffB2 = kOffW2 + kMlpH * kMlpH;
 constexpr int kOffW3 = kOffB2 + kMlpH;
 constexpr int kOffB3 = kOffW3 + kMlpOut * kMlpH;
-constexpr int kMlpParams = kOffB3 + kMlpOut;   // 5187
+constexpr int kMlpParams = kOffB3 + kMlpOut;   // 5443
 constexpr int kMlpSlice = 256;                 // samples per weight-gradient partial sum
 
-// The marker velocity feature is scaled by 1 / 0.02, the largest lattice
-// terminal velocity of the cases, so it is O(1); the force-like features
-// and the output are taken over a per-marker scale instead.
-constexpr double kFeatScale = 50.0;
-// Features kFeatHPrev .. kFeatHPrev + 2 are the previous step's final h over
-// the marker's scale; a zero network output starts from them.
-constexpr int kFeatHPrev = 9;
+// Warm-start features of marker k, each a 3-vector over the marker's scale
+// s_k = |h0(t)| + |h(t-1)|: the plain start h0(t) = U - I[u*], the previous
+// step's final h(t-1), the last change of the final h, h(t-1) - h(t-2), and
+// the change of the plain start, h0(t) - h0(t-1) (the changes are formed in
+// FP64 before they are scaled: as differences of two FP16 operands of
+// similar size they would keep only a few bits); then the normal n and the
+// marker's area dS.  The network predicts the change of h from h(t-1), over
+// s_k.
+constexpr int kFeatH0 = 0, kFeatHPrev = 3, kFeatDH = 6, kFeatDH0 = 9, kFeatNormal = 12, kFeatArea = 15;
 
 // Per-sample training scratch, [field][sample] layout (n samples).
 struct MlpScratch {

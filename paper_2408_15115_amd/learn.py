@@ -12,7 +12,7 @@ import numpy as np
 
 from . import turret as T
 
-_SHAPES = [(12, 64), (64, 64), (64, 3)]
+_SHAPES = [(T.MLP_IN, 64), (64, 64), (64, 3)]
 
 
 def _split(theta):

@@ -19,7 +19,9 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "turret.h")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_F32, LBM_F16, LBM_BF16, LBM_MOM = 0, 1, 2, 3
 LBM_WARM_NONE, LBM_WARM_PREVIOUS, LBM_WARM_MLP = 0, 1, 2
-MLP_PARAMS = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
+MLP_IN = 16   # network inputs (LBM_MLP_IN)
+FEAT_NORMAL = 12   # first of the three normal components among the features
+MLP_PARAMS = MLP_IN * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
 STORAGE = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16, "mom": LBM_MOM}
 ELEM_BYTES = {LBM_F32: 4, LBM_F16: 2, LBM_BF16: 2, LBM_MOM: 4}
 ERRNAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE", -5: "LBM_ESTATE"}
@@ -77,6 +79,7 @@ _sig = {
     "lbm_save": (C.c_int32, [_ctx, C.c_char_p]),
     "lbm_load": (C.c_int32, [_ctx, C.c_char_p]),
     "lbm_pop_offset": (C.c_int64, [_ctx, C.c_int32]),
+    "lbm_plane_stride": (C.c_int64, [_ctx, C.c_int32]),
     "lbm_current_buffer": (C.c_void_p, [_ctx]),
     "lbm_stream_copy": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "mlp_required_bytes": (C.c_int32, [C.c_int32, _P(C.c_int64)]),
@@ -316,7 +319,7 @@ class Solver:
         M = self.marker_count()
         cur = torch.cuda.current_stream()
         with torch.cuda.stream(self.stream):
-            f = torch.empty((M, 12), dtype=torch.float32, device="cuda")
+            f = torch.empty((M, MLP_IN), dtype=torch.float32, device="cuda")
             t = torch.empty((M, 3), dtype=torch.float32, device="cuda")
             self._chk("lbm_ibm_samples", lbm_ibm_samples(self._ctx, C.c_void_p(f.data_ptr()),
                                                          C.c_void_p(t.data_ptr())))
@@ -341,6 +344,9 @@ class Solver:
     def pop_offset(self, case=0):
         return int(lbm_pop_offset(self._ctx, case))
 
+    def plane_stride(self, case=0):
+        return int(lbm_plane_stride(self._ctx, case))
+
     def current_buffer(self):
         return int(lbm_current_buffer(self._ctx))
 
@@ -361,7 +367,7 @@ def mlp_init_params(seed):
     the library's flat layout."""
     rng = np.random.default_rng(seed)
     parts = []
-    for fan_in, fan_out in ((12, 64), (64, 64), (64, 3)):
+    for fan_in, fan_out in ((MLP_IN, 64), (64, 64), (64, 3)):
         b = np.sqrt(6.0 / fan_in)
         parts += [rng.uniform(-b, b, size=fan_out * fan_in), np.zeros(fan_out)]
     return np.concatenate(parts).astype(np.float32)

@@ -47,7 +47,8 @@ def test_required_bytes_of_the_sphere_case():
     from paper_2408_15115_amd import turret as T
     case, body = W.case_sphere48()
     a, b, aux = T.required_bytes([case], [body])
-    assert a == b == 27 * 48 ** 3 * 4
+    plane = 48 ** 3 + 256          # direction planes staggered by 1 KB
+    assert a == b == 27 * plane * 4
     a16, _, _ = T.required_bytes([case], [body], storage="f16")
     assert a16 == a // 2
     assert aux > 400 * 8 * 3
@@ -148,8 +149,9 @@ def test_d3q19_lattice_option():
     from paper_2408_15115_amd import turret as T
     case = W.make_case(24, 20, 16, 0.6, W.BC_PERIODIC, W.BC_PERIODIC, 0)
     a, b, _ = T.required_bytes([case], None, lattice=19)
-    assert a == b == 19 * 24 * 20 * 16 * 4
-    assert T.required_bytes([case], None)[0] == 27 * 24 * 20 * 16 * 4
+    plane = 24 * 20 * 16 + 256
+    assert a == b == 19 * plane * 4
+    assert T.required_bytes([case], None)[0] == 27 * plane * 4
     bad = [({"storage": "f16"}, "FP32"), ({"schedule": 1}, "schedule 0"), ({"lattice": 21}, "lattice")]
     for kw, needle in bad:
         with pytest.raises(T.TurretError) as e:
@@ -172,7 +174,7 @@ def test_moment_storage_option():
     from paper_2408_15115_amd import turret as T
     case = W.make_case(24, 20, 40, 0.6, W.BC_PERIODIC, W.BC_PERIODIC, 0)
     cells = 24 * 20 * 40
-    plane = (cells + 127) // 128 * 128
+    plane = (cells + 127) // 128 * 128 + 256   # staggered direction planes
     a, b, _ = T.required_bytes([case], None, storage="mom")
     assert a == b == 10 * plane * 4
     T.required_bytes([dict(case, sponge=6)], None, storage="mom")

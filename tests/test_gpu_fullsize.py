@@ -38,9 +38,10 @@ def analytic_deviation(i, x, y, z, nx, ny, nz, w):
 
 def current_state(S, torch, nx, ny, nz):
     """FP32 deviations of the current buffer as a device view (27, nz, ny, nx);
-    valid for one case whose ring origin is 0 and whose plane is nx*ny*nz."""
+    valid for one case whose ring origin is 0."""
     cur = S.bufs[0] if S.current_buffer() == S.bufs[0].data_ptr() else S.bufs[1]
-    return cur.view(torch.float32)[:27 * nx * ny * nz].view(27, nz, ny, nx)
+    plane = S.plane_stride(0)
+    return cur.view(torch.float32)[:27 * plane].view(27, plane)[:, :nx * ny * nz].view(27, nz, ny, nx)
 
 
 def test_lattice_step_at_full_size_sampled(T, orc):
@@ -51,7 +52,8 @@ def test_lattice_step_at_full_size_sampled(T, orc):
     xi, w = orc.lattice()
     say("full-size lattice parity: writing the analytic state")
     S = T.Solver([case], None, stream=torch.cuda.Stream())
-    plane = (nx * ny * nz + 127) // 128 * 128
+    plane = S.plane_stride(0)
+    assert S.pop_offset(0) == 0 and plane >= nx * ny * nz
     pop = S.bufs[0] if S.current_buffer() == S.bufs[0].data_ptr() else S.bufs[1]
     view = pop.view(torch.float32)
     X = np.arange(nx, dtype=np.float64)[None, None, :]
@@ -61,7 +63,6 @@ def test_lattice_step_at_full_size_sampled(T, orc):
         g = analytic_deviation(i, X, Y, Z, nx, ny, nz, w).astype(np.float32)
         view[i * plane:i * plane + nx * ny * nz].copy_(torch.from_numpy(np.ascontiguousarray(g).ravel()))
     torch.cuda.synchronize()
-    assert plane == nx * ny * nz
     S.lbm_step()
     torch.cuda.synchronize()
     out = current_state(S, torch, nx, ny, nz)

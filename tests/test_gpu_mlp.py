@@ -13,6 +13,7 @@ from paper_2408_15115_amd import workloads as W
 from tests.gpu_util import say
 
 pytestmark = pytest.mark.gpu
+NIN = ref.LAYERS[0][0]   # network inputs
 # result summaries go to $TURRET_RESULTS_DIR when it is set
 OUTDIR = os.environ.get("TURRET_RESULTS_DIR")
 
@@ -38,12 +39,22 @@ def dev(a):
 def test_forward_and_gradient_match_reference(T):
     rng = np.random.default_rng(3)
     theta = fp16_exact(ref.init_params(5) + 0.05 * rng.standard_normal(ref.N_PARAMS))
-    X = rng.standard_normal((1000, 12)).astype(np.float32)
+    X = rng.standard_normal((1000, NIN)).astype(np.float32)
     Tg = rng.standard_normal((1000, 3)).astype(np.float32)
     net = T.MLP(max_batch=4096, params=theta)
+    # inference: FP16 operands on the matrix cores, FP32 accumulation.  It
+    # matches the reference with binary16 operands up to the accumulation's
+    # rounding, which moves an operand across a binary16 rounding boundary
+    # now and then (one unit there is 4.9e-4 relative)
     Y = net.forward(dev(X)).cpu().numpy()
+    Yh = ref.forward_half_operands(theta.astype(np.float64), X.astype(np.float64))
     Yr, _ = ref.forward(theta.astype(np.float64), X.astype(np.float64))
-    assert np.max(np.abs(Y - Yr)) < 1e-5 * np.max(np.abs(Yr))
+    scale = np.max(np.abs(Yr))
+    err, err_med = np.max(np.abs(Y - Yh)) / scale, np.median(np.abs(Y - Yh)) / scale
+    say(f"  inference vs binary16-operand reference: max {err:.3e}, median {err_med:.3e}; "
+        f"vs FP64 reference {np.max(np.abs(Y - Yr)) / scale:.3e}")
+    assert err < 5e-4 and err_med < 1e-6
+    # the training passes keep FP32 operands: gradient and loss to 1e-5
     g, loss = net.grad(dev(X), dev(Tg))
     gr = ref.grad(theta.astype(np.float64), X.astype(np.float64), Tg.astype(np.float64))
     lr_ = ref.loss(theta.astype(np.float64), X.astype(np.float64), Tg.astype(np.float64))
@@ -58,7 +69,7 @@ def test_forward_and_gradient_match_reference(T):
 def test_adam_step_matches_reference(T):
     rng = np.random.default_rng(4)
     theta = fp16_exact(ref.init_params(1))
-    X = rng.standard_normal((512, 12)).astype(np.float32)
+    X = rng.standard_normal((512, NIN)).astype(np.float32)
     Tg = rng.standard_normal((512, 3)).astype(np.float32)
     net = T.MLP(max_batch=1024, params=theta)
     g, _ = net.grad(dev(X), dev(Tg))
@@ -72,8 +83,8 @@ def test_adam_step_matches_reference(T):
 def test_training_reduces_loss(T):
     import torch
     rng = np.random.default_rng(9)
-    X = rng.standard_normal((8192, 12)).astype(np.float32)
-    A = rng.standard_normal((12, 3)) * 0.3
+    X = rng.standard_normal((8192, NIN)).astype(np.float32)
+    A = rng.standard_normal((NIN, 3)) * 0.3
     Tg = (np.tanh(X @ A) + 0.1 * X[:, :3] ** 2).astype(np.float32)
     net = T.MLP(max_batch=8192, seed=2)
     Xd, Td = dev(X), dev(Tg)
@@ -143,7 +154,7 @@ def evaluate(T, cases, bodies, mode, net=None, cycles=1, gate=1e30, steps=80, sk
 def test_samples_from_a_side_stream_are_ready_on_the_current_stream(T):
     """The solver runs on its own stream; the samples it returns are read on
     the caller's current stream right away (no explicit synchronization) and
-    must hold every marker's features: the unit normals (features 6..8)."""
+    must hold every marker's features: the unit normals."""
     import torch
     cases, bodies = learned_batch(5)
     S = T.Solver(cases, bodies, stream=torch.cuda.Stream())
@@ -154,14 +165,15 @@ def test_samples_from_a_side_stream_are_ready_on_the_current_stream(T):
     fb, tb = f.cpu().numpy(), t.cpu().numpy()
     S.close()
     assert np.array_equal(fa, fb) and np.array_equal(ta, tb)
-    assert np.allclose(np.linalg.norm(fa[:, 6:9], axis=1), 1.0, atol=1e-6)
+    nrm = fa[:, T.FEAT_NORMAL:T.FEAT_NORMAL + 3]
+    assert np.allclose(np.linalg.norm(nrm, axis=1), 1.0, atol=1e-6)
 
 
 def test_gate_extremes(T):
     """Gate 0 rejects every learned start and reproduces the plain run
     bitwise; an infinite gate accepts every start after its first cycle."""
     cases, bodies = learned_batch(5)
-    # a zero network: the learned start is the plain start itself
+    # a zero network: the learned start is the previous step's h
     net = T.MLP(max_batch=1024, params=np.zeros(ref.N_PARAMS, np.float32))
     steps = 12
     plain = evaluate(T, cases, bodies, "plain", steps=steps, skip=0)
@@ -198,7 +210,10 @@ def test_learned_warm_start_gains_over_plain_start(T):
     plain = evaluate(T, cases, bodies, "plain")
     prev = evaluate(T, cases, bodies, "previous", None, cycles=4, gate=0.0)
     mlp = evaluate(T, cases, bodies, "mlp", net, cycles=4, gate=0.0)
-    assert plain is not None and mlp is not None and prev is not None
+    # a zero network starts from the previous step's h: the same residuals
+    zero = T.MLP(max_batch=1024, params=np.zeros(ref.N_PARAMS, np.float32))
+    zero_run = evaluate(T, cases, bodies, "mlp", zero, cycles=4, gate=0.0)
+    assert plain is not None and mlp is not None and prev is not None and zero_run is not None
     r = lambda run, k: float(np.median(run["hist"][:, :, k]))
     # 4. gated learned start: cycles until the plain four-cycle residual
     # level of the case is reached, at most 3, else the plain cycles
@@ -224,13 +239,19 @@ def test_learned_warm_start_gains_over_plain_start(T):
            "plain_resid_after_k_cycles": [r(plain, k) for k in range(4)],
            "previous_h_resid_after_k_cycles": [r(prev, k) for k in range(4)],
            "mlp_resid_after_k_cycles": [r(mlp, k) for k in range(4)],
+           "zero_network_resid_after_k_cycles": [r(zero_run, k) for k in range(4)],
            "gated": gated}
     say("  " + json.dumps(res))
     if OUTDIR:
         os.makedirs(OUTDIR, exist_ok=True)
         with open(os.path.join(OUTDIR, "learned_gain.json"), "w") as f:
             json.dump(res, f)
-    # the learned start beats the plain start after one cycle
+    # after one cycle the learned start beats the plain start and its
+    # control, the previous step's h (a zero network)
     assert r(mlp, 0) < r(plain, 0)
+    assert r(mlp, 0) < r(prev, 0)
     # the diagnostic runs are the plain run
     assert np.array_equal(mlp["Fz"], plain["Fz"]) and np.array_equal(prev["Fz"], plain["Fz"])
+    assert np.array_equal(zero_run["Fz"], plain["Fz"])
+    # a zero network is the control start, cycle by cycle
+    assert np.array_equal(zero_run["hist"], prev["hist"])
