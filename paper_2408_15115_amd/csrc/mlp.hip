@@ -89,12 +89,12 @@ struct MlpRegs {
 };
 
 // Four consecutive FP16 parameters starting at a multiple of 4 (one 8-byte load).
-__device__ __forceinline__ half4_t load_half4(const _Float16 *__restrict__ th, int at)
+__device__ __forceinline__ half4_t load_half4(const _Float16 *th, int at)
 {
     return *reinterpret_cast<const half4_t *>(th + at);
 }
 
-__device__ inline void mlp_load_regs(const _Float16 *__restrict__ th, MlpRegs &R)
+__device__ inline void mlp_load_regs(const _Float16 *th, MlpRegs &R)
 {
     const int l = threadIdx.x & 63, r = l & 15, kq = (l >> 4) * 4;
     const _Float16 zero = (_Float16)0.0f;
@@ -121,6 +121,17 @@ __device__ inline void mlp_load_regs(const _Float16 *__restrict__ th, MlpRegs &R
     }
 #pragma unroll
     for (int e = 0; e < 4; e++) R.b3[e] = kq + e < kMlpOut ? (float)th[kOffB3 + kq + e] : 0.0f;
+}
+
+// The FP16 parameters, staged once per workgroup in LDS with 16-byte copies
+// (the parameter buffer extends to a 256-byte boundary, past the rounding up
+// to 8 values); the waves then take their operands from there.
+constexpr int kMlpParams8 = (kMlpParams + 7) / 8 * 8;
+__device__ inline void mlp_stage(const _Float16 *__restrict__ th, _Float16 *w)
+{
+    for (int i = 8 * (int)threadIdx.x; i < kMlpParams8; i += 8 * (int)blockDim.x)
+        *reinterpret_cast<uint4 *>(w + i) = *reinterpret_cast<const uint4 *>(th + i);
+    __syncthreads();
 }
 
 __device__ __forceinline__ float4_t mfma16(half4_t a, half4_t b, float4_t c)
@@ -164,19 +175,34 @@ __device__ inline float4_t mlp_tile(const MlpRegs &R, const half4_t x[kInSteps])
 }
 
 // This lane's layer-1 operand for sample s of an n x kMlpIn FP32 array
-// (zeros past n): four consecutive features, one 16-byte load.
+// (zeros past n): four consecutive features per input step, one 16-byte
+// load each.  The loads and the conversion to FP16 are split so that a
+// wave can issue the next tile's loads before it works on the current tile.
 static_assert(kMlpIn % 16 == 0, "one 16-byte feature load per lane and input step");
-__device__ inline void mlp_operand(const float *__restrict__ X, int s, int n, half4_t x[kInSteps])
+struct MlpRaw {
+    float4 v[kInSteps];
+};
+
+__device__ inline MlpRaw mlp_load(const float *__restrict__ X, int s, int n)
 {
     const int kq = ((threadIdx.x & 63) >> 4) * 4;
+    MlpRaw r;
 #pragma unroll
     for (int kc = 0; kc < kInSteps; kc++) {
-        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (s < n) v = *reinterpret_cast<const float4 *>(X + (long long)s * kMlpIn + 16 * kc + kq);
-        x[kc][0] = (_Float16)v.x;
-        x[kc][1] = (_Float16)v.y;
-        x[kc][2] = (_Float16)v.z;
-        x[kc][3] = (_Float16)v.w;
+        r.v[kc] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (s < n) r.v[kc] = *reinterpret_cast<const float4 *>(X + (long long)s * kMlpIn + 16 * kc + kq);
+    }
+    return r;
+}
+
+__device__ inline void mlp_convert(const MlpRaw &r, half4_t x[kInSteps])
+{
+#pragma unroll
+    for (int kc = 0; kc < kInSteps; kc++) {
+        x[kc][0] = (_Float16)r.v[kc].x;
+        x[kc][1] = (_Float16)r.v[kc].y;
+        x[kc][2] = (_Float16)r.v[kc].z;
+        x[kc][3] = (_Float16)r.v[kc].w;
     }
 }
 
@@ -185,14 +211,19 @@ __device__ inline void mlp_operand(const float *__restrict__ X, int s, int n, ha
 __global__ void __launch_bounds__(256) k_mlp_forward(const _Float16 *__restrict__ th16, const float *__restrict__ X,
                                                      int n, float *__restrict__ Y)
 {
+    __shared__ __align__(16) _Float16 wsh[kMlpParams8];
+    mlp_stage(th16, wsh);
     MlpRegs R;
-    mlp_load_regs(th16, R);
+    mlp_load_regs(wsh, R);
     const int l = threadIdx.x & 63;
     const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), nwaves = (int)((gridDim.x * blockDim.x) >> 6);
-    for (int s0 = 16 * wave; s0 < n; s0 += 16 * nwaves) {
+    const int stride = 16 * nwaves;
+    MlpRaw next = mlp_load(X, 16 * wave + (l & 15), n);
+    for (int s0 = 16 * wave; s0 < n; s0 += stride) {
         const int s = s0 + (l & 15);
         half4_t x[kInSteps];
-        mlp_operand(X, s, n, x);
+        mlp_convert(next, x);
+        next = mlp_load(X, s + stride, n);   // the next tile's features, in flight during this one
         const float4_t y = mlp_tile(R, x);
         if (l < 16 && s < n)
 #pragma unroll
@@ -207,14 +238,19 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const _Float16 *__restrict_
 // starts from h(t-1), the control start.
 __global__ void __launch_bounds__(256) k_mlp_warm_start(const _Float16 *__restrict__ th16, DevPtrs p, int Mtot)
 {
+    __shared__ __align__(16) _Float16 wsh[kMlpParams8];
+    mlp_stage(th16, wsh);
     MlpRegs R;
-    mlp_load_regs(th16, R);
+    mlp_load_regs(wsh, R);
     const int l = threadIdx.x & 63;
     const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), nwaves = (int)((gridDim.x * blockDim.x) >> 6);
-    for (int s0 = 16 * wave; s0 < Mtot; s0 += 16 * nwaves) {
+    const int stride = 16 * nwaves;
+    MlpRaw next = mlp_load(p.feat, 16 * wave + (l & 15), Mtot);
+    for (int s0 = 16 * wave; s0 < Mtot; s0 += stride) {
         const int k = s0 + (l & 15);
         half4_t x[kInSteps];
-        mlp_operand(p.feat, k, Mtot, x);
+        mlp_convert(next, x);
+        next = mlp_load(p.feat, k + stride, Mtot);   // the next tile's features, in flight during this one
         // the epilogue's operands, loaded before the matrix work
         bool live = false;
         float hp[3] = {0.0f, 0.0f, 0.0f};
@@ -380,11 +416,14 @@ __global__ void k_mlp_round(const float *__restrict__ th32, _Float16 *__restrict
 
 // ------------------------------------------------------------ launchers
 // Workgroups of 4 waves for the matrix-core inference: one wave per 16-sample
-// tile up to 4096 waves (4 per SIMD, the kernel's occupancy), which then stride.
+// tile up to 2048 waves (2 per SIMD), which then stride.  Over the 161,818
+// markers of the 64-case batch 2048 waves took 12.5 us, 1024 and 4096 waves
+// 13.2 and 12.8 us (weights staged in LDS; 16.6 us with every wave loading
+// them from memory at 4096 waves).
 static dim3 infer_grid(int n)
 {
     const int tiles = (n + 15) / 16;
-    return dim3((unsigned)std::max(1, (std::min(tiles, 4096) + 3) / 4));
+    return dim3((unsigned)std::max(1, (std::min(tiles, 2048) + 3) / 4));
 }
 
 hipError_t launch_mlp_forward(const _Float16 *th16, const float *X, int n, float *Y, hipStream_t s)
