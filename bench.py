@@ -90,9 +90,14 @@ def timed_steps(S, torch, steps, warmup):
 
 
 def graph_steps(S, torch, steps):
-    """Exactly `steps` coupled steps as replays of a captured 2-step graph (a
-    1-step graph for an odd count), after one untimed replay; ms per step."""
-    per = 2 if steps % 2 == 0 else 1
+    """Exactly `steps` coupled steps as replays of a captured 10-step graph
+    (2-step when `steps` is not a multiple of 10; graphs hold an even number
+    of steps), after one untimed replay; ms per step.  Inside a graph the
+    window test of one step and the body advance of the next share a kernel."""
+    if steps % 2:
+        raise ValueError("graph replay times an even number of steps")
+    per = 10 if steps % 10 == 0 else 2
+    graph_steps.per = per
     S.graph_capture(per)
     S.graph_launch()
     torch.cuda.synchronize()
@@ -552,7 +557,8 @@ def lattice_rate_run(T, W, torch, n=(256, 256, 768), steps=20, warmup=3):
 
 def long_run(T, W, torch, which, steps, storage="f32", chunk=None):
     """The stated run lengths, once: the scale case for 20k steps (about five
-    window shifts) or the 64-case batch for 5k steps.  Graph replay in chunks;
+    window shifts) or the 64-case batch for 5k steps.  Replays of a 10-step
+    graph in chunks;
     after each chunk the body states (shifts, drag, velocity, the Reynolds
     number reached, error bits) are read back and logged."""
     import numpy as np
@@ -568,17 +574,19 @@ def long_run(T, W, torch, which, steps, storage="f32", chunk=None):
         sched = autotune.tune_step(cases, bodies, storage=storage)["best"]
         chunk = chunk or 250
     S = T.Solver(cases, bodies, storage=storage, stream=torch.cuda.Stream(), **sched)
-    S.graph_capture(2)
+    S.graph_capture(10)
     nu = [(c["tau"] - 0.5) / 3.0 for c in cases]
     rows, done = [], 0
     t0 = time.perf_counter()
     gpu_ms = 0.0
     while done < steps:
         n = min(chunk, steps - done)
-        n -= n % 2
+        n -= n % 10
+        if n == 0:
+            break
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(S.stream)
-        for _ in range(n // 2):
+        for _ in range(n // 10):
             S.graph_launch()
         e1.record(S.stream)
         torch.cuda.synchronize()
@@ -712,6 +720,7 @@ def main():
     ap.add_argument("--sweep-offsets", type=str, default="0,3",
                     help="force-surface offsets of the --settling-sweep runs")
     ap.add_argument("--no-stability", action="store_true")
+    ap.add_argument("--no-long", action="store_true", help="skip the stated run lengths (20k / 5k steps)")
     ap.add_argument("--kappa", type=float, default=2.7, help="density ratio of the --table3 spheres")
     ap.add_argument("--lattice-rates", action="store_true",
                     help="run only the fluid-only lattice kernel comparison (D3Q27, D3Q19, moment storage)")
@@ -904,6 +913,24 @@ def main():
         log(f"  fluid-only lattice kernel: D3Q27 {lr19['d3q27']}, D3Q19 {lr19['d3q19']}, "
             f"D3Q27 moment storage {lr19['d3q27_moments']}")
 
+    if not args.no_variants and not args.no_long:
+        # the stated run lengths: the scale case for 20k steps, the batch for 5k
+        runs = {}
+        for which, n in (("scale", 20000), ("batch", 5000)):
+            r = long_run(T, W, torch, which, n)
+            last = r["chunks"][-1]
+            runs[which] = {k: v for k, v in r.items() if k not in ("chunks", "cases")}
+            runs[which]["final"] = last
+            if which == "batch":
+                runs[which]["shifts_total"] = int(sum(c["shifts"] for c in r["cases"]))
+                runs[which]["masked_seeds"] = [c["seed"] for c in r["cases"] if c["err"]]
+                runs[which]["re_reached_over_target"] = sorted(
+                    round(c["re_reached"] / c["re_target"], 3) for c in r["cases"])
+        variants["stated_run_lengths"] = runs
+        log(f"  stated run lengths: scale {runs['scale']['ms_per_step']:.3f} ms/step, "
+            f"{runs['scale']['final']['shifts']} shifts; batch {runs['batch']['ms_per_step']:.3f} ms/step, "
+            f"{runs['batch']['shifts_total']} shifts, masked {runs['batch']['masked_seeds']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle on bounded samples")
@@ -928,7 +955,8 @@ def main():
         "config": {"workload": "falling-frame box 256x256x768, tilted oblate ellipsoid 32/32/16 with 12252 "
                                "markers, kappa 2.7, Re 100, sponge 61, free-slip z, 4 IBM cycles",
                    "cells": cells, "markers": M, "storage": args.storage,
-                   "launch": "graph replay of 2-step graphs" if main_run["graph_ms_per_step"] else "eager",
+                   "launch": (f"graph replay of {graph_steps.per}-step graphs" if main_run["graph_ms_per_step"]
+                              else "eager"),
                    "coupling": "after the lattice kernel" if modes.get(args.storage) else "beside the lattice kernel",
                    "eager_ms_per_step": round(main_run["ms_per_step"], 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",

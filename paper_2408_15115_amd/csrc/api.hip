@@ -714,11 +714,12 @@ static int32_t do_ibm(lbm_ctx *ctx)
     return LBM_OK;
 }
 
-static int32_t do_window(lbm_ctx *ctx)
+// advance set: the next step's body advance rides in the window test's kernel
+static int32_t do_window(lbm_ctx *ctx, int advance = 0)
 {
     if (!ctx->has_body) return LBM_OK;
     HIPCHK(ctx, launch_window(ctx->opt.storage, ctx->pop[ctx->cur], ctx->p, ctx->n, ctx->plan.max_slab, ctx->cur,
-                              ctx->stream),
+                              advance, ctx->stream),
            "window_shift");
     return LBM_OK;
 }
@@ -751,22 +752,24 @@ int32_t window_shift(lbm_ctx *ctx)
     return do_window(ctx);
 }
 
-static int32_t full_step(lbm_ctx *ctx)
+// nsteps whole steps in Table 1 order; between two of them the window test
+// of one and the body advance of the next share a kernel.
+static int32_t run_steps(lbm_ctx *ctx, int nsteps)
 {
-    int32_t r;
-    if ((r = do_body_advance(ctx)) || (r = do_lbm_step(ctx)) || (r = do_ibm(ctx)) || (r = do_window(ctx))) return r;
-    return LBM_OK;
+    if (nsteps <= 0) return LBM_OK;
+    int32_t r = do_body_advance(ctx);
+    for (int s = 0; s < nsteps && r == LBM_OK; s++) {
+        if ((r = do_lbm_step(ctx)) || (r = do_ibm(ctx))) return r;
+        r = do_window(ctx, s + 1 < nsteps);
+    }
+    return r;
 }
 
 int32_t lbm_run(lbm_ctx *ctx, int32_t nsteps)
 {
     if (!ctx || nsteps < 0) return LBM_EINVAL;
     if (ctx->needs_ibm) return fail(ctx, LBM_ESTATE, "lbm_run between lbm_step and ibm_couple");
-    for (int s = 0; s < nsteps; s++) {
-        int32_t r = full_step(ctx);
-        if (r) return r;
-    }
-    return LBM_OK;
+    return run_steps(ctx, nsteps);
 }
 
 static void drop_graph(lbm_ctx *ctx);
@@ -823,8 +826,7 @@ int32_t lbm_graph_capture(lbm_ctx *ctx, int32_t steps)
     drop_graph(ctx);
     const int cur0 = ctx->cur;
     HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    int32_t r = LBM_OK;
-    for (int s = 0; s < steps && r == LBM_OK; s++) r = full_step(ctx);
+    int32_t r = run_steps(ctx, steps);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->stream, &g);
     ctx->cur = cur0;

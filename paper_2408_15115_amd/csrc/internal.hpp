@@ -181,6 +181,9 @@ hipError_t launch_correct(int storage, void *cur, const DevPtrs &p, int n_cases,
 inline bool ibm_fused(int warm_mode, int cycles) { return warm_mode == 0 && cycles <= kHBufs; }
 hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, long long bytes, hipStream_t s);
-hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, hipStream_t s);
+// The window test and reset of Sec. 2.5; with advance set, the test and the
+// next step's body advance run in one kernel (identical results).
+hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, int advance,
+                         hipStream_t s);
 
 }  // namespace turret

@@ -67,10 +67,8 @@ __device__ inline void mv3(const double A[9], const double x[3], double y[3])
 // w(t+1/2) through M^-1 (J/m)^-1 M with the fluid torque plus the body's
 // constant external torque; orientation predictor-corrector.  Then the IBM
 // region origin for the new position.
-__global__ void k_body_advance(DevPtrs p, int n_cases)
+__device__ inline void body_advance_case(const DevPtrs &p, int c)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cases) return;
     const CaseDev &cd = p.cases[c];
     BodyDev &B = p.body[c];
     if (cd.M == 0 || B.err != 0) return;
@@ -102,6 +100,12 @@ __global__ void k_body_advance(DevPtrs p, int n_cases)
     B.steps += 1;
 #pragma unroll
     for (int d = 0; d < 3; d++) B.org[d] = (int)floor(B.r[d] - B.Rb) - 2;
+}
+
+__global__ void k_body_advance(DevPtrs p, int n_cases)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n_cases) body_advance_case(p, c);
 }
 
 // X_k = r + sum_j xb_kj d_j, n_k = sum_j nb_kj d_j, U_k = v + w x (X_k - r).
@@ -1353,10 +1357,8 @@ __global__ void k_correct_mom(DevPtrs p, int resid_slot)
 // Sec. 2.5: below h_end the content and the body move up by dz rows.  With
 // the ring layout the move is the origin change z0 -> z0 - dz; the dz rows
 // that now form the bottom (the former top rows) restart at rest.
-__global__ void k_window_trigger(DevPtrs p, int n_cases)
+__device__ inline void window_trigger_case(const DevPtrs &p, int c)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cases) return;
     const CaseDev &cd = p.cases[c];
     BodyDev &B = p.body[c];
     B.shift_now = 0;
@@ -1387,6 +1389,26 @@ __global__ void k_window_trigger(DevPtrs p, int n_cases)
     rec[30] = B.z0;
     rec[31] = B.err;
     B.logged += 1;
+}
+
+__global__ void k_window_trigger(DevPtrs p, int n_cases)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n_cases) window_trigger_case(p, c);
+}
+
+// The end of one step and the start of the next in one launch, for steps
+// the library sequences itself (lbm_run, graph capture): the window test of
+// step t, then the body advance of step t + 1.  The window reset that
+// follows reads no field the advance writes (it uses the ring origin and
+// the full-precision box origins), so the result is that of the separate
+// kernels, bit for bit.
+__global__ void k_window_advance(DevPtrs p, int n_cases)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cases) return;
+    window_trigger_case(p, c);
+    body_advance_case(p, c);
 }
 
 template <class CD>
@@ -1566,9 +1588,13 @@ hipError_t launch_targets(const DevPtrs &p, int Mtot, float *out, hipStream_t s)
 }
 
 template <class CD>
-static hipError_t window_impl(void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, hipStream_t s)
+static hipError_t window_impl(void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, int advance,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_window_trigger, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
+    if (advance)
+        hipLaunchKernelGGL(k_window_advance, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
+    else
+        hipLaunchKernelGGL(k_window_trigger, dim3((n_cases + 63) / 64), dim3(64), 0, s, p, n_cases);
     if (max_slab > 0) {
         // about 2048 workgroups in all, at least 8 per case
         const int per_case = std::max(8, std::min((max_slab + 255) / 256, 2048 / n_cases));
@@ -1578,13 +1604,14 @@ static hipError_t window_impl(void *cur, const DevPtrs &p, int n_cases, int max_
     return hipGetLastError();
 }
 
-hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, hipStream_t s)
+hipError_t launch_window(int storage, void *cur, const DevPtrs &p, int n_cases, int max_slab, int cur_id, int advance,
+                         hipStream_t s)
 {
     switch (storage) {
-    case ST_MOM: return window_impl<CodecMom>(cur, p, n_cases, max_slab, cur_id, s);
-    case ST_F16: return window_impl<CodecF16>(cur, p, n_cases, max_slab, cur_id, s);
-    case ST_BF16: return window_impl<CodecBF16>(cur, p, n_cases, max_slab, cur_id, s);
-    default: return window_impl<CodecF32>(cur, p, n_cases, max_slab, cur_id, s);
+    case ST_MOM: return window_impl<CodecMom>(cur, p, n_cases, max_slab, cur_id, advance, s);
+    case ST_F16: return window_impl<CodecF16>(cur, p, n_cases, max_slab, cur_id, advance, s);
+    case ST_BF16: return window_impl<CodecBF16>(cur, p, n_cases, max_slab, cur_id, advance, s);
+    default: return window_impl<CodecF32>(cur, p, n_cases, max_slab, cur_id, advance, s);
     }
 }
 

@@ -223,6 +223,37 @@ def test_graph_replay_equals_eager(T, storage):
             assert np.array_equal(sa["F"], sb["F"]) and np.array_equal(sa["r"], sb["r"])
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_library_sequenced_steps_equal_separate_calls(T, storage):
+    """lbm_run and a 6-step graph join the window test of one step and the
+    body advance of the next in one kernel; the four separate calls per step
+    launch them apart.  The runs are identical, bit for bit, through a window
+    shift."""
+    import torch
+    case, body = small_sphere(h_end=19.5 - 1e-6, h_ini=25.5, sponge=5)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        A = T.Solver([case], [body], stream=stream, storage=storage)
+        B = T.Solver([case], [body], stream=stream, storage=storage)
+        C = T.Solver([case], [body], stream=stream, storage=storage)
+        C.graph_capture(6)
+        for _ in range(12):
+            A.body_advance()
+            A.lbm_step()
+            A.ibm_couple()
+            A.window_shift()
+        B.run(12)
+        C.graph_launch()
+        C.graph_launch()
+        stream.synchronize()
+        sa, sb, sc = A.body_state(), B.body_state(), C.body_state()
+        assert sa["shifts"] == 1 and sa["steps"] == 12
+        for k in ("F", "T", "r", "v", "w", "d"):
+            assert np.array_equal(sa[k], sb[k]) and np.array_equal(sa[k], sc[k]), k
+        pa = A.populations()
+        assert np.array_equal(pa, B.populations()) and np.array_equal(pa, C.populations())
+
+
 def test_runs_are_bitwise_deterministic(T):
     case, body = small_sphere()
     outs = []
