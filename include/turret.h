@@ -340,8 +340,9 @@ int32_t lbm_load(lbm_ctx *ctx, const char *path);
 
 /* Element offset of a case's population block inside pop_a / pop_b, the
  * element stride between its direction planes (its cell count rounded up to
- * 128, plus 256), and the device pointer of the current buffer (for tests
- * that read raw storage).  -1 / NULL for a bad case or context. */
+ * 128, plus 1 KB: 256 elements of 4 bytes or 512 of 2), and the device
+ * pointer of the current buffer (for tests that read raw storage).  -1 /
+ * NULL for a bad case or context. */
 int64_t lbm_pop_offset(const lbm_ctx *ctx, int32_t case_id);
 int64_t lbm_plane_stride(const lbm_ctx *ctx, int32_t case_id);
 void *lbm_current_buffer(const lbm_ctx *ctx);

@@ -244,9 +244,11 @@ std::string make_plan(const lbm_case *cases, const lbm_body *bodies, int n, cons
         d.cells = (long long)k.nx * k.ny * k.nz;
         // 256-byte aligned direction planes, 1 KB apart from a multiple of
         // 256 bytes: with the planes of a case starting at staggered offsets
-        // the lattice kernel's 27-plane pull ran 1.4 % faster (FP32,
-        // 256 x 256 x 768, where the unpadded stride is a multiple of 64 MiB)
-        d.plane = (d.cells + 127) / 128 * 128 + 256;
+        // the lattice kernel's 27-plane pull ran 1.4 % faster at 256 x 256 x 768
+        // (where the unpadded stride is a multiple of 64 MiB), in FP32 with
+        // 256 elements of pad and in FP16 with 512; other pads from 128 to 768
+        // elements were slower
+        d.plane = (d.cells + 127) / 128 * 128 + 1024 / eb;
         d.pop_off = pop;
         pop += P.planes * d.plane;
         d.M = b ? std::max(0, b->n_markers) : 0;
@@ -680,11 +682,18 @@ static int32_t do_lbm_step(lbm_ctx *ctx)
                                      (int)ctx->plan.tiles.size(), ctx->opt.block, ctx->opt.schedule,
                                      ctx->opt.persist_wgs, ctx->opt.collision, ctx->stream),
                "lbm_step");
-    if (ctx->plan.max_box > 0)
+    if (ctx->plan.max_box > 0) {
+        // the lattice kernel leaves the box cells to this step, which reads
+        // only the buffer the lattice kernel reads: with the coupling beside
+        // the lattice kernel it runs on the coupling's stream too, ahead of
+        // the coupling (joined before the forced correction)
+        const bool beside = ctx->has_body && !ctx->opt.serial_ibm;
+        if (beside) HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->fork, 0), "side stream waits for the fork event");
         HIPCHK(ctx,
                launch_fine_step(ctx->opt.storage, ctx->pop[src], ctx->pop[dst], ctx->p, src, dst, ctx->n,
-                                ctx->plan.max_box, ctx->opt.collision, ctx->stream),
+                                ctx->plan.max_box, ctx->opt.collision, beside ? ctx->side : ctx->stream),
                "full-precision box");
+    }
     ctx->cur = dst;
     ctx->needs_ibm = ctx->has_body;
     return LBM_OK;

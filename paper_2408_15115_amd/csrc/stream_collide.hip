@@ -2,6 +2,9 @@
 // collision kernel of the lattice Boltzmann step (arXiv 2408.15115, Sec. 2.1
 // and App. A), one thread per cell over SoA storage, its launch schedules,
 // and the plain streaming copy that calibrates HBM bandwidth and counters.
+#include <type_traits>
+
+#include "fine.hpp"
 #include "internal.hpp"
 #include "lattice.hpp"
 #include "pull.hpp"
@@ -39,6 +42,22 @@ __device__ __forceinline__ void stream_collide_tile(const typename CD::T *__rest
     const int t2 = cell / nx;
     const int y = t2 % ny;
     const int z = t2 / ny;
+    // FP16 / BF16 with the full-precision box: the box step writes the box's
+    // cells (it may run beside this kernel), so their stores are skipped
+    // here (the cells are still collided for the stability guard).  The box
+    // of this step starts one cell before the particle region, whose origin
+    // the body advance has set.
+    bool in_box = false;
+    if constexpr (!std::is_same<CD, CodecF32>::value) {
+        if (cd.LB[0] > 0) {
+            const BodyDev &Bb = body[tl.c];
+            int kx = x - wrap_mod(Bb.org[0] - 1, nx), ky = y - wrap_mod(Bb.org[1] - 1, ny);
+            kx += kx < 0 ? nx : 0;
+            ky += ky < 0 ? ny : 0;
+            const int kz = z - (Bb.org[2] - 1);
+            in_box = kx < cd.LB[0] && ky < cd.LB[1] && kz >= 0 && kz < cd.LB[2];
+        }
+    }
     float g[Q];
     pull<CD>(src + cd.pop_off, cd.plane, nx, ny, nz, z0, cd.bc_lo, cd.bc_hi, cd.uw_lo, cd.uw_hi, x, y, z, g);
     const Macro M = macro(raw_moments(g));
@@ -58,6 +77,7 @@ __device__ __forceinline__ void stream_collide_tile(const typename CD::T *__rest
         post_collision_coeffs(M, M.u, om, A);
         hermite_to_populations(A, out);
     }
+    if (in_box) return;
     int zc = z + z0;
     if (zc >= nz) zc -= nz;
     store_all<CD>(dst + cd.pop_off, cd.plane, (zc * ny + y) * nx + x, out);

@@ -47,10 +47,10 @@ def test_required_bytes_of_the_sphere_case():
     from paper_2408_15115_amd import turret as T
     case, body = W.case_sphere48()
     a, b, aux = T.required_bytes([case], [body])
-    plane = 48 ** 3 + 256          # direction planes staggered by 1 KB
+    plane = 48 ** 3 + 256          # direction planes staggered by 1 KB (256 four-byte elements)
     assert a == b == 27 * plane * 4
     a16, _, _ = T.required_bytes([case], [body], storage="f16")
-    assert a16 == a // 2
+    assert a16 == 27 * (48 ** 3 + 512) * 2   # the 1 KB stagger is 512 two-byte elements
     assert aux > 400 * 8 * 3
 
 
