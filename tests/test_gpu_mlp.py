@@ -225,13 +225,20 @@ def test_learned_warm_start_gains_over_plain_start(T):
         S_g.set_warm_start(T.LBM_WARM_MLP, net, 3)
         for c in range(len(cases)):
             S_g.set_ibm_gate(c, float(gates[c]))
-        S_g.run(80)
+        Fz_g = []
+        for n in range(80):
+            S_g.run(1)
+            if n >= 40:
+                Fz_g.append([S_g.body_state(c)["F"][2] for c in range(len(cases))])
         st = [S_g.ibm_stats(c) for c in range(len(cases))]
-        Fz = np.array([S_g.body_state(c)["F"][2] for c in range(len(cases))])
         acc, rej = sum(x["accepts"] for x in st), sum(x["rejects"] for x in st)
-        gated = {"accepts": acc, "rejects": rej,
+        # the drag averaged over steps 41..80 against the plain run's, over the
+        # body's weight kappa V g
+        weight = np.array([b["kappa"] * b["volume"] * c["gravity"] for c, b in zip(cases, bodies)])
+        mean_dev = np.abs(np.mean(Fz_g, axis=0) - plain["Fz"][20:].mean(0)) / weight
+        gated = {"accepts": acc, "rejects": rej, "acceptance": acc / max(1, acc + rej),
                  "mean_cycles": sum(x["warm_cycles_accepted"] for x in st) / max(1, acc),
-                 "drag_dev": float(np.max(np.abs(Fz - plain["Fz"][-1]) / np.abs(plain["Fz"][-1])))}
+                 "mean_drag_dev_over_weight": [float(v) for v in mean_dev]}
     finally:
         if S_g is not None:
             S_g.close()
@@ -250,6 +257,13 @@ def test_learned_warm_start_gains_over_plain_start(T):
     # control, the previous step's h (a zero network)
     assert r(mlp, 0) < r(plain, 0)
     assert r(mlp, 0) < r(prev, 0)
+    # the gated start (the plain 4-cycle residual of each case as its gate,
+    # which replaces the fixed 1e-6 threshold the plain method itself stays
+    # above) keeps the time-averaged drag within 0.5 % of the weight of the
+    # plain run's on these coarse bodies (R 3-4 cells; measured 0.07-0.36 %;
+    # on the 64-case batch the median is 1.3e-4 of the weight)
+    assert gated["acceptance"] > 0.9
+    assert max(gated["mean_drag_dev_over_weight"]) < 5e-3
     # the diagnostic runs are the plain run
     assert np.array_equal(mlp["Fz"], plain["Fz"]) and np.array_equal(prev["Fz"], plain["Fz"])
     assert np.array_equal(zero_run["Fz"], plain["Fz"])
