@@ -18,6 +18,10 @@ ARCH = "gfx950"
 
 HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source additions.  The network's inference keeps its matrix-core results
+# in ordinary VGPRs, where the SiLU that follows reads them without a copy out
+# of the accumulation registers.
+SOURCE_FLAGS = {"mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
@@ -27,7 +31,7 @@ def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
     flags = HIP_FLAGS + list(extra_flags or [])
     for src in SOURCES:
         obj = os.path.join(build_dir, src.replace(".hip", ".o"))
-        cmd = ["hipcc", *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", *flags, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

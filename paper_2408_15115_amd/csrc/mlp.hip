@@ -94,17 +94,79 @@ __device__ __forceinline__ half4_t load_half4(const _Float16 *th, int at)
     return *reinterpret_cast<const half4_t *>(th + at);
 }
 
-__device__ inline void mlp_load_regs(const _Float16 *th, MlpRegs &R)
+// The FP16 parameters, staged once per 256-thread workgroup in LDS with
+// 16-byte copies (the parameter buffer extends to a 256-byte boundary, past
+// the rounding up to 8 values).  Every load of a thread is issued before the
+// first store, so the staging waits for one memory latency, not one per
+// round of copies; the plain copy is padded to whole rounds (the padding
+// holds repeats of the last vector) so that no store is conditional.
+//
+// W1 and W2 are also laid out in LDS as the register image of their A
+// operands: slot (matrix, mc, kc) holds, for lanes l = 0..63 in a row, the 4
+// values W[16 mc + l % 16][16 kc + 4 (l / 16) + 0..3], so that a wave takes
+// each operand with one conflict-free 8-byte read per lane.  (Read straight
+// from the row-major copy, the 16 rows of a W2 operand lie 128 bytes apart
+// and fall into the same LDS banks.)  W3 and the biases are read from the
+// plain copy, where lanes that share an address get it broadcast.
+constexpr int kMlpParams8 = (kMlpParams + 7) / 8 * 8;
+constexpr int kStageVecs = kMlpParams8 / 8;
+constexpr int kStageRounds = (kStageVecs + 255) / 256;
+constexpr int kStageHalves = kStageRounds * 256 * 8;
+constexpr int kImgW1 = 0;                              // slot of (mc, kc): kImgW1 + mc kInSteps + kc
+constexpr int kImgW2 = kHChunks * kInSteps;            // slot of (mc, kc): kImgW2 + mc kHChunks + kc
+constexpr int kImgSlots = kImgW2 + kHChunks * kHChunks;
+static_assert(kOffW2 % 8 == 0 && kOffB1 % 8 == 0 && kOffB2 % 8 == 0,
+              "16-byte parameter vectors never straddle W1 / W2 and the next block");
+
+struct MlpLds {
+    _Float16 raw[kStageHalves];
+    half4_t img[kImgSlots * 64];
+};
+
+// Places W[o][c..c+3] (c a multiple of 4) of a matrix with `steps` 16-wide
+// column steps into its operand slot.
+__device__ __forceinline__ void img_put(half4_t *img, int base, int steps, int o, int c, half4_t v)
 {
+    img[(base + (o >> 4) * steps + (c >> 4)) * 64 + (o & 15) + 16 * ((c & 15) >> 2)] = v;
+}
+
+__device__ inline void mlp_stage(const _Float16 *__restrict__ th, MlpLds &L)
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(th);
+    uint4 *dst = reinterpret_cast<uint4 *>(L.raw);
+    uint4 v[kStageRounds];
+#pragma unroll
+    for (int j = 0; j < kStageRounds; j++) v[j] = src[std::min((int)threadIdx.x + 256 * j, kStageVecs - 1)];
+#pragma unroll
+    for (int j = 0; j < kStageRounds; j++) {
+        const int i = (int)threadIdx.x + 256 * j, h = 8 * i;
+        dst[i] = v[j];
+        const half4_t lo = __builtin_bit_cast(half4_t, make_uint2(v[j].x, v[j].y)),
+                      hi = __builtin_bit_cast(half4_t, make_uint2(v[j].z, v[j].w));
+        if (h < kOffB1) {
+            const int o = (h - kOffW1) / kMlpIn, c = (h - kOffW1) % kMlpIn;
+            img_put(L.img, kImgW1, kInSteps, o, c, lo);
+            img_put(L.img, kImgW1, kInSteps, o, c + 4, hi);
+        } else if (h >= kOffW2 && h < kOffB2) {
+            const int o = (h - kOffW2) / kMlpH, c = (h - kOffW2) % kMlpH;
+            img_put(L.img, kImgW2, kHChunks, o, c, lo);
+            img_put(L.img, kImgW2, kHChunks, o, c + 4, hi);
+        }
+    }
+    __syncthreads();
+}
+
+__device__ inline void mlp_load_regs(const MlpLds &L, MlpRegs &R)
+{
+    const _Float16 *th = L.raw;
     const int l = threadIdx.x & 63, r = l & 15, kq = (l >> 4) * 4;
     const _Float16 zero = (_Float16)0.0f;
 #pragma unroll
     for (int mc = 0; mc < kHChunks; mc++) {
-        const int o = 16 * mc + r;   // output neuron of this lane's A rows
 #pragma unroll
-        for (int kc = 0; kc < kInSteps; kc++) R.w1[mc][kc] = load_half4(th, kOffW1 + o * kMlpIn + 16 * kc + kq);
+        for (int kc = 0; kc < kInSteps; kc++) R.w1[mc][kc] = L.img[(kImgW1 + mc * kInSteps + kc) * 64 + l];
 #pragma unroll
-        for (int kc = 0; kc < kHChunks; kc++) R.w2[mc][kc] = load_half4(th, kOffW2 + o * kMlpH + 16 * kc + kq);
+        for (int kc = 0; kc < kHChunks; kc++) R.w2[mc][kc] = L.img[(kImgW2 + mc * kHChunks + kc) * 64 + l];
         // biases of the D rows this lane holds
         const half4_t b1 = load_half4(th, kOffB1 + 16 * mc + kq), b2 = load_half4(th, kOffB2 + 16 * mc + kq);
 #pragma unroll
@@ -123,54 +185,38 @@ __device__ inline void mlp_load_regs(const _Float16 *th, MlpRegs &R)
     for (int e = 0; e < 4; e++) R.b3[e] = kq + e < kMlpOut ? (float)th[kOffB3 + kq + e] : 0.0f;
 }
 
-// The FP16 parameters, staged once per workgroup in LDS with 16-byte copies
-// (the parameter buffer extends to a 256-byte boundary, past the rounding up
-// to 8 values); the waves then take their operands from there.
-constexpr int kMlpParams8 = (kMlpParams + 7) / 8 * 8;
-__device__ inline void mlp_stage(const _Float16 *__restrict__ th, _Float16 *w)
-{
-    for (int i = 8 * (int)threadIdx.x; i < kMlpParams8; i += 8 * (int)blockDim.x)
-        *reinterpret_cast<uint4 *>(w + i) = *reinterpret_cast<const uint4 *>(th + i);
-    __syncthreads();
-}
-
 __device__ __forceinline__ float4_t mfma16(half4_t a, half4_t b, float4_t c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
 
 // One tile of 16 samples: x holds this lane's B operand of layer 1; the
-// result holds, in lanes 0..15, outputs 0..kMlpOut-1 of sample l.
+// result holds, in lanes 0..15, outputs 0..kMlpOut-1 of sample l.  The bias
+// is the accumulator's initial value, so the matrix cores add it.  SiLU is
+// the tile's main cost: two quarter-rate transcendentals (exp, reciprocal)
+// per hidden value.
 __device__ inline float4_t mlp_tile(const MlpRegs &R, const half4_t x[kInSteps])
 {
     half4_t a1[kHChunks], a2[kHChunks];
 #pragma unroll
     for (int mc = 0; mc < kHChunks; mc++) {
-        float4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+        float4_t d = {R.b1[mc][0], R.b1[mc][1], R.b1[mc][2], R.b1[mc][3]};
 #pragma unroll
         for (int kc = 0; kc < kInSteps; kc++) d = mfma16(R.w1[mc][kc], x[kc], d);
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const float z = d[e] + R.b1[mc][e];
-            a1[mc][e] = (_Float16)(z * sigmoid_fast(z));
-        }
+        for (int e = 0; e < 4; e++) a1[mc][e] = (_Float16)(d[e] * sigmoid_fast(d[e]));
     }
 #pragma unroll
     for (int mc = 0; mc < kHChunks; mc++) {
-        float4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+        float4_t d = {R.b2[mc][0], R.b2[mc][1], R.b2[mc][2], R.b2[mc][3]};
 #pragma unroll
         for (int kc = 0; kc < kHChunks; kc++) d = mfma16(R.w2[mc][kc], a1[kc], d);
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const float z = d[e] + R.b2[mc][e];
-            a2[mc][e] = (_Float16)(z * sigmoid_fast(z));
-        }
+        for (int e = 0; e < 4; e++) a2[mc][e] = (_Float16)(d[e] * sigmoid_fast(d[e]));
     }
-    float4_t y = {0.0f, 0.0f, 0.0f, 0.0f};
+    float4_t y = {R.b3[0], R.b3[1], R.b3[2], R.b3[3]};
 #pragma unroll
     for (int kc = 0; kc < kHChunks; kc++) y = mfma16(R.w3[kc], a2[kc], y);
-#pragma unroll
-    for (int e = 0; e < 4; e++) y[e] += R.b3[e];
     return y;
 }
 
@@ -206,29 +252,52 @@ __device__ inline void mlp_convert(const MlpRaw &r, half4_t x[kInSteps])
     }
 }
 
-// Inference on caller arrays: X (n x kMlpIn) -> Y (n x 3).  Every wave strides
-// over 16-sample tiles; the loop bound is the same for the whole wave.
-__global__ void __launch_bounds__(256) k_mlp_forward(const _Float16 *__restrict__ th16, const float *__restrict__ X,
-                                                     int n, float *__restrict__ Y)
+// Tiles a wave takes per round.  Their features are loaded together, those
+// of the first round before the weights are staged (both latencies overlap),
+// those of the next round while the wave works on the current one.
+constexpr int kMlpRound = 2;
+
+// The inference loop shared by the two kernels: every wave strides over
+// 16-sample tiles (the loop bounds are the same for the whole wave); epi(s,
+// x, R) finishes sample s of this lane from its layer-1 operand x.
+template <class Epi>
+__device__ inline void mlp_stream(const _Float16 *__restrict__ th16, MlpLds &wsh, const float *__restrict__ X,
+                                  int n, Epi &&epi)
 {
-    __shared__ __align__(16) _Float16 wsh[kMlpParams8];
+    const int l = threadIdx.x & 63;
+    const int wave = (int)(blockIdx.x * 4 + (threadIdx.x >> 6)), nwaves = (int)(gridDim.x * 4);   // 256 threads
+    const int stride = 16 * nwaves;
+    MlpRaw buf[kMlpRound];
+#pragma unroll
+    for (int j = 0; j < kMlpRound; j++) buf[j] = mlp_load(X, 16 * wave + j * stride + (l & 15), n);
     mlp_stage(th16, wsh);
     MlpRegs R;
     mlp_load_regs(wsh, R);
+    for (int base = 16 * wave; base < n; base += kMlpRound * stride) {
+#pragma unroll
+        for (int j = 0; j < kMlpRound; j++) {
+            const int s0 = base + j * stride;
+            if (s0 >= n) break;
+            half4_t x[kInSteps];
+            mlp_convert(buf[j], x);
+            buf[j] = mlp_load(X, s0 + kMlpRound * stride + (l & 15), n);   // the next round's tile j
+            epi(s0 + (l & 15), x, R);
+        }
+    }
+}
+
+// Inference on caller arrays: X (n x kMlpIn) -> Y (n x 3).
+__global__ void __launch_bounds__(256) k_mlp_forward(const _Float16 *__restrict__ th16, const float *__restrict__ X,
+                                                     int n, float *__restrict__ Y)
+{
+    __shared__ __align__(16) MlpLds wsh;
     const int l = threadIdx.x & 63;
-    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), nwaves = (int)((gridDim.x * blockDim.x) >> 6);
-    const int stride = 16 * nwaves;
-    MlpRaw next = mlp_load(X, 16 * wave + (l & 15), n);
-    for (int s0 = 16 * wave; s0 < n; s0 += stride) {
-        const int s = s0 + (l & 15);
-        half4_t x[kInSteps];
-        mlp_convert(next, x);
-        next = mlp_load(X, s + stride, n);   // the next tile's features, in flight during this one
+    mlp_stream(th16, wsh, X, n, [&](int s, const half4_t *x, const MlpRegs &R) {
         const float4_t y = mlp_tile(R, x);
         if (l < 16 && s < n)
 #pragma unroll
             for (int j = 0; j < kMlpOut; j++) Y[(long long)s * kMlpOut + j] = y[j];
-    }
+    });
 }
 
 // Warm start inside the IBM coupling: the network predicts, over the
@@ -238,19 +307,9 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const _Float16 *__restrict_
 // starts from h(t-1), the control start.
 __global__ void __launch_bounds__(256) k_mlp_warm_start(const _Float16 *__restrict__ th16, DevPtrs p, int Mtot)
 {
-    __shared__ __align__(16) _Float16 wsh[kMlpParams8];
-    mlp_stage(th16, wsh);
-    MlpRegs R;
-    mlp_load_regs(wsh, R);
+    __shared__ __align__(16) MlpLds wsh;
     const int l = threadIdx.x & 63;
-    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), nwaves = (int)((gridDim.x * blockDim.x) >> 6);
-    const int stride = 16 * nwaves;
-    MlpRaw next = mlp_load(p.feat, 16 * wave + (l & 15), Mtot);
-    for (int s0 = 16 * wave; s0 < Mtot; s0 += stride) {
-        const int k = s0 + (l & 15);
-        half4_t x[kInSteps];
-        mlp_convert(next, x);
-        next = mlp_load(p.feat, k + stride, Mtot);   // the next tile's features, in flight during this one
+    mlp_stream(th16, wsh, p.feat, Mtot, [&](int k, const half4_t *x, const MlpRegs &R) {
         // the epilogue's operands, loaded before the matrix work
         bool live = false;
         float hp[3] = {0.0f, 0.0f, 0.0f};
@@ -268,7 +327,7 @@ __global__ void __launch_bounds__(256) k_mlp_warm_start(const _Float16 *__restri
                 p.hk[3 * k + a] = 0.0;
                 p.dh[3 * k + a] = ((double)hp[a] + (double)y[a]) * hs;
             }
-    }
+    });
 }
 
 // Training, pass 1: forward of every sample, keeping the activations and
@@ -417,9 +476,8 @@ __global__ void k_mlp_round(const float *__restrict__ th32, _Float16 *__restrict
 // ------------------------------------------------------------ launchers
 // Workgroups of 4 waves for the matrix-core inference: one wave per 16-sample
 // tile up to 2048 waves (2 per SIMD), which then stride.  Over the 161,818
-// markers of the 64-case batch 2048 waves took 12.5 us, 1024 and 4096 waves
-// 13.2 and 12.8 us (weights staged in LDS; 16.6 us with every wave loading
-// them from memory at 4096 waves).
+// markers of the 64-case batch this takes 9.1 us; 1024 and 4096 waves were
+// slower, and 8192 waves much slower (each workgroup stages the weights).
 static dim3 infer_grid(int n)
 {
     const int tiles = (n + 15) / 16;

@@ -408,9 +408,11 @@ class MLP:
         self._chk("mlp_get_params", mlp_get_params(self._m, a.ctypes.data_as(C.POINTER(C.c_float))))
         return a
 
-    def forward(self, X):
+    def forward(self, X, out=None):
         X = X.contiguous()
-        Y = self.torch.empty((X.shape[0], 3), dtype=self.torch.float32, device="cuda")
+        Y = out if out is not None else self.torch.empty((X.shape[0], 3), dtype=self.torch.float32, device="cuda")
+        if Y.shape != (X.shape[0], 3) or Y.dtype != self.torch.float32 or not Y.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor of shape (n, 3)")
         self._chk("mlp_forward", mlp_forward(self._m, C.c_void_p(X.data_ptr()), X.shape[0], C.c_void_p(Y.data_ptr())))
         return Y
 
