@@ -25,7 +25,7 @@ namespace turret {
 
 namespace mom {
 #ifndef TURRET_MOM_TILE
-#define TURRET_MOM_TILE 32, 5, 32, 256
+#define TURRET_MOM_TILE 32, 13, 32, 512
 #endif
 // x, y extent of a column tile; z planes per chunk; threads per workgroup
 constexpr int kTile[4] = {TURRET_MOM_TILE};
