@@ -71,35 +71,63 @@ __device__ inline void body_advance_case(const DevPtrs &p, int c)
 {
     const CaseDev &cd = p.cases[c];
     BodyDev &B = p.body[c];
-    if (cd.M == 0 || B.err != 0) return;
-    const double kv = B.kappa * B.vol;
-    const double a[3] = {B.F[0] / kv, B.F[1] / kv, B.F[2] / kv - B.gravity};
+    // every field first, in one round of loads (no short-circuit between the
+    // two tests, so both loads issue together), then the arithmetic, then the
+    // stores
+    const int M = cd.M, err = B.err;
+    if ((M == 0) | (err != 0)) return;
+    const double kappa = B.kappa, vol = B.vol, grav = B.gravity, Rb = B.Rb;
+    double F[3], T[3], Te[3], v[3], r[3], w[3], d[9], J[9];
 #pragma unroll
-    for (int d = 0; d < 3; d++) {
-        B.v[d] += a[d];
-        B.r[d] += B.v[d];
+    for (int k = 0; k < 3; k++) {
+        F[k] = B.F[k];
+        T[k] = B.T[k];
+        Te[k] = B.Text[k];
+        v[k] = B.v[k];
+        r[k] = B.r[k];
+        w[k] = B.w[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        d[k] = B.d[k];
+        J[k] = B.Jm_inv[k];
+    }
+    const int steps = B.steps;
+    const double kv = kappa * vol;
+    const double a[3] = {F[0] / kv, F[1] / kv, F[2] / kv - grav};
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        v[k] += a[k];
+        r[k] += v[k];
     }
     double Minv[9], t1[3], t2[3], t3[3];
-    inverse3(B.d, Minv);
-    const double Ttot[3] = {B.T[0] + B.Text[0], B.T[1] + B.Text[1], B.T[2] + B.Text[2]};
-    mv3(B.d, Ttot, t1);
-    mv3(B.Jm_inv, t1, t2);
+    inverse3(d, Minv);
+    const double Ttot[3] = {T[0] + Te[0], T[1] + Te[1], T[2] + Te[2]};
+    mv3(d, Ttot, t1);
+    mv3(J, t1, t2);
     mv3(Minv, t2, t3);
 #pragma unroll
-    for (int d = 0; d < 3; d++) B.w[d] += t3[d] / kv;
+    for (int k = 0; k < 3; k++) w[k] += t3[k] / kv;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        double di[3] = {B.d[3 * i], B.d[3 * i + 1], B.d[3 * i + 2]}, wd[3], mid[3], wm[3];
-        cross3(B.w, di, wd);
+        double di[3] = {d[3 * i], d[3 * i + 1], d[3 * i + 2]}, wd[3], mid[3], wm[3];
+        cross3(w, di, wd);
 #pragma unroll
-        for (int d = 0; d < 3; d++) mid[d] = 0.5 * (di[d] + (di[d] + wd[d]));
-        cross3(B.w, mid, wm);
+        for (int k = 0; k < 3; k++) mid[k] = 0.5 * (di[k] + (di[k] + wd[k]));
+        cross3(w, mid, wm);
 #pragma unroll
-        for (int d = 0; d < 3; d++) B.d[3 * i + d] = di[d] + wm[d];
+        for (int k = 0; k < 3; k++) d[3 * i + k] = di[k] + wm[k];
     }
-    B.steps += 1;
 #pragma unroll
-    for (int d = 0; d < 3; d++) B.org[d] = (int)floor(B.r[d] - B.Rb) - 2;
+    for (int k = 0; k < 3; k++) {
+        B.v[k] = v[k];
+        B.r[k] = r[k];
+        B.w[k] = w[k];
+        B.org[k] = (int)floor(r[k] - Rb) - 2;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) B.d[k] = d[k];
+    B.steps = steps + 1;
 }
 
 __global__ void k_body_advance(DevPtrs p, int n_cases)
@@ -1357,58 +1385,82 @@ __global__ void k_correct_mom(DevPtrs p, int resid_slot)
 // Sec. 2.5: below h_end the content and the body move up by dz rows.  With
 // the ring layout the move is the origin change z0 -> z0 - dz; the dz rows
 // that now form the bottom (the former top rows) restart at rest.
-__device__ inline void window_trigger_case(const DevPtrs &p, int c)
+// The step's record for the case's log ring, taken after the window test.
+struct StepRecord {
+    double v[kLogFields];
+};
+
+__device__ inline StepRecord window_trigger_case(const DevPtrs &p, int c)
 {
     const CaseDev &cd = p.cases[c];
     BodyDev &B = p.body[c];
+    // the test's operands in one round of loads (no short-circuit)
+    const int M = cd.M, dz = cd.dz, nz = cd.nz, err = B.err;
+    const double h_end = cd.h_end, rz = B.r[2];
+    const bool shift = (M > 0) & (err == 0) & (dz > 0) & (h_end > 0.0) & (rz < h_end);
     B.shift_now = 0;
-    if (cd.M > 0 && B.err == 0 && cd.dz > 0 && cd.h_end > 0.0 && B.r[2] < cd.h_end) {
-        B.r[2] += (double)cd.dz;
-        B.z0 = wrapi(B.z0 - cd.dz, cd.nz);
-        B.fo[0][2] += cd.dz;   // the full-precision boxes move with the content
-        B.fo[1][2] += cd.dz;
+    if (shift) {
+        B.r[2] = rz + (double)dz;
+        B.z0 = wrapi(B.z0 - dz, nz);
+        B.fo[0][2] += dz;   // the full-precision boxes move with the content
+        B.fo[1][2] += dz;
         B.shift_now = 1;
         B.shifts += 1;
     }
-    // the step's record in the case's log ring
-    double *rec = p.log + ((long long)c * kLogCap + B.logged % kLogCap) * kLogFields;
+    StepRecord rec;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        rec[a] = B.r[a];
-        rec[12 + a] = B.v[a];
-        rec[15 + a] = B.w[a];
-        rec[18 + a] = B.F[a];
-        rec[21 + a] = B.T[a];
-        rec[24 + a] = B.Fp[a];
+        rec.v[a] = B.r[a];
+        rec.v[12 + a] = B.v[a];
+        rec.v[15 + a] = B.w[a];
+        rec.v[18 + a] = B.F[a];
+        rec.v[21 + a] = B.T[a];
+        rec.v[24 + a] = B.Fp[a];
     }
 #pragma unroll
-    for (int a = 0; a < 9; a++) rec[3 + a] = B.d[a];
-    rec[27] = B.resid;
-    rec[28] = B.steps;
-    rec[29] = B.shifts;
-    rec[30] = B.z0;
-    rec[31] = B.err;
-    B.logged += 1;
+    for (int a = 0; a < 9; a++) rec.v[3 + a] = B.d[a];
+    rec.v[27] = B.resid;
+    rec.v[28] = B.steps;
+    rec.v[29] = B.shifts;
+    rec.v[30] = B.z0;
+    rec.v[31] = B.err;
+    return rec;
+}
+
+// Appends a record to the case's log ring.  Written last in its kernel: the
+// stores go through a plain double pointer, which the compiler must assume
+// may alias the body state, so no body field is read after them.
+__device__ inline void log_append(const DevPtrs &p, int c, const StepRecord &rec)
+{
+    BodyDev &B = p.body[c];
+    const unsigned int n = B.logged;
+    B.logged = n + 1;
+    double *dst = p.log + ((long long)c * kLogCap + n % kLogCap) * kLogFields;
+#pragma unroll
+    for (int k = 0; k < kLogFields; k++) dst[k] = rec.v[k];
 }
 
 __global__ void k_window_trigger(DevPtrs p, int n_cases)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < n_cases) window_trigger_case(p, c);
+    if (c >= n_cases) return;
+    const StepRecord rec = window_trigger_case(p, c);
+    log_append(p, c, rec);
 }
 
 // The end of one step and the start of the next in one launch, for steps
 // the library sequences itself (lbm_run, graph capture): the window test of
-// step t, then the body advance of step t + 1.  The window reset that
-// follows reads no field the advance writes (it uses the ring origin and
-// the full-precision box origins), so the result is that of the separate
-// kernels, bit for bit.
+// step t, then the body advance of step t + 1, then step t's record.  The
+// window reset that follows reads no field the advance writes (it uses the
+// ring origin and the full-precision box origins), so the result is that of
+// the separate kernels, bit for bit.
 __global__ void k_window_advance(DevPtrs p, int n_cases)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cases) return;
-    window_trigger_case(p, c);
+    const StepRecord rec = window_trigger_case(p, c);
     body_advance_case(p, c);
+    log_append(p, c, rec);
 }
 
 template <class CD>
