@@ -149,8 +149,11 @@ typedef struct {
  *               2 = persistent: persist_wgs workgroups stride over the table;
  *               3 = persistent work queue: persist_wgs workgroups take tiles
  *                   from a device counter (dynamic balance across uneven
- *                   cases; the counter is reset by a kernel, graph-safe)
- *   persist_wgs workgroups of schedules 2 and 3 (0 = 2048)
+ *                   cases; the counter is reset by a kernel, graph-safe);
+ *                   the table is split in 8 contiguous segments, one per XCD
+ *               4 = as 3, with the 8 segments interleaved chunk by chunk,
+ *                   so that the XCDs work through the table side by side
+ *   persist_wgs workgroups of schedules 2, 3 and 4 (0 = 2048)
  *   tile_order  0 = case after case; 1 = tiles of all cases interleaved
  *               round-robin; 2 = largest case first
  *   ibm_diag    1 = keep the residual max |U_k - I[u* + H](X_k)| after every

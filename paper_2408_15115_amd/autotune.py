@@ -24,6 +24,8 @@ def default_candidates(n_cu=256):
     for wgs in (4 * n_cu, 8 * n_cu, 16 * n_cu):
         c.append(dict(block=256, schedule=2, persist_wgs=wgs, tile_order=1))
         c.append(dict(block=256, schedule=3, persist_wgs=wgs, tile_order=2))
+        c.append(dict(block=256, schedule=4, persist_wgs=wgs, tile_order=2))
+        c.append(dict(block=256, schedule=4, persist_wgs=wgs, tile_order=0))
     c.append(dict(block=128, schedule=3, persist_wgs=16 * n_cu, tile_order=2))
     return c
 

@@ -99,7 +99,7 @@ std::string check_options(const lbm_options *o)
     if (o->storage < LBM_F32 || o->storage > LBM_MOM) return "unknown storage";
     if (o->ibm_cycles < 0 || o->ibm_cycles > 16) return "ibm_cycles must be 1..16 (0 = default 4)";
     if (o->block && o->block != 64 && o->block != 128 && o->block != 256) return "block must be 64, 128 or 256";
-    if (o->schedule < 0 || o->schedule > 3) return "schedule must be 0..3";
+    if (o->schedule < 0 || o->schedule > 4) return "schedule must be 0..4";
     if (o->persist_wgs < 0 || o->persist_wgs > (1 << 20)) return "persist_wgs must be 0..2^20";
     if (o->tile_order < 0 || o->tile_order > 2) return "tile_order must be 0, 1 or 2";
     if (o->ibm_diag < 0 || o->ibm_diag > 1) return "ibm_diag must be 0 or 1";

@@ -31,11 +31,12 @@ __device__ __forceinline__ void store_all(typename CD::T *__restrict__ dst, long
 // comparison, f0 + (1 - 1/tau)(f - f0) with the raw off-equilibrium.
 template <class CD, int COLL>
 __device__ __forceinline__ void stream_collide_tile(const typename CD::T *__restrict__ src, typename CD::T *__restrict__ dst,
-                                                    const CaseDev *__restrict__ cases, BodyDev *__restrict__ body, Tile tl)
+                                                    const CaseDev *__restrict__ cases, BodyDev *__restrict__ body, Tile tl,
+                                                    int off)
 {
     const CaseDev &cd = cases[tl.c];
     const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
-    const int cell = tl.first + (int)threadIdx.x;
+    const int cell = tl.first + off;   // off: this thread's cell in the tile
     if (body[tl.c].err != 0 || cell >= (int)cd.cells) return;
     const int z0 = body[tl.c].z0;
     const int x = cell % nx;
@@ -91,8 +92,15 @@ __device__ __forceinline__ void stream_collide_tile(const typename CD::T *__rest
 // (a single device-wide counter serializes every grab across the XCDs);
 // workgroup b starts on segment b mod 8, takes kQueueChunk tiles per grab and
 // moves on to the other segments when its own is exhausted.  Counters only
-// grow, so every workgroup leaves the loop.  One instantiation per schedule
-// keeps the register allocation of the plain schedules free of the loops.
+// grow, so every workgroup leaves the loop.  4: the same 8 counters, but
+// interleaved: counter g hands out chunks g, g + 8, g + 16, ... of the whole
+// table, so the 8 XCDs advance through the table side by side and only the
+// cases around one point of the table stream at a time (with contiguous
+// segments each XCD streams a case of its own, 8 times the plane streams).
+// (A queue of single wavefronts, without the barriers, was slower: four
+// times the grabs on the same counters.)
+// One instantiation per schedule keeps the register allocation of the plain
+// schedules free of the loops.
 constexpr int kQueueChunk = 4;
 
 template <class CD, int SCHED, int COLL = 0>
@@ -115,15 +123,30 @@ __global__ void __launch_bounds__(256) k_stream_collide(const typename CD::T *__
                 __syncthreads();
                 if (t0 >= hi) break;
                 const int t1 = min(t0 + kQueueChunk, hi);
-                for (int t = t0; t < t1; t++) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t]);
+                for (int t = t0; t < t1; t++) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t], (int)threadIdx.x);
+            }
+        }
+    } else if constexpr (SCHED == 4) {
+        __shared__ int s_j;
+        const int nchunks = (ntiles + kQueueChunk - 1) / kQueueChunk;
+        for (int k = 0; k < 8; k++) {
+            const int grp = (blockIdx.x + k) & 7;
+            for (;;) {
+                if (threadIdx.x == 0) s_j = atomicAdd(&counter[grp], 1);
+                __syncthreads();
+                const int chunk = 8 * __builtin_amdgcn_readfirstlane(s_j) + grp;
+                __syncthreads();
+                if (chunk >= nchunks) break;
+                const int t0 = chunk * kQueueChunk, t1 = min(t0 + kQueueChunk, ntiles);
+                for (int t = t0; t < t1; t++) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t], (int)threadIdx.x);
             }
         }
     } else if constexpr (SCHED == 2) {
-        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t]);
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t], (int)threadIdx.x);
     } else {
         int t = blockIdx.x;
         if constexpr (SCHED == 1) t = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-        if (t < ntiles) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t]);
+        if (t < ntiles) stream_collide_tile<CD, COLL>(src, dst, cases, body, tiles[t], (int)threadIdx.x);
     }
 }
 
@@ -178,6 +201,11 @@ static hipError_t stream_collide_impl(const void *src, void *dst, const DevPtrs 
     case 3:
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, p.counter);
         hipLaunchKernelGGL((k_stream_collide<CD, 3>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
+                           ntiles, p.counter);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, p.counter);
+        hipLaunchKernelGGL((k_stream_collide<CD, 4>), dim3(grid), dim3(block), 0, s, a, b, p.cases, p.body, p.tiles,
                            ntiles, p.counter);
         break;
     default:

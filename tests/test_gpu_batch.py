@@ -52,7 +52,8 @@ def alone(T):
 
 SCHEDULES = [dict(block=256, schedule=0, tile_order=0), dict(block=64, schedule=1, tile_order=1),
              dict(block=128, schedule=2, persist_wgs=7, tile_order=2),
-             dict(block=256, schedule=3, persist_wgs=5, tile_order=1)]
+             dict(block=256, schedule=3, persist_wgs=5, tile_order=1),
+             dict(block=128, schedule=4, persist_wgs=6, tile_order=2)]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
@@ -111,8 +112,8 @@ def test_batched_cases_match_oracle(T, orc):
 def test_schedule_switch_on_a_live_context(T, alone):
     cases, bodies = small_batch()
     S = T.Solver(cases, bodies)
-    for k, sched in enumerate(SCHEDULES * 3):
-        S.set_schedule(**sched)
+    for k in range(12):   # the steps of the runs alone, cycling through every schedule
+        S.set_schedule(**SCHEDULES[k % len(SCHEDULES)])
         S.run(1)
     for c in range(3):
         assert np.array_equal(S.populations(c), alone[c][0])
