@@ -855,6 +855,7 @@ def main():
             gm = r["graph_ms_per_step"]
             variants[sto] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                              "mlups_graph": round(cells / (gm * 1e-3) / 1e6, 1), "graph_ms_per_step": round(gm, 4),
+                             "coupling": "serial" if modes[sto] else "beside",
                              "k1_gbps": round(r["k1_gbps"], 1), "k1_frac": round(r["k1_gbps"] / HBM_PEAK_GBPS, 4),
                              "drag_rel_diff_vs_f32": abs(fz - fz_ref) / abs(fz_ref),
                              "vz_rel_diff_vs_f32": abs(r["v"][2] - ref["v"][2]) / abs(ref["v"][2]),
