@@ -10,8 +10,11 @@
 
 namespace turret {
 
+// Compiled for 8 waves per SIMD (at most 64 VGPRs): it runs beside the
+// lattice kernel, whose waves hold 64 VGPRs each, and only fits the slots
+// they free with the same budget.
 template <class CD, int COLL>
-__global__ void __launch_bounds__(256) k_fine_step(const typename CD::T *__restrict__ src,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_fine_step(const typename CD::T *__restrict__ src,
                                                    typename CD::T *__restrict__ dst, DevPtrs p, int sid, int did)
 {
     const int c = blockIdx.y;

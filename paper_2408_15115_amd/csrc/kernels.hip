@@ -1526,7 +1526,11 @@ static hipError_t ibm_impl(const void *prev, void *cur, const DevPtrs &p, int n_
     // plain start with at most kHBufs cycles: each cycle's spread rides on
     // the pass before it (force + spread 1, update c + spread c + 1)
     static_assert(kHBufs == 4, "the launch below instantiates 1..4 accumulators");
-    constexpr int W = std::is_same<CD, CodecF32>::value ? 8 : 1;   // register budget of the tile passes
+    // register budget of the tile passes: 8 waves per SIMD (they fit the
+    // slots the lattice kernel frees) for the population stores, whose
+    // coupling runs beside that kernel; the occupancy the LDS allows for the
+    // moment store
+    constexpr int W = std::is_same<CD, CodecMom>::value ? 1 : 8;
     const int fused = ibm_fused(warm_mode, cycles);
     hipLaunchKernelGGL(k_interp_force_tiles<W>, tile_grid, blk, kLdsForce, s, p, n_mtiles, fused);
     if (force_surface) hipLaunchKernelGGL(k_offset_force, tile_grid, blk, 0, s, p, n_mtiles);
