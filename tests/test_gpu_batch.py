@@ -165,11 +165,12 @@ def test_step_tuner_times_whole_steps_and_caches(T, tmp_path):
     assert r2["cached"] and r2["best"] == r1["best"]
 
 
-def test_fp16_batch_case_equals_case_alone(T):
+@pytest.mark.parametrize("sched", [dict(schedule=3, persist_wgs=11), dict(schedule=4, persist_wgs=9)])
+def test_fp16_batch_case_equals_case_alone(T, sched):
     """FP16 storage with a full-precision box per body: each case of the
-    batch (persistent work-queue schedule) equals the case run alone."""
+    batch (persistent work-queue schedules) equals the case run alone."""
     cases, bodies = small_batch()
-    S = T.Solver(cases, bodies, storage="f16", schedule=3, persist_wgs=11)
+    S = T.Solver(cases, bodies, storage="f16", **sched)
     S.run(12)
     for c in range(3):
         A = T.Solver([cases[c]], [bodies[c]], storage="f16")
